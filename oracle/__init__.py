@@ -1,0 +1,112 @@
+"""CPU reference ("oracle") of the video kernel chain -- TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the benchmark's CPU-baseline leg
+use this package.  It imports nothing from the GPU library and the GPU library
+never imports it.
+
+* ``chain``: the plain, unfused, frame-by-frame FP64 chain (``oracle.c``),
+  Sec. III composition I_out = K_n(...K_1(I_in)).
+* ``partition``: brute-force enumeration of every contiguous partition of a
+  kernel sequence (Sec. VI, Fig. 5 model).
+* ``mlp``: FP64 forward / backward of the cost-model network.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+OPS = {
+    "rgb2gray": 1, "gauss5": 2, "sobel3": 3, "gradmag": 4, "products": 5,
+    "boxsum5": 6, "harris": 7, "threshold": 8, "nms3": 9, "framediff": 10,
+}
+_IN_CH = {"rgb2gray": 3, "sobel3": 1, "gradmag": 2, "products": 2, "harris": 3}
+_OUT_CH = {"sobel3": 2, "products": 3}
+
+SIGMA = 1.0
+HARRIS_K = 0.04
+THRESHOLD = 1.0e8
+
+
+def build(force: bool = True) -> str:
+    """Compile oracle.c into liboracle.so with gcc (plain -O2, no fast-math)."""
+    if force or not os.path.exists(_LIB_PATH):
+        tmp = _LIB_PATH + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-fno-fast-math", "-ffp-contract=off", "-fPIC", "-shared",
+                               "-std=c99", "-o", tmp, os.path.join(_HERE, "oracle.c"), "-lm", "-lpthread"])
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build()
+        lib = ctypes.CDLL(_LIB_PATH)
+        d = ctypes.POINTER(ctypes.c_double)
+        lib.or_chain.restype = ctypes.c_int
+        lib.or_chain.argtypes = [ctypes.POINTER(ctypes.c_int32), ctypes.c_int32, d, ctypes.c_int32,
+                                 ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, d, ctypes.c_int32,
+                                 ctypes.c_double, ctypes.c_double, ctypes.c_double, d, ctypes.c_int64,
+                                 ctypes.POINTER(ctypes.c_int64), ctypes.c_int32]
+        _lib = lib
+    return _lib
+
+
+def _dp(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def chain_channels(ops, in_ch=None):
+    """(input channels, output channels) of a chain of op names."""
+    ch = _IN_CH.get(ops[0], in_ch if in_ch is not None else 1)
+    first = ch
+    for op in ops:
+        ch = _OUT_CH.get(op, ch if op == "boxsum5" else 1)
+    return first, ch
+
+
+def chain(ops, volume, in_ch=None, sigma=SIGMA, k=HARRIS_K, thr=THRESHOLD,
+          nthreads=None, max_points=1 << 18):
+    """Run the chain ``ops`` (list of names) over ``volume``.
+
+    ``volume`` is [T][H][W] (one channel), [T][H][W][3] (RGB interleaved, for a
+    chain starting with rgb2gray) or [C][T][H][W] planar float for multi-channel
+    float input.  Returns (out [C][T][H][W] float64, points [n][4] float64 rows
+    (t, y, x, response)).
+    """
+    ops = list(ops)
+    v = np.asarray(volume)
+    if ops[0] == "rgb2gray":
+        planes = np.ascontiguousarray(np.moveaxis(v, -1, 0), dtype=np.float64)
+    elif v.ndim == 3:
+        planes = np.ascontiguousarray(v[None], dtype=np.float64)
+    else:
+        planes = np.ascontiguousarray(v, dtype=np.float64)
+    cin, cout = chain_channels(ops, planes.shape[0])
+    if planes.shape[0] != cin:
+        raise ValueError(f"chain {ops} wants {cin} input channels, got {planes.shape[0]}")
+    C, T, H, W = planes.shape
+    out = np.zeros((cout, T, H, W), np.float64)
+    codes = (ctypes.c_int32 * len(ops))(*[OPS[o] for o in ops])
+    cap = int(max_points)
+    pts = np.zeros((max(cap, 1), 4), np.float64)
+    npts = ctypes.c_int64(0)
+    if nthreads is None:
+        nthreads = min(os.cpu_count() or 1, T)
+    rc = _load().or_chain(codes, len(ops), _dp(planes), C, W, H, T, _dp(out), cout,
+                          sigma, k, thr, _dp(pts), cap, ctypes.byref(npts), int(nthreads))
+    if rc != 0:
+        raise RuntimeError(f"oracle chain failed with code {rc}")
+    n = npts.value
+    if n > cap:
+        raise RuntimeError(f"oracle point buffer overflow ({n} > {cap})")
+    return out, pts[:n].copy()
+
