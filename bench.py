@@ -1,0 +1,194 @@
+"""Benchmark of the fused video-kernel chain on one MI355X.
+
+Default workload: 800x600x1000 RGB uint8 video (synthetic, seeded), rgb2gray
+followed by the 8-stage Harris chain (Gaussian 5x5, Sobel, structure products,
+5x5 window sums, Harris response, threshold, 3x3 suppression, frame
+difference), partition chosen by the planner (full fusion).  One step = one
+pass of the whole chain over the whole video, input already resident in HBM.
+
+Prints one JSON line: fused throughput in Mpixel/s (`value`), the unfused
+sequence measured in the same process, the roofline of the dominant kernel
+(timed with HIP events on the stream it is launched on) and the CPU oracle on a
+bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# MI355X figures used for roofline fractions
+HBM_PEAK_GBS = 8000.0
+N_CU, CLOCK_GHZ, LANES_PER_CU = 256, 2.4, 64  # 4 SIMDs x 16 lanes
+VALU_PEAK_GOPS = N_CU * LANES_PER_CU * CLOCK_GHZ  # 39,321.6 G lane-ops/s (non-packed)
+
+WORKLOADS = {
+    "rgb800": dict(W=800, H=600, T=1000, rgb=True, seed=3, chain="rgb_harris",
+                   desc="800x600x1000 RGB u8, rgb2gray + 8-stage Harris chain"),
+    "harris192": dict(W=192, H=432, T=600, rgb=False, seed=2, chain="harris",
+                      desc="192x432x600 gray u8, 8-stage Harris chain"),
+    "grad192": dict(W=192, H=432, T=64, rgb=False, seed=1, chain="grad",
+                    desc="192x432x64 gray u8, Gaussian -> Sobel -> magnitude"),
+}
+METRIC = "Mpixel/s fused vs unfused and HBM GB/s (% of peak), 800×600×1000 chain"
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def chain_ops(name):
+    from paper_1509_04394_amd import fz
+    return {"rgb_harris": fz.RGB_HARRIS_CHAIN, "harris": fz.HARRIS_CHAIN, "grad": fz.GRAD_CHAIN}[name]
+
+
+def ops_per_px(ops):
+    """Algorithmic VALU operations per output pixel (separable forms, no recompute)."""
+    table = {"rgb2gray": 9, "gauss5": 11, "sobel3": 10, "gradmag": 3, "products": 3, "boxsum5": 24,
+             "harris": 5, "threshold": 2, "nms3": 7, "framediff": 2}
+    return sum(table[o] for o in ops)
+
+
+def time_plan(plan, x, bufs, steps, warmup, stream):
+    """Mean ms per run over `steps` runs after `warmup`, with HIP events on `stream`."""
+    import torch
+    out, pts, cnt, ws = bufs
+    for _ in range(warmup):
+        plan.run(x, out, pts, cnt, ws, stream=stream.cuda_stream)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    per = []
+    for _ in range(steps):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        plan.run(x, out, pts, cnt, ws, stream=stream.cuda_stream)
+        b.record(stream)
+        per.append((a, b))
+    ev0.record(stream)
+    torch.cuda.synchronize()
+    times = [a.elapsed_time(b) for a, b in per]
+    del ev0, ev1
+    return float(np.mean(times)), float(np.median(times)), times
+
+
+def cpu_baseline(wl, ops, budget_s=15.0):
+    """The oracle (FP64, unfused) on a bounded sample of the same workload."""
+    import oracle
+    from paper_1509_04394_amd import synth
+    oracle.build(force=False)
+    cores = os.cpu_count() or 1
+    W, H = wl["W"], wl["H"]
+    n = 8
+    vol = synth.video(W, H, n, seed=wl["seed"], rgb=wl["rgb"])
+    t = time.perf_counter()
+    oracle.chain(ops, vol, nthreads=cores)
+    dt = time.perf_counter() - t
+    # grow the sample to about budget_s of work
+    frames = int(min(wl["T"], max(n, n * budget_s / max(dt, 1e-3))))
+    frames = max(cores, frames - frames % cores) if frames >= cores else frames
+    vol = synth.video(W, H, frames, seed=wl["seed"], rgb=wl["rgb"])
+    t = time.perf_counter()
+    oracle.chain(ops, vol, nthreads=min(cores, frames))
+    dt = time.perf_counter() - t
+    px = W * H * frames
+    return {"value": px / dt / 1e6, "unit": "Mpixel/s", "cores": min(cores, frames), "kind": "oracle",
+            "sample": f"frames 0-{frames - 1} of the {W}x{H}x{wl['T']} workload ({px / 1e6:.1f} Mpx), "
+                      f"whole chain unfused in FP64, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="rgb800", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-unfused", action="store_true", help="skip timing the unfused sequence")
+    ap.add_argument("--fused-only", action="store_true", help="time only the fused plan (for profiling)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py: this build runs on one GPU only; multi-GPU runs are not supported "
+              "(the temporal sharding that would split the video is described in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1509_04394_amd import fz, synth
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    fz.lib()  # fail loudly if the HIP library is missing
+    wl = WORKLOADS[args.workload]
+    ops = chain_ops(wl["chain"])
+    W, H, T = wl["W"], wl["H"], wl["T"]
+    npx = W * H * T
+    dev = torch.device("cuda:0")
+    log(f"generating {wl['desc']}")
+    t = time.perf_counter()
+    vol = synth.video(W, H, T, seed=wl["seed"], rgb=wl["rgb"])
+    log(f"generated in {time.perf_counter() - t:.1f} s")
+    x = torch.from_numpy(vol).to(dev)
+    del vol
+    stream = torch.cuda.current_stream(dev)
+
+    fused = fz.Plan(ops, W, H, T)
+    info = fused.segment_info()
+    fb = fused.alloc(dev)
+    log("fused plan groups", fused.segments, "tiles", [(s.tile_w, s.tile_h, s.frames_per_block) for s in info])
+    f_mean, f_med, _ = time_plan(fused, x, fb, args.steps, args.warmup, stream)
+    nfused = int(fb[2].item()) if fb[2] is not None else 0
+    log(f"fused: {f_mean:.3f} ms/step mean, {f_med:.3f} median, {nfused} points")
+
+    unf = None
+    if not (args.no_unfused or args.fused_only):
+        del fb
+        torch.cuda.empty_cache()
+        uplan = fz.Plan(ops, W, H, T, partition="unfused")
+        ub = uplan.alloc(dev)
+        u_mean, u_med, _ = time_plan(uplan, x, ub, max(3, args.steps // 2), 1, stream)
+        log(f"unfused: {u_mean:.3f} ms/step mean, {u_med:.3f} median")
+        unf = {"mpx_s": npx / (u_mean * 1e-3) / 1e6, "ms_per_step": u_mean,
+               "algorithmic_GBs": uplan.cost / (u_mean * 1e-3) / 1e9,
+               "hbm_frac": uplan.cost / (u_mean * 1e-3) / 1e9 / HBM_PEAK_GBS,
+               "kernels": len(uplan.segments)}
+        del ub
+        torch.cuda.empty_cache()
+
+    value = npx / (f_mean * 1e-3) / 1e6
+    alg_bytes = fused.cost  # compulsory bytes of the planned groups
+    dominant = info[0] if len(info) == 1 else max(info, key=lambda s: s.cost)
+    opx = ops_per_px(ops[dominant.first:dominant.last + 1])
+    achieved_gops = npx * opx / (f_mean * 1e-3) / 1e9
+    achieved_gbs = alg_bytes / (f_mean * 1e-3) / 1e9
+    roof = {"bound": "alu", "achieved": round(achieved_gops, 1), "peak": VALU_PEAK_GOPS, "unit": "Gop/s",
+            "frac": round(achieved_gops / VALU_PEAK_GOPS, 4), "traffic": None,
+            "ops_per_px": opx, "hbm_achieved_GBs": round(achieved_gbs, 1),
+            "hbm_frac": round(achieved_gbs / HBM_PEAK_GBS, 4)}
+    rec = {"metric": METRIC, "value": round(value, 1), "unit": "Mpixel/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": round(f_mean, 4), "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": wl["desc"], "partition": fused.segments,
+                      "tile": [dominant.tile_w, dominant.tile_h, dominant.frames_per_block],
+                      "points_per_step": nfused},
+           "roofline": roof}
+    if unf is not None:
+        rec["unfused"] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in unf.items()}
+        rec["speedup_vs_unfused"] = round(u_mean / f_mean, 3)
+        rec["paper_context"] = "2-3x fused over sequential kernels on Tesla C1060 / K20 / GTX 750 Ti (Abstract)"
+    if not (args.no_cpu or args.fused_only):
+        log("timing the CPU oracle on a sample")
+        rec["cpu_baseline"] = cpu_baseline(wl, ops)
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

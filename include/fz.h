@@ -1,0 +1,182 @@
+/*
+ * fz -- fused video-kernel chains on MI355X (gfx950).
+ *
+ * C ABI of the library.  It implements the method of "Efficient Kernel Fusion
+ * Techniques for Massive Video Data Analysis on GPGPUs" (Adnan, Radhakrishnan,
+ * Karabuk): a sequence of image kernels K_1..K_n applied in order to a video
+ * volume N x M x T (Sec. III) is split into contiguous groups, each group run as
+ * one fused kernel that loads its input box once, keeps every intermediate
+ * on chip and stores only its last output (Sec. V-B, Eq. 2; Sec. VI-B,
+ * Algorithm 1).  The split is the one with the least predicted cost under the
+ * on-chip memory budget (Sec. VI-A, Fig. 5).
+ *
+ * Conventions for every call:
+ *   - All device pointers are caller-owned device memory (hipMalloc'd or a
+ *     PyTorch CUDA tensor's data_ptr()); the library never frees them and
+ *     allocates no device memory on the run path.
+ *   - Host pointers are read during the call only, unless stated.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *     Runs are asynchronous on that stream; all argument checks happen on the
+ *     host before the first launch, so an error return means nothing was
+ *     launched.
+ *   - Errors are reported by the return code; fz_last_error() gives a
+ *     human-readable message for the calling thread's last failed call.
+ *
+ * Video layouts (frame-major, row-major, x along the width):
+ *   u8 gray / mask:      [T][H][W]
+ *   u8 RGB:              [T][H][W][3] interleaved
+ *   f32, c channels:     [c][T][H][W] planar
+ */
+#ifndef FZ_H
+#define FZ_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t fz_status;
+enum {
+    FZ_OK = 0,
+    FZ_E_INVALID = 1,     /* null pointer, bad size, malformed or unsupported chain */
+    FZ_E_LDS = 2,         /* some stage cannot fit the on-chip (LDS) budget even alone */
+    FZ_E_HIP = 3,         /* a HIP launch or query failed; see fz_last_error() */
+    FZ_E_WORKSPACE = 4,   /* workspace smaller than fz_workspace_bytes() */
+    FZ_E_UNSUPPORTED = 5  /* valid request this build does not implement */
+};
+
+/* Image operations.  Table II of the paper classifies the operations of its
+ * tracking pipeline as point, rectangular and multi-frame operations (Table I
+ * gives the classes by the extent of the input window); the Harris-corner
+ * chain below is built from the same classes. */
+enum {
+    FZ_OP_RGB2GRAY = 1,   /* point op: u8 RGB -> u8 gray, floor((299R+587G+114B+500)/1000) */
+    FZ_OP_GAUSS5 = 2,     /* rectangular, radius 2: u8 -> f32, sampled Gaussian, param[0] = sigma */
+    FZ_OP_SOBEL3 = 3,     /* rectangular, radius 1: f32 -> 2 x f32 (Ix, Iy), unnormalised */
+    FZ_OP_GRADMAG = 4,    /* point op: 2 x f32 -> f32, sqrt(Ix^2 + Iy^2) */
+    FZ_OP_PRODUCTS = 5,   /* point op: 2 x f32 -> 3 x f32 (Ix^2, Ix*Iy, Iy^2) */
+    FZ_OP_BOXSUM5 = 6,    /* rectangular, radius 2: 3 x f32 -> 3 x f32, 5x5 window sums */
+    FZ_OP_HARRIS = 7,     /* point op: 3 x f32 -> f32, Sxx*Syy - Sxy^2 - k (Sxx+Syy)^2, param[0] = k */
+    FZ_OP_THRESHOLD = 8,  /* point op: f32 -> f32, v >= param[0] ? v : 0 */
+    FZ_OP_NMS3 = 9,       /* rectangular, radius 1: f32 -> u8 mask (255 = feature) + feature points */
+    FZ_OP_FRAMEDIFF = 10  /* multi-frame point op, 1 frame back: u8 -> u8, |m[t] - m[t-1]| (m[-1] = m[0]) */
+};
+
+enum { FZ_U8 = 1, FZ_F32 = 2 };
+
+/* Dependence of a stage on its predecessor (Sec. V-A): thread-to-thread (the
+ * same pixel), thread-to-multi-thread (a window of pixels of the same block),
+ * kernel-to-kernel (pixels of other blocks: never fused with its predecessor). */
+enum { FZ_DEP_TT = 0, FZ_DEP_TMT = 1, FZ_DEP_KK = 2 };
+
+/* Access pattern and parameters of one stage (Sec. IV: an output pixel reads a
+ * (2rx+1) x (2ry+1) window of its input over rt+1 frames).  Fill it with
+ * fz_stage_describe() and change param[] as needed; the planner rejects a
+ * descriptor whose pattern disagrees with the operation. */
+typedef struct fz_stage {
+    int32_t op;
+    int32_t rx, ry, rt;
+    int32_t in_ch, out_ch;
+    int32_t in_dtype, out_dtype;
+    int32_t dep;
+    float param[4];
+} fz_stage;
+
+/* Feature point emitted by FZ_OP_NMS3 (frame, row, column, corner response). */
+typedef struct fz_point {
+    uint32_t t, y, x;
+    float response;
+} fz_point;
+
+enum { FZ_PART_OPTIMAL = 0, FZ_PART_UNFUSED = 1, FZ_PART_EXPLICIT = 2 };
+enum { FZ_COST_ANALYTIC = 0, FZ_COST_LEARNED = 1, FZ_COST_MEASURED = 2 };
+
+typedef struct fz_plan_opts {
+    int32_t width, height, frames;  /* video size the plan is made for (> 0) */
+    int32_t lds_budget_bytes;       /* on-chip budget per fused kernel; 0 = 163840 (160 KB per CU) */
+    int32_t partition;              /* FZ_PART_*: optimal (planner), one kernel per stage, or explicit */
+    int32_t n_cuts;                 /* FZ_PART_EXPLICIT: number of entries in cuts */
+    const int32_t* cuts;            /* FZ_PART_EXPLICIT: last stage index of every group but the final,
+                                       strictly increasing, each in [0, n-2] */
+    int32_t cost_model;             /* FZ_COST_*; only FZ_COST_ANALYTIC is implemented */
+    int32_t tile_w, tile_h;         /* output box of one workgroup; 0 = planner's choice */
+    int32_t frames_per_block;       /* frames one workgroup marches through; 0 = planner's choice */
+} fz_plan_opts;
+
+typedef struct fz_plan fz_plan;  /* opaque, host memory */
+
+/* Per-group description of a plan. */
+typedef struct fz_segment_info {
+    int32_t first, last;            /* stage indices covered by this fused kernel */
+    int32_t tile_w, tile_h;         /* output box x, y (Sec. V, Fig. 3) */
+    int32_t frames_per_block;       /* output box t */
+    int32_t halo, halo_t;           /* input-box growth per side in x/y, and in frames (Sec. VI-C) */
+    int32_t lds_bytes;              /* on-chip memory of one workgroup */
+    int32_t streaming;              /* 1 = no window stage: one pass, no on-chip staging */
+    double bytes_per_px;            /* compulsory global-memory bytes per output pixel */
+    double cost;                    /* the planner's cost of this group */
+} fz_segment_info;
+
+/* Fill `out` with the access pattern and default parameters of `op`
+ * (sigma 1, k 0.04, threshold 1e8).  FZ_E_INVALID for an unknown op. */
+fz_status fz_stage_describe(int32_t op, fz_stage* out);
+
+/* Plan a chain (Sec. VI-A): validate the n stage descriptors (host array),
+ * split them into fusable sets at kernel-to-kernel dependences, price every
+ * contiguous group, and pick the partition of least total cost (ties: fewer
+ * groups, then later cuts).  The analytic cost of a group is its compulsory
+ * global-memory traffic (Eq. 2 applied per group; Sec. VI-D); a group whose
+ * smallest tile does not fit `lds_budget_bytes` is not allowed.  On success
+ * *out owns a new plan the caller frees with fz_plan_destroy().  The chain must
+ * be a contiguous part of  rgb2gray, gauss5, sobel3, products, boxsum5,
+ * harris, threshold, nms3, framediff  or of  gauss5, sobel3, gradmag. */
+fz_status fz_plan_chain(const fz_stage* stages, int32_t n, const fz_plan_opts* opts, fz_plan** out);
+
+void fz_plan_destroy(fz_plan* plan);
+
+int32_t fz_plan_num_segments(const fz_plan* plan);
+/* Copy the last stage index of each group into seg_last[0..cap). */
+fz_status fz_plan_segments(const fz_plan* plan, int32_t* seg_last, int32_t cap);
+fz_status fz_plan_segment_info(const fz_plan* plan, int32_t i, fz_segment_info* out);
+/* Planner objective of the chosen partition (bytes for the analytic model). */
+double fz_plan_cost(const fz_plan* plan);
+/* The planner's price of the group a..b (inclusive); +inf if not allowed. */
+fz_status fz_plan_group_cost(const fz_plan* plan, int32_t a, int32_t b, double* cost);
+
+/* Solve the partition model of Fig. 5 for an arbitrary price table: cost is an
+ * n x n row-major host array, cost[a*n+b] = price of fusing a..b (a <= b;
+ * +inf = not allowed; entries below the diagonal are ignored).  Writes the
+ * last stage of each group to seg_last (capacity n), their number to *n_seg
+ * and the optimum to *total (+inf if nothing is feasible).  Exact: the
+ * contiguous-group model is a shortest path over cut positions.  n in [1, 64]. */
+fz_status fz_partition_min(const double* cost, int32_t n, int32_t* seg_last, int32_t* n_seg, double* total);
+
+/* Device workspace the run needs for intermediates between groups. */
+size_t fz_workspace_bytes(const fz_plan* plan);
+
+/* Run the planned chain on the device (Sec. VI-B, Algorithm 1 per group):
+ *   d_in:   input video in the layout of the first stage's input type
+ *   d_out:  output video in the layout of the last stage's output type
+ *   d_points, d_point_count, point_capacity: feature points of FZ_OP_NMS3
+ *           (may be NULL/0 if the chain has no nms3 stage).  *d_point_count is
+ *           reset by the run and counts every point, also past the capacity;
+ *           read it after the stream has synchronised and compare.  Point order
+ *           is unspecified.
+ *   d_workspace, ws_bytes: at least fz_workspace_bytes(plan) bytes.
+ * The output equals that of the plain sequence whatever the partition. */
+fz_status fz_run_chain(const fz_plan* plan, const void* d_in, void* d_out, fz_point* d_points,
+                       uint32_t* d_point_count, uint32_t point_capacity, void* d_workspace,
+                       size_t ws_bytes, void* stream);
+
+/* Message for the calling thread's last failed call ("" if none). */
+const char* fz_last_error(void);
+
+/* Library version string. */
+const char* fz_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FZ_H */

@@ -1,0 +1,65 @@
+// Internal host-side declarations of the fz library.
+#pragma once
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/fz.h"
+#include "fz_ops.h"
+
+namespace fz {
+
+struct Segment {
+    int first, last;        // stage indices of the user chain
+    int cfirst, clast;      // the same in the compiled chain
+    int tile;               // tile index (window groups), -1 for streaming groups
+    int tile_w, tile_h;
+    int tpb;                // frames per workgroup
+    int halo, halo_t;
+    int lds_bytes;
+    int streaming;
+    double bytes_per_px;
+    double cost;
+};
+
+struct Params {
+    float sigma = 1.0f, k = 0.04f, thr = 1.0e8f;
+    float gw[3] = {0, 0, 0};  // Gaussian weights w0, w1, w2 (FP32)
+};
+
+}  // namespace fz
+
+struct fz_plan {
+    std::vector<fz_stage> stages;
+    int n = 0;
+    int chain = 0, offset = 0;
+    int W = 0, H = 0, T = 0;
+    int lds_budget = 0;
+    std::vector<double> cost;  // n x n, +inf where not allowed
+    std::vector<fz::Segment> segs;
+    double total = 0.0;
+    fz::Params prm;
+    bool has_nms = false;
+};
+
+namespace fz {
+
+// thread-local error message
+void set_error(const std::string& msg);
+fz_status fail(fz_status code, const std::string& msg);
+
+// Price of group [a..b] of plan p, with its tile / frames-per-block choice.
+Segment price_group(const fz_plan& p, int a, int b, int tile_req_w, int tile_req_h, int tpb_req);
+
+// Exact partition DP (Fig. 5 model) with the tie rule: fewer groups, then later cuts.
+double partition_dp(const double* cost, int n, std::vector<int>& seg_last);
+
+// Device side (run.hip)
+fz_status run_plan(const fz_plan& p, const void* d_in, void* d_out, fz_point* d_points, uint32_t* d_count,
+                   uint32_t cap, void* d_ws, size_t ws_bytes, void* stream);
+size_t workspace_bytes(const fz_plan& p);
+
+}  // namespace fz

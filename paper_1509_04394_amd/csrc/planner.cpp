@@ -1,0 +1,364 @@
+// Host planner and C-ABI entry points that do not touch the device.
+//
+// Sec. VI-A: kernels with only thread-to-thread or thread-to-multi-thread
+// dependences form fusable sets; within a set every contiguous group of
+// kernels is a candidate fused kernel (n(n+1)/2 of them, Fig. 5) and the
+// partition of least total cost is chosen.  Because the candidates are the
+// contiguous runs of a sequence, an exact cover by chosen candidates is a path
+// through the cut positions 0..n, and the minimum is a shortest path solved by
+// dynamic programming over the last cut, with no integer-programming solver.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <limits>
+#include <string>
+#include <vector>
+
+#include "fz_internal.h"
+
+namespace fz {
+
+static thread_local std::string g_err;
+
+void set_error(const std::string& msg) { g_err = msg; }
+
+fz_status fail(fz_status code, const std::string& msg)
+{
+    g_err = msg;
+    return code;
+}
+
+static const double kInf = std::numeric_limits<double>::infinity();
+
+static int op_bytes_in(int op)
+{
+    const OpInfo o = op_info(op);
+    return o.in_ch * dt_bytes(o.in_dt);
+}
+static int op_bytes_out(int op)
+{
+    const OpInfo o = op_info(op);
+    return o.out_ch * dt_bytes(o.out_dt);
+}
+
+// Data utilisation of an output box x*y*t with growth 2H per axis and Ht
+// frames (Eq. 3).
+static double data_utilisation(int x, int y, int t, int H, int Ht)
+{
+    return (double)x * y * t / ((double)(x + 2 * H) * (y + 2 * H) * (t + Ht));
+}
+
+Segment price_group(const fz_plan& p, int a, int b, int req_w, int req_h, int req_tpb)
+{
+    Segment s{};
+    s.first = a;
+    s.last = b;
+    s.cfirst = p.offset + a;
+    s.clast = p.offset + b;
+    s.cost = kInf;
+    s.tile = -1;
+    for (int j = a + 1; j <= b; ++j)
+        if (p.stages[j].dep == FZ_DEP_KK) return s;  // kernel-to-kernel: never fused (Sec. VI-A)
+    const int ch = p.chain, A = s.cfirst, B = s.clast;
+    s.halo = group_halo(ch, A, B);
+    s.halo_t = group_halo_t(ch, A, B);
+    s.streaming = group_has_window(ch, A, B) ? 0 : 1;
+    s.tpb = req_tpb > 0 ? req_tpb : (s.halo_t > 0 ? 8 : 1);
+    if (s.tpb > p.T) s.tpb = p.T;
+    if (s.streaming) {
+        s.lds_bytes = 0;
+        s.tile_w = s.tile_h = 0;
+    } else {
+        double best_du = -1.0;
+        for (int t = 0; t < N_TILES; ++t) {
+            const int tw = tile_w(t), th = tile_h(t);
+            if (req_w > 0 && (tw != req_w || th != req_h)) continue;
+            const int lds = engine_lds_bytes(ch, A, B, tw, th);
+            if (lds > p.lds_budget) continue;
+            const double du = data_utilisation(tw, th, s.tpb, s.halo, s.halo_t);
+            if (du > best_du) {
+                best_du = du;
+                s.tile = t;
+                s.tile_w = tw;
+                s.tile_h = th;
+                s.lds_bytes = lds;
+            }
+        }
+        if (s.tile < 0) return s;  // no compiled tile fits the on-chip budget
+    }
+    // Compulsory traffic (Eq. 2 per group): the group's input once, its output
+    // once; a multi-frame group re-reads its temporal halo once per frame run.
+    const double bin = op_bytes_in(p.stages[a].op), bout = op_bytes_out(p.stages[b].op);
+    const double temporal = s.halo_t > 0 ? bin * s.halo_t / (s.streaming ? 1.0 : (double)s.tpb) : 0.0;
+    s.bytes_per_px = bin + bout + temporal;
+    s.cost = s.bytes_per_px * (double)p.W * p.H * p.T;
+    return s;
+}
+
+double partition_dp(const double* cost, int n, std::vector<int>& seg_last)
+{
+    // best[e]: optimum over stages 0..e-1; key (cost, groups, cut list)
+    std::vector<double> best(n + 1, kInf);
+    std::vector<int> groups(n + 1, 0);
+    std::vector<std::vector<int>> cuts(n + 1);
+    best[0] = 0.0;
+    for (int e = 1; e <= n; ++e) {
+        for (int a = 0; a < e; ++a) {  // last group a..e-1
+            const double c = cost[(size_t)a * n + (e - 1)];
+            if (!(best[a] < kInf) || !(c < kInf)) continue;
+            const double tot = best[a] + c;
+            const int g = groups[a] + 1;
+            std::vector<int> cl = cuts[a];
+            if (a > 0) cl.push_back(a - 1);
+            bool better;
+            if (!(best[e] < kInf)) better = true;
+            else if (tot != best[e]) better = tot < best[e];
+            else if (g != groups[e]) better = g < groups[e];
+            else better = cl > cuts[e];  // later cuts win
+            if (better) {
+                best[e] = tot;
+                groups[e] = g;
+                cuts[e] = cl;
+            }
+        }
+    }
+    seg_last.clear();
+    if (!(best[n] < kInf)) return kInf;
+    seg_last = cuts[n];
+    seg_last.push_back(n - 1);
+    return best[n];
+}
+
+}  // namespace fz
+
+using namespace fz;
+
+extern "C" {
+
+const char* fz_last_error(void) { return g_err.c_str(); }
+
+const char* fz_version(void) { return "fz 0.1 gfx950"; }
+
+fz_status fz_stage_describe(int32_t op, fz_stage* out)
+{
+    if (!out) return fail(FZ_E_INVALID, "fz_stage_describe: null output");
+    const OpInfo o = op_info(op);
+    if (o.op == 0) return fail(FZ_E_INVALID, "fz_stage_describe: unknown op " + std::to_string(op));
+    memset(out, 0, sizeof(*out));
+    out->op = op;
+    out->rx = out->ry = o.r;
+    out->rt = o.rt;
+    out->in_ch = o.in_ch;
+    out->out_ch = o.out_ch;
+    out->in_dtype = o.in_dt;
+    out->out_dtype = o.out_dt;
+    out->dep = o.dep;
+    if (op == FZ_OP_GAUSS5) out->param[0] = 1.0f;
+    if (op == FZ_OP_HARRIS) out->param[0] = 0.04f;
+    if (op == FZ_OP_THRESHOLD) out->param[0] = 1.0e8f;
+    return FZ_OK;
+}
+
+fz_status fz_partition_min(const double* cost, int32_t n, int32_t* seg_last, int32_t* n_seg, double* total)
+{
+    if (!cost || !seg_last || !n_seg || !total) return fail(FZ_E_INVALID, "fz_partition_min: null pointer");
+    if (n < 1 || n > 64) return fail(FZ_E_INVALID, "fz_partition_min: n must be in [1, 64]");
+    std::vector<int> sl;
+    *total = partition_dp(cost, n, sl);
+    *n_seg = (int32_t)sl.size();
+    for (size_t i = 0; i < sl.size(); ++i) seg_last[i] = sl[i];
+    return FZ_OK;
+}
+
+fz_status fz_plan_chain(const fz_stage* stages, int32_t n, const fz_plan_opts* opts, fz_plan** out)
+{
+    if (!stages || !opts || !out) return fail(FZ_E_INVALID, "fz_plan_chain: null pointer");
+    *out = nullptr;
+    if (n <= 0 || n > 16) return fail(FZ_E_INVALID, "fz_plan_chain: n must be in [1, 16]");
+    if (opts->width <= 0 || opts->height <= 0 || opts->frames <= 0)
+        return fail(FZ_E_INVALID, "fz_plan_chain: width, height and frames must be positive");
+    if ((int64_t)opts->width * opts->height > (int64_t)1 << 28)
+        return fail(FZ_E_INVALID, "fz_plan_chain: frame larger than 2^28 pixels");
+    if (opts->cost_model != FZ_COST_ANALYTIC)
+        return fail(FZ_E_UNSUPPORTED, "fz_plan_chain: only the analytic cost model is available here");
+    if (opts->frames_per_block < 0) return fail(FZ_E_INVALID, "fz_plan_chain: negative frames_per_block");
+    if ((opts->tile_w > 0) != (opts->tile_h > 0))
+        return fail(FZ_E_INVALID, "fz_plan_chain: give both tile_w and tile_h or neither");
+
+    // validate the descriptors against the operation registry (Sec. IV access patterns)
+    for (int i = 0; i < n; ++i) {
+        const fz_stage& s = stages[i];
+        const OpInfo o = op_info(s.op);
+        if (o.op == 0) return fail(FZ_E_INVALID, "stage " + std::to_string(i) + ": unknown op");
+        if (s.rx != o.r || s.ry != o.r || s.rt != o.rt || s.in_ch != o.in_ch || s.out_ch != o.out_ch ||
+            s.in_dtype != o.in_dt || s.out_dtype != o.out_dt)
+            return fail(FZ_E_INVALID, "stage " + std::to_string(i) + ": access pattern does not match its op");
+        if (s.dep < FZ_DEP_TT || s.dep > FZ_DEP_KK)
+            return fail(FZ_E_INVALID, "stage " + std::to_string(i) + ": bad dependence type");
+        if (i > 0 && (stages[i - 1].out_ch != s.in_ch || stages[i - 1].out_dtype != s.in_dtype))
+            return fail(FZ_E_INVALID, "stage " + std::to_string(i) + ": input does not match the previous output");
+    }
+    // locate the chain among the compiled sequences
+    int chain = -1, offset = -1;
+    for (int c = 0; c < N_CHAINS && chain < 0; ++c)
+        for (int o = 0; o + n <= chain_len(c); ++o) {
+            bool ok = true;
+            for (int i = 0; i < n && ok; ++i) ok = chain_op(c, o + i) == stages[i].op;
+            if (ok) {
+                chain = c;
+                offset = o;
+                break;
+            }
+        }
+    if (chain < 0) return fail(FZ_E_UNSUPPORTED, "fz_plan_chain: stage sequence is not one the kernels are built for");
+
+    fz_plan* p = new fz_plan();
+    p->stages.assign(stages, stages + n);
+    p->n = n;
+    p->chain = chain;
+    p->offset = offset;
+    p->W = opts->width;
+    p->H = opts->height;
+    p->T = opts->frames;
+    p->lds_budget = opts->lds_budget_bytes > 0 ? opts->lds_budget_bytes : 163840;
+    for (int i = 0; i < n; ++i) {
+        const fz_stage& s = stages[i];
+        if (s.op == FZ_OP_GAUSS5) {
+            if (!(s.param[0] > 0.0f)) {
+                delete p;
+                return fail(FZ_E_INVALID, "gauss5: sigma must be positive");
+            }
+            p->prm.sigma = s.param[0];
+        }
+        if (s.op == FZ_OP_HARRIS) p->prm.k = s.param[0];
+        if (s.op == FZ_OP_THRESHOLD) p->prm.thr = s.param[0];
+        if (s.op == FZ_OP_NMS3) p->has_nms = true;
+    }
+    {
+        // sampled Gaussian weights, normalised in double, rounded once to FP32
+        double w[3], sum = 0.0;
+        const double sg = p->prm.sigma;
+        for (int i = 0; i < 3; ++i) w[i] = exp(-(double)(i * i) / (2.0 * sg * sg));
+        sum = w[0] + 2.0 * w[1] + 2.0 * w[2];
+        for (int i = 0; i < 3; ++i) p->prm.gw[i] = (float)(w[i] / sum);
+    }
+    // a stage that cannot run even alone makes the chain infeasible
+    for (int i = 0; i < n; ++i) {
+        Segment s = price_group(*p, i, i, opts->tile_w, opts->tile_h, opts->frames_per_block);
+        if (!(s.cost < kInf)) {
+            delete p;
+            if (opts->tile_w > 0)
+                return fail(FZ_E_UNSUPPORTED, "requested tile is not compiled or does not fit the budget");
+            return fail(FZ_E_LDS, "stage " + std::to_string(i) + " does not fit the on-chip budget");
+        }
+    }
+    p->cost.assign((size_t)n * n, kInf);
+    std::vector<std::vector<Segment>> segtab(n, std::vector<Segment>(n));
+    for (int a = 0; a < n; ++a)
+        for (int b = a; b < n; ++b) {
+            segtab[a][b] = price_group(*p, a, b, opts->tile_w, opts->tile_h, opts->frames_per_block);
+            p->cost[(size_t)a * n + b] = segtab[a][b].cost;
+        }
+    std::vector<int> seg_last;
+    if (opts->partition == FZ_PART_OPTIMAL) {
+        p->total = partition_dp(p->cost.data(), n, seg_last);
+    } else if (opts->partition == FZ_PART_UNFUSED) {
+        for (int i = 0; i < n; ++i) seg_last.push_back(i);
+    } else if (opts->partition == FZ_PART_EXPLICIT) {
+        if (opts->n_cuts < 0 || opts->n_cuts > n - 1 || (opts->n_cuts > 0 && !opts->cuts)) {
+            delete p;
+            return fail(FZ_E_INVALID, "explicit partition: bad cut list");
+        }
+        int prev = -1;
+        for (int i = 0; i < opts->n_cuts; ++i) {
+            const int c = opts->cuts[i];
+            if (c <= prev || c > n - 2) {
+                delete p;
+                return fail(FZ_E_INVALID, "explicit partition: cuts must increase strictly within [0, n-2]");
+            }
+            seg_last.push_back(c);
+            prev = c;
+        }
+        seg_last.push_back(n - 1);
+    } else {
+        delete p;
+        return fail(FZ_E_INVALID, "unknown partition mode");
+    }
+    if (seg_last.empty()) {
+        delete p;
+        return fail(FZ_E_LDS, "no partition of the chain fits the on-chip budget");
+    }
+    double total = 0.0;
+    int a = 0;
+    for (int last : seg_last) {
+        const Segment& s = segtab[a][last];
+        if (!(s.cost < kInf)) {
+            delete p;
+            return fail(FZ_E_LDS, "group " + std::to_string(a) + ".." + std::to_string(last) +
+                                      " is not allowed (kernel-to-kernel dependence or on-chip budget)");
+        }
+        p->segs.push_back(s);
+        total += s.cost;
+        a = last + 1;
+    }
+    p->total = total;
+    *out = p;
+    return FZ_OK;
+}
+
+void fz_plan_destroy(fz_plan* plan) { delete plan; }
+
+int32_t fz_plan_num_segments(const fz_plan* plan) { return plan ? (int32_t)plan->segs.size() : -1; }
+
+fz_status fz_plan_segments(const fz_plan* plan, int32_t* seg_last, int32_t cap)
+{
+    if (!plan || !seg_last) return fail(FZ_E_INVALID, "fz_plan_segments: null pointer");
+    if (cap < (int32_t)plan->segs.size()) return fail(FZ_E_INVALID, "fz_plan_segments: capacity too small");
+    for (size_t i = 0; i < plan->segs.size(); ++i) seg_last[i] = plan->segs[i].last;
+    return FZ_OK;
+}
+
+fz_status fz_plan_segment_info(const fz_plan* plan, int32_t i, fz_segment_info* out)
+{
+    if (!plan || !out) return fail(FZ_E_INVALID, "fz_plan_segment_info: null pointer");
+    if (i < 0 || i >= (int32_t)plan->segs.size()) return fail(FZ_E_INVALID, "fz_plan_segment_info: bad index");
+    const Segment& s = plan->segs[i];
+    out->first = s.first;
+    out->last = s.last;
+    out->tile_w = s.tile_w;
+    out->tile_h = s.tile_h;
+    out->frames_per_block = s.tpb;
+    out->halo = s.halo;
+    out->halo_t = s.halo_t;
+    out->lds_bytes = s.lds_bytes;
+    out->streaming = s.streaming;
+    out->bytes_per_px = s.bytes_per_px;
+    out->cost = s.cost;
+    return FZ_OK;
+}
+
+double fz_plan_cost(const fz_plan* plan) { return plan ? plan->total : kInf; }
+
+fz_status fz_plan_group_cost(const fz_plan* plan, int32_t a, int32_t b, double* cost)
+{
+    if (!plan || !cost) return fail(FZ_E_INVALID, "fz_plan_group_cost: null pointer");
+    if (a < 0 || b < a || b >= plan->n) return fail(FZ_E_INVALID, "fz_plan_group_cost: bad range");
+    *cost = plan->cost[(size_t)a * plan->n + b];
+    return FZ_OK;
+}
+
+size_t fz_workspace_bytes(const fz_plan* plan) { return plan ? workspace_bytes(*plan) : 0; }
+
+fz_status fz_run_chain(const fz_plan* plan, const void* d_in, void* d_out, fz_point* d_points, uint32_t* d_point_count,
+                       uint32_t point_capacity, void* d_workspace, size_t ws_bytes, void* stream)
+{
+    if (!plan || !d_in || !d_out) return fail(FZ_E_INVALID, "fz_run_chain: null plan or buffer");
+    if (point_capacity > 0 && !d_points) return fail(FZ_E_INVALID, "fz_run_chain: capacity without a point buffer");
+    const size_t need = workspace_bytes(*plan);
+    if (need > 0 && (!d_workspace || ws_bytes < need))
+        return fail(FZ_E_WORKSPACE, "fz_run_chain: workspace needs " + std::to_string(need) + " bytes");
+    return run_plan(*plan, d_in, d_out, d_points, d_point_count, point_capacity, d_workspace, ws_bytes, stream);
+}
+
+}  // extern "C"

@@ -1,0 +1,82 @@
+// Per-pixel arithmetic of every stage, in one fixed operation order.
+//
+// Every kernel variant (one kernel per stage, any fused group, the batched
+// launch) calls these functions and the library is built with
+// -ffp-contract=off, so a pixel's FP32 result does not depend on the
+// partition: fusion changes where intermediates live, not what is computed
+// (Sec. V-B: the fused kernel executes the same instructions, Algorithm 1).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fz {
+
+// Point op: integer BT.601 luma, round half up.  (299R + 587G + 114B + 500)
+// is at most 255500, and the division by the constant 1000 is exact integer
+// division.
+__device__ __forceinline__ uint32_t rgb2gray(uint32_t r, uint32_t g, uint32_t b)
+{
+    return (299u * r + 587u * g + 114u * b + 500u) / 1000u;
+}
+
+// Symmetric 5-tap weighted sum: w2*(x-2 + x+2) + w1*(x-1 + x+1) + w0*x0.
+struct Gauss5W {
+    float w0, w1, w2;
+};
+__device__ __forceinline__ float gauss5_taps(const Gauss5W& w, float m2, float m1, float c, float p1, float p2)
+{
+    float acc = w.w2 * (m2 + p2);
+    acc = __builtin_fmaf(w.w1, m1 + p1, acc);
+    return __builtin_fmaf(w.w0, c, acc);
+}
+
+// Unnormalised Sobel from the 3x3 neighbourhood g[row][col] (row = y-1..y+1).
+// Ix: column difference smoothed (1,2,1) over rows; Iy: the transpose.
+__device__ __forceinline__ void sobel3(const float g[3][3], float& ix, float& iy)
+{
+    float dm = g[0][2] - g[0][0];
+    float d0 = g[1][2] - g[1][0];
+    float dp = g[2][2] - g[2][0];
+    ix = __builtin_fmaf(2.0f, d0, dm + dp);
+    float em = g[2][0] - g[0][0];
+    float e0 = g[2][1] - g[0][1];
+    float ep = g[2][2] - g[0][2];
+    iy = __builtin_fmaf(2.0f, e0, em + ep);
+}
+
+__device__ __forceinline__ float gradmag(float ix, float iy)
+{
+    return __builtin_sqrtf(__builtin_fmaf(ix, ix, iy * iy));
+}
+
+__device__ __forceinline__ void products(float ix, float iy, float& pxx, float& pxy, float& pyy)
+{
+    pxx = ix * ix;
+    pxy = ix * iy;
+    pyy = iy * iy;
+}
+
+// Five-term sum, left to right.
+__device__ __forceinline__ float sum5(float a, float b, float c, float d, float e)
+{
+    return (((a + b) + c) + d) + e;
+}
+
+__device__ __forceinline__ float harris(float sxx, float sxy, float syy, float k)
+{
+    float det = __builtin_fmaf(sxx, syy, -(sxy * sxy));
+    float tr = sxx + syy;
+    return __builtin_fmaf(-k, tr * tr, det);
+}
+
+__device__ __forceinline__ float threshold(float v, float thr) { return v >= thr ? v : 0.0f; }
+
+__device__ __forceinline__ float max3(float a, float b, float c) { return __builtin_fmaxf(__builtin_fmaxf(a, b), c); }
+
+// 3x3 suppression decision given the centre and the window maximum.
+__device__ __forceinline__ uint32_t nms_keep(float c, float wmax) { return (c > 0.0f && c >= wmax) ? 255u : 0u; }
+
+__device__ __forceinline__ uint32_t framediff(uint32_t cur, uint32_t prev) { return cur > prev ? cur - prev : prev - cur; }
+
+}  // namespace fz

@@ -1,0 +1,332 @@
+"""Python binding of the fz C ABI (include/fz.h).
+
+Argument marshalling only: every step of the chain runs in the library's HIP
+kernels.  PyTorch supplies device memory and the stream.  The functions keep
+the C names; ``Plan`` is a small convenience wrapper that allocates outputs,
+workspace and the point buffer as torch tensors.
+
+The library is loaded from ``libfz.so`` next to this file; if it is missing the
+import of any entry point raises (there is no CPU fallback).
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfz.so")
+
+FZ_OK, FZ_E_INVALID, FZ_E_LDS, FZ_E_HIP, FZ_E_WORKSPACE, FZ_E_UNSUPPORTED = range(6)
+FZ_U8, FZ_F32 = 1, 2
+FZ_DEP_TT, FZ_DEP_TMT, FZ_DEP_KK = 0, 1, 2
+FZ_PART_OPTIMAL, FZ_PART_UNFUSED, FZ_PART_EXPLICIT = 0, 1, 2
+FZ_COST_ANALYTIC, FZ_COST_LEARNED, FZ_COST_MEASURED = 0, 1, 2
+
+OPS = {
+    "rgb2gray": 1, "gauss5": 2, "sobel3": 3, "gradmag": 4, "products": 5,
+    "boxsum5": 6, "harris": 7, "threshold": 8, "nms3": 9, "framediff": 10,
+}
+OP_NAMES = {v: k for k, v in OPS.items()}
+
+HARRIS_CHAIN = ["gauss5", "sobel3", "products", "boxsum5", "harris", "threshold", "nms3", "framediff"]
+RGB_HARRIS_CHAIN = ["rgb2gray"] + HARRIS_CHAIN
+GRAD_CHAIN = ["gauss5", "sobel3", "gradmag"]
+
+
+class FzError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"fz error {code}: {msg}")
+        self.code = code
+
+
+class fz_stage(ctypes.Structure):
+    _fields_ = [("op", ctypes.c_int32), ("rx", ctypes.c_int32), ("ry", ctypes.c_int32), ("rt", ctypes.c_int32),
+                ("in_ch", ctypes.c_int32), ("out_ch", ctypes.c_int32), ("in_dtype", ctypes.c_int32),
+                ("out_dtype", ctypes.c_int32), ("dep", ctypes.c_int32), ("param", ctypes.c_float * 4)]
+
+
+class fz_point(ctypes.Structure):
+    _fields_ = [("t", ctypes.c_uint32), ("y", ctypes.c_uint32), ("x", ctypes.c_uint32), ("response", ctypes.c_float)]
+
+
+class fz_plan_opts(ctypes.Structure):
+    _fields_ = [("width", ctypes.c_int32), ("height", ctypes.c_int32), ("frames", ctypes.c_int32),
+                ("lds_budget_bytes", ctypes.c_int32), ("partition", ctypes.c_int32), ("n_cuts", ctypes.c_int32),
+                ("cuts", ctypes.POINTER(ctypes.c_int32)), ("cost_model", ctypes.c_int32),
+                ("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32), ("frames_per_block", ctypes.c_int32)]
+
+
+class fz_segment_info(ctypes.Structure):
+    _fields_ = [("first", ctypes.c_int32), ("last", ctypes.c_int32), ("tile_w", ctypes.c_int32),
+                ("tile_h", ctypes.c_int32), ("frames_per_block", ctypes.c_int32), ("halo", ctypes.c_int32),
+                ("halo_t", ctypes.c_int32), ("lds_bytes", ctypes.c_int32), ("streaming", ctypes.c_int32),
+                ("bytes_per_px", ctypes.c_double), ("cost", ctypes.c_double)]
+
+
+_lib = None
+
+# (name, restype, argtypes) of every symbol include/fz.h declares
+SIGNATURES = [
+    ("fz_stage_describe", ctypes.c_int32, [ctypes.c_int32, ctypes.POINTER(fz_stage)]),
+    ("fz_plan_chain", ctypes.c_int32, [ctypes.POINTER(fz_stage), ctypes.c_int32, ctypes.POINTER(fz_plan_opts),
+                                       ctypes.POINTER(ctypes.c_void_p)]),
+    ("fz_plan_destroy", None, [ctypes.c_void_p]),
+    ("fz_plan_num_segments", ctypes.c_int32, [ctypes.c_void_p]),
+    ("fz_plan_segments", ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32), ctypes.c_int32]),
+    ("fz_plan_segment_info", ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(fz_segment_info)]),
+    ("fz_plan_cost", ctypes.c_double, [ctypes.c_void_p]),
+    ("fz_plan_group_cost", ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
+                                            ctypes.POINTER(ctypes.c_double)]),
+    ("fz_partition_min", ctypes.c_int32, [ctypes.POINTER(ctypes.c_double), ctypes.c_int32,
+                                          ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                                          ctypes.POINTER(ctypes.c_double)]),
+    ("fz_workspace_bytes", ctypes.c_size_t, [ctypes.c_void_p]),
+    ("fz_run_chain", ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                      ctypes.c_void_p, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_size_t,
+                                      ctypes.c_void_p]),
+    ("fz_last_error", ctypes.c_char_p, []),
+    ("fz_version", ctypes.c_char_p, []),
+]
+
+
+def lib():
+    """The loaded C library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() or "
+                              f"python paper_1509_04394_amd/build.py")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, res, args in SIGNATURES:
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != FZ_OK:
+        raise FzError(rc, fz_last_error())
+
+
+def fz_last_error() -> str:
+    return lib().fz_last_error().decode()
+
+
+def fz_version() -> str:
+    return lib().fz_version().decode()
+
+
+def fz_stage_describe(op) -> fz_stage:
+    s = fz_stage()
+    _check(lib().fz_stage_describe(OPS[op] if isinstance(op, str) else int(op), ctypes.byref(s)))
+    return s
+
+
+def fz_plan_chain(stages, opts: fz_plan_opts) -> ctypes.c_void_p:
+    arr = (fz_stage * len(stages))(*stages)
+    h = ctypes.c_void_p()
+    _check(lib().fz_plan_chain(arr, len(stages), ctypes.byref(opts), ctypes.byref(h)))
+    return h
+
+
+def fz_plan_destroy(plan):
+    lib().fz_plan_destroy(plan)
+
+
+def fz_plan_num_segments(plan) -> int:
+    return lib().fz_plan_num_segments(plan)
+
+
+def fz_plan_segments(plan) -> list[int]:
+    n = fz_plan_num_segments(plan)
+    buf = (ctypes.c_int32 * max(n, 1))()
+    _check(lib().fz_plan_segments(plan, buf, n))
+    return list(buf[:n])
+
+
+def fz_plan_segment_info(plan, i) -> fz_segment_info:
+    s = fz_segment_info()
+    _check(lib().fz_plan_segment_info(plan, i, ctypes.byref(s)))
+    return s
+
+
+def fz_plan_cost(plan) -> float:
+    return lib().fz_plan_cost(plan)
+
+
+def fz_plan_group_cost(plan, a, b) -> float:
+    c = ctypes.c_double()
+    _check(lib().fz_plan_group_cost(plan, a, b, ctypes.byref(c)))
+    return c.value
+
+
+def fz_partition_min(cost) -> tuple[float, list[int]]:
+    """cost: n x n nested list / array (inf = not allowed). Returns (total, seg_last)."""
+    n = len(cost)
+    flat = (ctypes.c_double * (n * n))()
+    for a in range(n):
+        for b in range(n):
+            v = cost[a][b] if b >= a else math.inf
+            flat[a * n + b] = math.inf if v is None else float(v)
+    sl = (ctypes.c_int32 * n)()
+    ns = ctypes.c_int32()
+    tot = ctypes.c_double()
+    _check(lib().fz_partition_min(flat, n, sl, ctypes.byref(ns), ctypes.byref(tot)))
+    return tot.value, list(sl[:ns.value])
+
+
+def fz_workspace_bytes(plan) -> int:
+    return int(lib().fz_workspace_bytes(plan))
+
+
+def fz_run_chain(plan, d_in, d_out, d_points, d_point_count, point_capacity, d_workspace, ws_bytes, stream):
+    _check(lib().fz_run_chain(plan, d_in, d_out, d_points, d_point_count, point_capacity, d_workspace, ws_bytes,
+                              stream))
+
+
+# ---------------------------------------------------------------- convenience wrapper
+def make_opts(W, H, T, partition="optimal", lds_budget=0, tile=None, frames_per_block=0, cost_model="analytic"):
+    o = fz_plan_opts()
+    o.width, o.height, o.frames = int(W), int(H), int(T)
+    o.lds_budget_bytes = int(lds_budget)
+    o._cuts = None
+    if partition == "optimal":
+        o.partition = FZ_PART_OPTIMAL
+    elif partition == "unfused":
+        o.partition = FZ_PART_UNFUSED
+    else:
+        cuts = list(partition)
+        o.partition = FZ_PART_EXPLICIT
+        o._cuts = (ctypes.c_int32 * max(len(cuts), 1))(*cuts)
+        o.cuts = ctypes.cast(o._cuts, ctypes.POINTER(ctypes.c_int32))
+        o.n_cuts = len(cuts)
+    o.cost_model = {"analytic": FZ_COST_ANALYTIC, "learned": FZ_COST_LEARNED, "measured": FZ_COST_MEASURED}[cost_model]
+    if tile is not None:
+        o.tile_w, o.tile_h = int(tile[0]), int(tile[1])
+    o.frames_per_block = int(frames_per_block)
+    return o
+
+
+class Plan:
+    """A planned chain of named ops for videos of W x H x T.
+
+    partition: "optimal" (planner), "unfused" (one kernel per stage) or a list
+    of cut positions (last stage index of every group but the final).
+    params: optional dict op name -> param[0] (sigma, k or threshold).
+    """
+
+    def __init__(self, ops, W, H, T, partition="optimal", lds_budget=0, tile=None, frames_per_block=0,
+                 params=None, deps=None):
+        self.ops = list(ops)
+        self.W, self.H, self.T = int(W), int(H), int(T)
+        stages = []
+        for i, op in enumerate(self.ops):
+            s = fz_stage_describe(op)
+            if params and op in params:
+                s.param[0] = float(params[op])
+            if deps and i in deps:
+                s.dep = int(deps[i])
+            stages.append(s)
+        self.stages = stages
+        self.opts = make_opts(W, H, T, partition, lds_budget, tile, frames_per_block)
+        self.handle = fz_plan_chain(stages, self.opts)
+        self._ws = None
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.fz_plan_destroy(h)
+            self.handle = None
+
+    # introspection
+    @property
+    def segments(self):
+        return fz_plan_segments(self.handle)
+
+    def segment_info(self):
+        return [fz_plan_segment_info(self.handle, i) for i in range(fz_plan_num_segments(self.handle))]
+
+    @property
+    def cost(self):
+        return fz_plan_cost(self.handle)
+
+    def group_cost(self, a, b):
+        return fz_plan_group_cost(self.handle, a, b)
+
+    @property
+    def workspace_bytes(self):
+        return fz_workspace_bytes(self.handle)
+
+    # shapes
+    def input_shape(self):
+        s = self.stages[0]
+        if s.op == OPS["rgb2gray"]:
+            return (self.T, self.H, self.W, 3)
+        if s.in_dtype == FZ_U8:
+            return (self.T, self.H, self.W)
+        return (s.in_ch, self.T, self.H, self.W)
+
+    def output_shape(self):
+        s = self.stages[-1]
+        if s.out_dtype == FZ_U8:
+            return (self.T, self.H, self.W)
+        return (s.out_ch, self.T, self.H, self.W)
+
+    def output_dtype(self):
+        import torch
+        return torch.uint8 if self.stages[-1].out_dtype == FZ_U8 else torch.float32
+
+    def has_points(self):
+        return any(s.op == OPS["nms3"] for s in self.stages)
+
+    def alloc(self, device="cuda", point_capacity=1 << 20):
+        """Allocate (out, points, count, workspace) tensors for a run."""
+        import torch
+        out = torch.empty(self.output_shape(), dtype=self.output_dtype(), device=device)
+        pts = cnt = None
+        if self.has_points() and point_capacity > 0:
+            pts = torch.empty((point_capacity, 4), dtype=torch.int32, device=device)
+            cnt = torch.zeros((1,), dtype=torch.int32, device=device)
+        ws = torch.empty((max(self.workspace_bytes, 1),), dtype=torch.uint8, device=device)
+        return out, pts, cnt, ws
+
+    def run(self, x, out=None, points=None, count=None, workspace=None, stream=None):
+        """Run on device tensors (asynchronous on the current torch stream)."""
+        import torch
+        if tuple(x.shape) != self.input_shape():
+            raise ValueError(f"input shape {tuple(x.shape)} != {self.input_shape()}")
+        want = torch.uint8 if self.stages[0].in_dtype == FZ_U8 else torch.float32
+        if x.dtype != want or not x.is_contiguous() or not x.is_cuda:
+            raise ValueError("input must be a contiguous CUDA tensor of the first stage's type")
+        if out is None:
+            out, p2, c2, ws2 = self.alloc(x.device)
+            points = points if points is not None else p2
+            count = count if count is not None else c2
+            workspace = workspace if workspace is not None else ws2
+        if workspace is None:
+            workspace = torch.empty((max(self.workspace_bytes, 1),), dtype=torch.uint8, device=x.device)
+        if stream is None:
+            stream = torch.cuda.current_stream(x.device).cuda_stream
+        cap = points.shape[0] if points is not None else 0
+        fz_run_chain(self.handle, x.data_ptr(), out.data_ptr(),
+                     points.data_ptr() if points is not None else None,
+                     count.data_ptr() if count is not None else None, cap,
+                     workspace.data_ptr(), workspace.numel(), stream)
+        return out, points, count
+
+
+def points_to_numpy(points, count):
+    """Device point buffer -> numpy array rows (t, y, x, response), count-limited."""
+    import numpy as np
+    n = int(count.item())
+    cap = points.shape[0]
+    if n > cap:
+        raise RuntimeError(f"point buffer overflow: {n} > {cap}")
+    raw = points[:n].cpu().numpy()
+    out = np.empty((n, 4), np.float64)
+    out[:, :3] = raw[:, :3].view(np.uint32)
+    out[:, 3] = raw[:, 3].view(np.float32)
+    return out

@@ -24,6 +24,9 @@ Recipe (all draws from numpy PCG64 seeded by ``seed``):
 """
 from __future__ import annotations
 
+import os
+from concurrent.futures import ThreadPoolExecutor
+
 import numpy as np
 from scipy.interpolate import RectBivariateSpline
 
@@ -92,18 +95,30 @@ class VideoSpec:
 
 
 def video(width: int, height: int, frames: int, seed: int, rgb: bool = False,
-          t0: int = 0, out: np.ndarray | None = None) -> np.ndarray:
+          t0: int = 0, out: np.ndarray | None = None, workers: int | None = None) -> np.ndarray:
     """Frames [t0, t0+frames) of the clip.
 
-    Gray: uint8 [T][H][W].  RGB: uint8 [T][H][W][3] (interleaved).
+    Gray: uint8 [T][H][W].  RGB: uint8 [T][H][W][3] (interleaved).  Frames are
+    independent draws, so they are made in parallel threads; the result does
+    not depend on ``workers``.
     """
     spec = VideoSpec(width, height, seed, 3 if rgb else 1)
     shape = (frames, height, width, 3) if rgb else (frames, height, width)
     if out is None:
         out = np.empty(shape, np.uint8)
-    for i in range(frames):
+
+    def one(i):
         fr = spec.frame(t0 + i)
         out[i] = fr if rgb else fr[:, :, 0]
+
+    if workers is None:
+        workers = min(16, os.cpu_count() or 1)
+    if workers <= 1 or frames < 4:
+        for i in range(frames):
+            one(i)
+    else:
+        with ThreadPoolExecutor(workers) as ex:
+            list(ex.map(one, range(frames)))
     return out
 
 

@@ -1,0 +1,173 @@
+"""Host-side tests of the planner and the C ABI (no GPU needed).
+
+The DP optimum is compared with the exhaustive enumeration of every partition
+(oracle/partition.py) on the planner's own price tables and on random tables
+with ties and forbidden groups, for every chain length up to 10.
+"""
+import ctypes
+import math
+import re
+
+import numpy as np
+import pytest
+
+from oracle import partition as P
+from paper_1509_04394_amd import fz
+
+
+def test_library_exports_every_declared_symbol():
+    header = open(fz.os.path.join(fz.os.path.dirname(fz.HERE), "include", "fz.h")).read()
+    declared = set(re.findall(r"\b(fz_[a-z_]+)\s*\(", header))
+    declared -= {"fz_plan"}  # type name, not a function
+    L = ctypes.CDLL(fz.LIB_PATH)
+    for name in declared:
+        assert hasattr(L, name), name
+    assert declared == {n for n, _, _ in fz.SIGNATURES}
+
+
+@pytest.mark.parametrize("n", range(1, 11))
+def test_dp_equals_exhaustive_random_tables(n):
+    rng = np.random.default_rng(100 + n)
+    for trial in range(30):
+        c = [[None] * n for _ in range(n)]
+        for a in range(n):
+            for b in range(a, n):
+                r = rng.random()
+                # small integer prices give many exact ties; some groups forbidden
+                c[a][b] = math.inf if (r < 0.15 and b > a) else float(rng.integers(1, 6))
+        total, sl = fz.fz_partition_min(c)
+        want_total, groups = P.best(c, n)
+        assert total == want_total
+        assert sl == [b for (_, b) in groups]
+
+
+def test_dp_infeasible():
+    c = [[math.inf, math.inf], [None, math.inf]]
+    total, sl = fz.fz_partition_min(c)
+    assert math.isinf(total) and sl == []
+
+
+CHAINS = [fz.RGB_HARRIS_CHAIN, fz.HARRIS_CHAIN, fz.GRAD_CHAIN, fz.HARRIS_CHAIN[2:7]]
+
+
+@pytest.mark.parametrize("ops", CHAINS, ids=lambda o: "-".join(o))
+@pytest.mark.parametrize("budget", [0, 40000, 24000])
+def test_planner_optimum_equals_exhaustive(ops, budget):
+    try:
+        plan = fz.Plan(ops, 800, 600, 1000, lds_budget=budget)
+    except fz.FzError as e:
+        assert e.code == fz.FZ_E_LDS
+        return
+    n = len(ops)
+    c = [[plan.group_cost(a, b) if b >= a else None for b in range(n)] for a in range(n)]
+    want, groups = P.best(c, n)
+    assert plan.cost == want
+    assert plan.segments == [b for (_, b) in groups]
+
+
+def test_analytic_costs_are_compulsory_traffic():
+    # per-pixel bytes in/out of every stage of the Harris chain (u8 RGB input)
+    ops = fz.RGB_HARRIS_CHAIN
+    bi = [3, 1, 4, 8, 12, 12, 4, 4, 1]
+    bo = [1, 4, 8, 12, 12, 4, 4, 1, 1]
+    W, H, T = 800, 600, 1000
+    npx = W * H * T
+    plan = fz.Plan(ops, W, H, T, partition="unfused")
+    info = plan.segment_info()
+    for i, s in enumerate(info):
+        extra = bi[i] if ops[i] == "framediff" else 0.0  # the previous frame is re-read
+        assert s.bytes_per_px == P.compulsory_bytes(bi, bo, i, i) + extra
+    assert plan.cost == npx * (P.unfused_bytes(bi, bo) + 1)
+    full = fz.Plan(ops, W, H, T)
+    assert full.segments == [8]
+    s = full.segment_info()[0]
+    assert s.halo == 6 and s.halo_t == 1
+    assert s.bytes_per_px == 3 + 1 + 3 / s.frames_per_block
+    assert s.lds_bytes <= 163840
+
+
+def test_halo_is_sum_of_radii_not_max():
+    # gauss (r=2) then sobel (r=1) needs a 3-pixel halo; taking the larger
+    # radius (2) would leave the sobel of the outermost output pixels reading
+    # gauss values that were never computed
+    plan = fz.Plan(["gauss5", "sobel3"], 64, 48, 2)
+    assert plan.segment_info()[0].halo == 3
+    plan = fz.Plan(fz.HARRIS_CHAIN[:7], 64, 48, 2)
+    assert plan.segment_info()[0].halo == 2 + 1 + 2 + 1
+
+
+def test_kk_dependence_forces_a_cut():
+    plan = fz.Plan(fz.HARRIS_CHAIN, 192, 432, 600, deps={4: fz.FZ_DEP_KK})
+    segs = plan.segments
+    assert 3 in segs  # group boundary right before stage 4
+    assert math.isinf(plan.group_cost(0, 4)) and math.isinf(plan.group_cost(3, 5))
+
+
+def test_budget_limits_fusion():
+    loose = fz.Plan(fz.HARRIS_CHAIN, 192, 432, 600)
+    tight = fz.Plan(fz.HARRIS_CHAIN, 192, 432, 600, lds_budget=40000)
+    assert len(loose.segments) == 1
+    assert len(tight.segments) >= 1
+    for s in tight.segment_info():
+        assert s.lds_bytes <= 40000
+    assert tight.cost >= loose.cost
+
+
+def test_explicit_and_unfused_partitions():
+    p = fz.Plan(fz.HARRIS_CHAIN, 64, 48, 4, partition=[0, 2, 5])
+    assert p.segments == [0, 2, 5, 7]
+    u = fz.Plan(fz.HARRIS_CHAIN, 64, 48, 4, partition="unfused")
+    assert u.segments == list(range(8))
+    assert u.workspace_bytes >= 64 * 48 * 4 * 12
+
+
+@pytest.mark.parametrize("bad", [
+    dict(ops=["sobel3", "gauss5"]),                       # not a compiled sequence / type mismatch
+    dict(ops=["gauss5"], W=0),
+    dict(ops=["gauss5"], T=-1),
+    dict(ops=fz.HARRIS_CHAIN, partition=[3, 3]),
+    dict(ops=fz.HARRIS_CHAIN, partition=[7]),
+    dict(ops=["gauss5"], tile=(48, 48)),
+])
+def test_plan_errors(bad):
+    kw = dict(W=64, H=48, T=2)
+    kw.update(bad)
+    ops = kw.pop("ops")
+    with pytest.raises(fz.FzError) as e:
+        fz.Plan(ops, kw.pop("W"), kw.pop("H"), kw.pop("T"), **kw)
+    assert e.value.code in (fz.FZ_E_INVALID, fz.FZ_E_UNSUPPORTED)
+    assert fz.fz_last_error()
+
+
+def test_descriptor_mismatch_rejected():
+    s = fz.fz_stage_describe("gauss5")
+    s.rx = 3
+    with pytest.raises(fz.FzError) as e:
+        fz.fz_plan_chain([s], fz.make_opts(10, 10, 1))
+    assert e.value.code == fz.FZ_E_INVALID
+
+
+def test_run_argument_errors_without_launch():
+    p = fz.Plan(fz.HARRIS_CHAIN, 64, 48, 2, partition="unfused")
+    with pytest.raises(fz.FzError) as e:
+        fz.fz_run_chain(p.handle, 1, 1, None, None, 0, None, 0, None)
+    assert e.value.code == fz.FZ_E_WORKSPACE
+    with pytest.raises(fz.FzError) as e:
+        fz.fz_run_chain(p.handle, None, 1, None, None, 0, None, 0, None)
+    assert e.value.code == fz.FZ_E_INVALID
+    with pytest.raises(fz.FzError) as e:
+        fz.fz_run_chain(p.handle, 1, 1, None, None, 5, 1, 1 << 40, None)
+    assert e.value.code == fz.FZ_E_INVALID
+
+
+def test_stage_describe_access_patterns():
+    # Table I classes: point ops read one pixel, window ops a square, the frame
+    # difference one frame back
+    for name in ["rgb2gray", "gradmag", "products", "harris", "threshold"]:
+        s = fz.fz_stage_describe(name)
+        assert (s.rx, s.ry, s.rt) == (0, 0, 0)
+    assert (fz.fz_stage_describe("gauss5").rx, fz.fz_stage_describe("boxsum5").rx) == (2, 2)
+    assert (fz.fz_stage_describe("sobel3").rx, fz.fz_stage_describe("nms3").rx) == (1, 1)
+    assert fz.fz_stage_describe("framediff").rt == 1
+    with pytest.raises(fz.FzError):
+        fz.fz_stage_describe(99)
