@@ -62,7 +62,8 @@ def test_rgb2gray_every_triple(dev):
     v = np.arange(1 << 24, dtype=np.uint32)
     rgb = np.stack([(v >> 16) & 255, (v >> 8) & 255, v & 255], -1).astype(np.uint8).reshape(1, 4096, 4096, 3)
     g, _, _ = run_gpu(["rgb2gray"], rgb, dev)
-    ref = (299 * rgb[..., 0].astype(np.int64) + 587 * rgb[..., 1] + 114 * rgb[..., 2] + 500) // 1000
+    c = rgb.astype(np.int64)
+    ref = (299 * c[..., 0] + 587 * c[..., 1] + 114 * c[..., 2] + 500) // 1000
     o, _ = oracle_run(["rgb2gray"], rgb[:, :64])  # the oracle on a slice pins ref's formula
     assert np.array_equal(o[0], ref[:, :64])
     assert np.array_equal(g, ref.astype(np.uint8))
