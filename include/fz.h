@@ -103,18 +103,28 @@ typedef struct fz_plan_opts {
     int32_t cost_model;             /* FZ_COST_*; only FZ_COST_ANALYTIC is implemented */
     int32_t tile_w, tile_h;         /* output box of one workgroup; 0 = planner's choice */
     int32_t frames_per_block;       /* frames one workgroup marches through; 0 = planner's choice */
+    int32_t engine;                 /* FZ_ENGINE_*: kernel family for groups that have a choice */
 } fz_plan_opts;
+
+/* Kernel families.  TILE: a workgroup loads its halo box into LDS and runs the
+ * group's stages there (any group).  ROW: a wavefront marches down a strip of
+ * columns keeping each stage's live rows in registers (the Harris chain from
+ * the Gaussian or the gray conversion to the suppression or the frame
+ * difference, frames at least 128 pixels wide).  AUTO picks ROW where it
+ * applies, TILE elsewhere. */
+enum { FZ_ENGINE_AUTO = 0, FZ_ENGINE_TILE = 1, FZ_ENGINE_ROW = 2, FZ_ENGINE_STREAM = 3 };
 
 typedef struct fz_plan fz_plan;  /* opaque, host memory */
 
 /* Per-group description of a plan. */
 typedef struct fz_segment_info {
     int32_t first, last;            /* stage indices covered by this fused kernel */
-    int32_t tile_w, tile_h;         /* output box x, y (Sec. V, Fig. 3) */
+    int32_t tile_w, tile_h;         /* output box x, y (Sec. V, Fig. 3); ROW: strip span, band rows */
     int32_t frames_per_block;       /* output box t */
     int32_t halo, halo_t;           /* input-box growth per side in x/y, and in frames (Sec. VI-C) */
     int32_t lds_bytes;              /* on-chip memory of one workgroup */
     int32_t streaming;              /* 1 = no window stage: one pass, no on-chip staging */
+    int32_t engine;                 /* FZ_ENGINE_TILE, FZ_ENGINE_ROW or FZ_ENGINE_STREAM */
     double bytes_per_px;            /* compulsory global-memory bytes per output pixel */
     double cost;                    /* the planner's cost of this group */
 } fz_segment_info;

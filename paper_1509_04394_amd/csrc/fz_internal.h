@@ -21,6 +21,8 @@ struct Segment {
     int halo, halo_t;
     int lds_bytes;
     int streaming;
+    int engine;             // FZ_ENGINE_TILE / ROW / STREAM
+    int row_k, nstrips, nbands, nchunks;  // row-marching geometry
     double bytes_per_px;
     double cost;
 };
@@ -52,7 +54,7 @@ void set_error(const std::string& msg);
 fz_status fail(fz_status code, const std::string& msg);
 
 // Price of group [a..b] of plan p, with its tile / frames-per-block choice.
-Segment price_group(const fz_plan& p, int a, int b, int tile_req_w, int tile_req_h, int tpb_req);
+Segment price_group(const fz_plan& p, int a, int b, int tile_req_w, int tile_req_h, int tpb_req, int engine_req);
 
 // Exact partition DP (Fig. 5 model) with the tie rule: fewer groups, then later cuts.
 double partition_dp(const double* cost, int n, std::vector<int>& seg_last);

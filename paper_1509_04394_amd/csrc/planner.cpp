@@ -16,6 +16,7 @@
 #include <vector>
 
 #include "fz_internal.h"
+#include "rowgeom.h"
 
 namespace fz {
 
@@ -49,7 +50,7 @@ static double data_utilisation(int x, int y, int t, int H, int Ht)
     return (double)x * y * t / ((double)(x + 2 * H) * (y + 2 * H) * (t + Ht));
 }
 
-Segment price_group(const fz_plan& p, int a, int b, int req_w, int req_h, int req_tpb)
+Segment price_group(const fz_plan& p, int a, int b, int req_w, int req_h, int req_tpb, int req_engine)
 {
     Segment s{};
     s.first = a;
@@ -66,10 +67,28 @@ Segment price_group(const fz_plan& p, int a, int b, int req_w, int req_h, int re
     s.streaming = group_has_window(ch, A, B) ? 0 : 1;
     s.tpb = req_tpb > 0 ? req_tpb : (s.halo_t > 0 ? 8 : 1);
     if (s.tpb > p.T) s.tpb = p.T;
+    const bool row_ok = !s.streaming && row_group(ch, A, B) && row_strips_best(p.W) > 0 && p.H >= 8 &&
+                        req_engine != FZ_ENGINE_TILE && req_w == 0;
     if (s.streaming) {
+        s.engine = FZ_ENGINE_STREAM;
         s.lds_bytes = 0;
         s.tile_w = s.tile_h = 0;
+    } else if (row_ok) {
+        s.engine = FZ_ENGINE_ROW;
+        const bool diff = chain_op(ch, B) == FZ_OP_FRAMEDIFF;
+        s.row_k = row_strips_best(p.W);
+        s.nstrips = row_strips(p.W, s.row_k);
+        const RowShape rs = row_shape(p.H, p.T, s.nstrips, diff, req_h, req_tpb);
+        s.tpb = rs.tt;
+        s.nchunks = (p.T + s.tpb - 1) / s.tpb;
+        s.tile_h = rs.band_h;
+        s.nbands = (p.H + s.tile_h - 1) / s.tile_h;
+        s.tile_w = 64 * s.row_k;
+        s.lds_bytes = diff ? row_lds_bytes(s.tile_h) : 0;
+        if (s.lds_bytes > p.lds_budget) return s;
+        s.tile = 0;
     } else {
+        s.engine = FZ_ENGINE_TILE;
         double best_du = -1.0;
         for (int t = 0; t < N_TILES; ++t) {
             const int tw = tile_w(t), th = tile_h(t);
@@ -183,8 +202,11 @@ fz_status fz_plan_chain(const fz_stage* stages, int32_t n, const fz_plan_opts* o
     if (opts->cost_model != FZ_COST_ANALYTIC)
         return fail(FZ_E_UNSUPPORTED, "fz_plan_chain: only the analytic cost model is available here");
     if (opts->frames_per_block < 0) return fail(FZ_E_INVALID, "fz_plan_chain: negative frames_per_block");
-    if ((opts->tile_w > 0) != (opts->tile_h > 0))
-        return fail(FZ_E_INVALID, "fz_plan_chain: give both tile_w and tile_h or neither");
+    if (opts->engine < FZ_ENGINE_AUTO || opts->engine > FZ_ENGINE_ROW)
+        return fail(FZ_E_INVALID, "fz_plan_chain: unknown engine");
+    if (opts->tile_w > 0 && opts->tile_h <= 0)
+        return fail(FZ_E_INVALID, "fz_plan_chain: a tile width needs a tile height");
+    if (opts->tile_w < 0 || opts->tile_h < 0) return fail(FZ_E_INVALID, "fz_plan_chain: negative tile size");
 
     // validate the descriptors against the operation registry (Sec. IV access patterns)
     for (int i = 0; i < n; ++i) {
@@ -245,7 +267,7 @@ fz_status fz_plan_chain(const fz_stage* stages, int32_t n, const fz_plan_opts* o
     }
     // a stage that cannot run even alone makes the chain infeasible
     for (int i = 0; i < n; ++i) {
-        Segment s = price_group(*p, i, i, opts->tile_w, opts->tile_h, opts->frames_per_block);
+        Segment s = price_group(*p, i, i, opts->tile_w, opts->tile_h, opts->frames_per_block, opts->engine);
         if (!(s.cost < kInf)) {
             delete p;
             if (opts->tile_w > 0)
@@ -257,7 +279,7 @@ fz_status fz_plan_chain(const fz_stage* stages, int32_t n, const fz_plan_opts* o
     std::vector<std::vector<Segment>> segtab(n, std::vector<Segment>(n));
     for (int a = 0; a < n; ++a)
         for (int b = a; b < n; ++b) {
-            segtab[a][b] = price_group(*p, a, b, opts->tile_w, opts->tile_h, opts->frames_per_block);
+            segtab[a][b] = price_group(*p, a, b, opts->tile_w, opts->tile_h, opts->frames_per_block, opts->engine);
             p->cost[(size_t)a * n + b] = segtab[a][b].cost;
         }
     std::vector<int> seg_last;
@@ -333,6 +355,7 @@ fz_status fz_plan_segment_info(const fz_plan* plan, int32_t i, fz_segment_info* 
     out->halo_t = s.halo_t;
     out->lds_bytes = s.lds_bytes;
     out->streaming = s.streaming;
+    out->engine = s.engine;
     out->bytes_per_px = s.bytes_per_px;
     out->cost = s.cost;
     return FZ_OK;

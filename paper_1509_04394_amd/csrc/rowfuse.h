@@ -1,0 +1,313 @@
+// Row-marching fused kernel for the Harris chain (gray or RGB input,
+// Gaussian 5x5 -> Sobel -> products -> 5x5 sums -> Harris -> threshold ->
+// 3x3 suppression [-> frame difference]).
+//
+// Same computation as the LDS tile engine (same per-pixel expressions, so the
+// outputs are identical bit for bit), organised for gfx950 wavefronts:
+//   * a wavefront owns a strip of 64*K columns (K adjacent columns per lane)
+//     of a band of rows of one frame and marches down the rows; every window
+//     stage keeps the few rows it still needs in registers (rings of 2r+1
+//     rows), so nothing is staged in LDS and no barrier is needed;
+//   * horizontal neighbours come from the adjacent lanes through DPP wave
+//     shifts; a lane at the strip's edge receives its own edge value, which is
+//     exactly the replicate border when the strip touches the frame edge (and a
+//     don't-care halo value inside the frame, where the strips overlap by the
+//     chain's horizontal halo);
+//   * the row loop is unrolled by 15 (the least common multiple of the ring
+//     sizes 3 and 5) so every ring slot is a fixed register;
+//   * vertical replicate borders: when a stage produces the first row of the
+//     frame it also writes it into the ring slots of the rows above, and after
+//     the last row it copies it into the slots of the rows below, one slot per
+//     iteration, once the consumer no longer needs the slot's old row;
+//   * the suppression mask feeds the frame difference through a per-wavefront
+//     LDS row of previous-frame mask bits; a work item then covers a run of
+//     frames, preceded by the frame before them (one frame of temporal halo).
+// The input rows are prefetched two iterations ahead.
+#pragma once
+
+#include "engine.h"
+#include "rowgeom.h"
+
+namespace fz {
+
+constexpr int ROW_UNROLL = 15;  // lcm of the ring sizes
+
+struct RowParams {
+    SegParams sp;
+    int nstrips, nbands, nchunks, total;
+    int strip_step;  // 64K - 2*ROW_HX
+    int band_h;
+    int tt;          // frames per work item
+};
+
+__device__ __forceinline__ float dpp_from_left(float v, float edge)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(edge), __float_as_int(v), 0x138, 0xf, 0xf, false));
+}
+__device__ __forceinline__ float dpp_from_right(float v, float edge)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(edge), __float_as_int(v), 0x130, 0xf, 0xf, false));
+}
+
+// e[0 .. K+2R) = this lane's columns x-R .. x+K-1+R of a row held K per lane.
+template <int K, int R>
+__device__ __forceinline__ void extend_row(const float (&v)[K], float (&e)[K + 2 * R])
+{
+    static_assert(R <= K, "neighbour lanes must hold the halo");
+#pragma unroll
+    for (int k = 0; k < K; ++k) e[R + k] = v[k];
+#pragma unroll
+    for (int i = 1; i <= R; ++i) {
+        e[R - i] = dpp_from_left(v[K - i], v[0]);
+        e[R + K - 1 + i] = dpp_from_right(v[i - 1], v[K - 1]);
+    }
+}
+
+template <int K>
+__device__ __forceinline__ void copy_row(float (&d)[K], const float (&s)[K])
+{
+#pragma unroll
+    for (int k = 0; k < K; ++k) d[k] = s[k];
+}
+
+template <int K, bool RGB>
+struct RowState {
+    static constexpr int NRAW = RGB ? 3 * K : K;
+    float h[5][K];     // Gaussian horizontal pass
+    float g[3][K];     // Gaussian output
+    float b[5][3][K];  // window-sum horizontal pass, 3 channels
+    float rt[3][K];    // thresholded response
+    float m[3][K];     // 3-wide horizontal maximum of rt
+    uint32_t raw[3][NRAW];
+};
+
+struct RowCtx {
+    const uint8_t* in_frame;  // frame t of the input
+    uint8_t* out_frame;       // frame t of the output
+    int W, Hf, x0, lane, y0, y1, t;
+    bool real;
+    uint32_t valid;           // bit k: column k of this lane is an output column of the strip
+    int lo_in, hi_in, lo_g, hi_g, lo_s, hi_s, lo_b, hi_b;
+    uint8_t* prev;            // LDS previous-frame mask bits of this wavefront (DIFF)
+};
+
+template <int K, bool RGB>
+__device__ __forceinline__ void load_raw(const RowCtx& c, int row, uint32_t (&raw)[RowState<K, RGB>::NRAW])
+{
+    constexpr int C = RGB ? 3 : 1;
+    const uint8_t* p = c.in_frame + ((size_t)row * c.W + c.x0 + K * c.lane) * C;
+#pragma unroll
+    for (int i = 0; i < K * C; ++i) raw[i] = p[i];
+}
+
+template <int K, bool RGB, bool DIFF, int U>
+__device__ __forceinline__ void row_step(RowState<K, RGB>& st, const RowCtx& c, const SegParams& p, int j)
+{
+    constexpr int U3 = U % 3, U5 = U % 5;
+    const int row_in = c.y0 - ROW_HX + j;
+
+    // prefetch the input row two iterations ahead
+    {
+        const int rp = row_in + 2;
+        if (rp >= c.lo_in && rp < c.hi_in) load_raw<K, RGB>(c, rp, st.raw[(U + 2) % 3]);
+    }
+    // Gaussian, horizontal pass, on the gray input row
+    if (row_in >= c.lo_in && row_in < c.hi_in) {
+        float gr[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            if constexpr (RGB)
+                gr[k] = (float)rgb2gray(st.raw[U3][3 * k], st.raw[U3][3 * k + 1], st.raw[U3][3 * k + 2]);
+            else
+                gr[k] = (float)st.raw[U3][k];
+        }
+        float e[K + 4];
+        extend_row<K, 2>(gr, e);
+#pragma unroll
+        for (int k = 0; k < K; ++k) st.h[U5][k] = gauss5_taps(p.gw, e[k], e[k + 1], e[k + 2], e[k + 3], e[k + 4]);
+        if (row_in == 0) {
+            copy_row<K>(st.h[(U + 4) % 5], st.h[U5]);
+            copy_row<K>(st.h[(U + 3) % 5], st.h[U5]);
+        }
+    }
+    // Gaussian, vertical pass: row row_in - 2
+    const int rg = row_in - 2;
+    if (rg >= c.lo_g && rg < c.hi_g) {
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+            st.g[U3][k] = gauss5_taps(p.gw, st.h[(U + 1) % 5][k], st.h[(U + 2) % 5][k], st.h[(U + 3) % 5][k],
+                                      st.h[(U + 4) % 5][k], st.h[U5][k]);
+        if (rg == 0) copy_row<K>(st.g[(U + 2) % 3], st.g[U3]);
+    }
+    // Sobel, products and the horizontal pass of the window sums: row row_in - 3
+    const int rs = row_in - 3;
+    if (rs >= c.lo_s && rs < c.hi_s) {
+        float sv[K], ev[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const float gm = st.g[(U + 1) % 3][k], g0 = st.g[(U + 2) % 3][k], gp = st.g[U3][k];
+            sv[k] = sobel_sv(gm, g0, gp);
+            ev[k] = sobel_e(gm, gp);
+        }
+        float esv[K + 2], eev[K + 2];
+        extend_row<K, 1>(sv, esv);
+        extend_row<K, 1>(ev, eev);
+        float pr[3][K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const float ix = sobel_ix(esv[k], esv[k + 2]);
+            const float iy = sobel_iy(eev[k], eev[k + 1], eev[k + 2]);
+            products(ix, iy, pr[0][k], pr[1][k], pr[2][k]);
+        }
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) {
+            float e[K + 4];
+            extend_row<K, 2>(pr[ch], e);
+#pragma unroll
+            for (int k = 0; k < K; ++k) st.b[U5][ch][k] = sum5(e[k], e[k + 1], e[k + 2], e[k + 3], e[k + 4]);
+        }
+        if (rs == 0) {
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch) {
+                copy_row<K>(st.b[(U + 4) % 5][ch], st.b[U5][ch]);
+                copy_row<K>(st.b[(U + 3) % 5][ch], st.b[U5][ch]);
+            }
+        }
+    }
+    // Window sums (vertical), Harris, threshold, 3-wide maximum: row row_in - 5
+    const int rb = row_in - 5;
+    if (rb >= c.lo_b && rb < c.hi_b) {
+        float s[3][K];
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch)
+#pragma unroll
+            for (int k = 0; k < K; ++k)
+                s[ch][k] = sum5(st.b[(U + 1) % 5][ch][k], st.b[(U + 2) % 5][ch][k], st.b[(U + 3) % 5][ch][k],
+                                st.b[(U + 4) % 5][ch][k], st.b[U5][ch][k]);
+#pragma unroll
+        for (int k = 0; k < K; ++k) st.rt[U3][k] = threshold(harris(s[0][k], s[1][k], s[2][k], p.k), p.thr);
+        float e[K + 2];
+        extend_row<K, 1>(st.rt[U3], e);
+#pragma unroll
+        for (int k = 0; k < K; ++k) st.m[U3][k] = max3(e[k], e[k + 1], e[k + 2]);
+        if (rb == 0) {
+            copy_row<K>(st.rt[(U + 2) % 3], st.rt[U3]);
+            copy_row<K>(st.m[(U + 2) % 3], st.m[U3]);
+        }
+    }
+    // Suppression, feature points, output: row row_in - 6
+    const int rn = row_in - 6;
+    if (rn >= c.y0 && rn < c.y1) {
+        uint32_t bits = 0;
+        float centre[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const float wmax = max3(st.m[(U + 1) % 3][k], st.m[(U + 2) % 3][k], st.m[U3][k]);
+            centre[k] = st.rt[(U + 2) % 3][k];
+            bits |= (nms_keep(centre[k], wmax) != 0u ? 1u : 0u) << k;
+        }
+        if (p.count != nullptr) {
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const bool is_pt = c.real && ((bits & c.valid) >> k & 1u);
+                emit_points(p, is_pt, (uint32_t)c.t, (uint32_t)rn, (uint32_t)(c.x0 + K * c.lane + k), centre[k]);
+            }
+        }
+        uint32_t outbits = bits;
+        if constexpr (DIFF) {
+            uint8_t* slot = c.prev + (rn - c.y0) * 64 + c.lane;
+            const uint32_t prev = c.t == 0 ? bits : (uint32_t)*slot;
+            *slot = (uint8_t)bits;
+            outbits = bits ^ prev;
+        }
+        if (c.real) {
+            uint8_t* o = c.out_frame + (size_t)rn * c.W + c.x0 + K * c.lane;
+#pragma unroll
+            for (int k = 0; k < K; ++k)
+                if (c.valid >> k & 1u) o[k] = (outbits >> k & 1u) ? (uint8_t)255 : (uint8_t)0;
+        }
+    }
+    // bottom replicate: after the last frame row, copy it into the next slot of
+    // each ring, once per iteration, for as many rows as the consumer reads
+    if (row_in >= c.Hf - 1 && row_in <= c.Hf) copy_row<K>(st.h[(U + 1) % 5], st.h[U5]);
+    if (rg == c.Hf - 1) copy_row<K>(st.g[(U + 1) % 3], st.g[U3]);
+    if (rs >= c.Hf - 1 && rs <= c.Hf) {
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) copy_row<K>(st.b[(U + 1) % 5][ch], st.b[U5][ch]);
+    }
+    if (rb == c.Hf - 1) {
+        copy_row<K>(st.rt[(U + 1) % 3], st.rt[U3]);
+        copy_row<K>(st.m[(U + 1) % 3], st.m[U3]);
+    }
+}
+
+template <int K, bool RGB, bool DIFF, int... U>
+__device__ __forceinline__ void row_block(RowState<K, RGB>& st, const RowCtx& c, const SegParams& p, int jb, int n,
+                                          std::integer_sequence<int, U...>)
+{
+    ((jb + U < n ? row_step<K, RGB, DIFF, U>(st, c, p, jb + U) : void()), ...);
+}
+
+template <int K, bool RGB, bool DIFF>
+__global__ __launch_bounds__(ROW_WAVES * 64) void k_rowfuse(RowParams rp)
+{
+    extern __shared__ uint8_t row_lds[];
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wavefront-uniform
+    const int item = blockIdx.x * ROW_WAVES + wave;
+    if (item >= rp.total) return;  // whole wavefront leaves; no barrier is used
+    const SegParams& p = rp.sp;
+    const int strip = item % rp.nstrips;
+    const int rest = item / rp.nstrips;
+    const int band = rest % rp.nbands;
+    const int chunk = rest / rp.nbands;
+
+    RowCtx c;
+    c.W = p.W;
+    c.Hf = p.H;
+    c.lane = threadIdx.x & 63;
+    const int S = rp.strip_step;
+    c.x0 = min(strip * S, p.W - 64 * K);
+    const int vx0 = strip == 0 ? 0 : (strip - 1) * S + 64 * K - ROW_HX;
+    const int vx1 = strip == rp.nstrips - 1 ? p.W : strip * S + 64 * K - ROW_HX;
+    c.valid = 0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int x = c.x0 + K * c.lane + k;
+        c.valid |= (x >= vx0 && x < vx1 ? 1u : 0u) << k;
+    }
+    c.y0 = band * rp.band_h;
+    c.y1 = min(c.y0 + rp.band_h, p.H);
+    c.lo_in = max(0, c.y0 - 6);
+    c.hi_in = min(p.H, c.y1 + 6);
+    c.lo_g = max(0, c.y0 - 4);
+    c.hi_g = min(p.H, c.y1 + 4);
+    c.lo_s = max(0, c.y0 - 3);
+    c.hi_s = min(p.H, c.y1 + 3);
+    c.lo_b = max(0, c.y0 - 1);
+    c.hi_b = min(p.H, c.y1 + 1);
+    c.prev = row_lds + wave * rp.band_h * 64;
+
+    const int t0 = chunk * rp.tt;
+    const int t1 = min(t0 + rp.tt, p.T);
+    const int ts = (DIFF && t0 > 0) ? t0 - 1 : t0;
+    constexpr int C = RGB ? 3 : 1;
+    const size_t plane = (size_t)p.W * p.H;
+    const int n = c.y1 - c.y0 + 2 * ROW_HX;
+    for (int t = ts; t < t1; ++t) {
+        c.t = t;
+        c.real = t >= t0;
+        c.in_frame = (const uint8_t*)p.in + (size_t)t * plane * C;
+        c.out_frame = (uint8_t*)p.out + (size_t)t * plane;
+        RowState<K, RGB> st;
+        // first two input rows
+        const int r0 = c.y0 - ROW_HX;
+        if (r0 >= c.lo_in && r0 < c.hi_in) load_raw<K, RGB>(c, r0, st.raw[0]);
+        if (r0 + 1 >= c.lo_in && r0 + 1 < c.hi_in) load_raw<K, RGB>(c, r0 + 1, st.raw[1]);
+        for (int jb = 0; jb < n; jb += ROW_UNROLL)
+            row_block<K, RGB, DIFF>(st, c, p, jb, n, std::make_integer_sequence<int, ROW_UNROLL>{});
+    }
+}
+
+hipError_t launch_rowfuse(const RowParams& rp, int K, bool rgb, bool diff, hipStream_t s);
+
+}  // namespace fz

@@ -1,0 +1,72 @@
+// Geometry of the row-marching kernel, shared by the planner and the launcher.
+#pragma once
+
+#include "fz_ops.h"
+
+namespace fz {
+
+constexpr int ROW_HX = 6;     // horizontal and vertical halo of the chain: 2 + 1 + 2 + 1
+constexpr int ROW_WAVES = 4;  // independent wavefronts per workgroup
+constexpr int ROW_TARGET_ITEMS = 4096;  // enough wavefronts to fill 256 CUs several times
+
+// Groups the row kernel implements: gray conversion or Gaussian first, suppression
+// or frame difference last, of the Harris chain.
+inline bool row_group(int ch, int A, int B) { return ch == CHAIN_HARRIS && (A == 0 || A == 1) && (B == 7 || B == 8); }
+
+// Strips of 64*K columns that overlap by 2*ROW_HX cover a frame of width W.
+inline int row_strips(int W, int K)
+{
+    const int span = 64 * K, S = span - 2 * ROW_HX;
+    if (W < span) return 0;
+    return 1 + (W - span + S - 1) / S;
+}
+
+// Columns per lane (2 or 3) that compute the fewest columns in total; 0 if the
+// frame is narrower than 128 columns.
+inline int row_strips_best(int W)
+{
+    const int n2 = row_strips(W, 2), n3 = row_strips(W, 3);
+    if (n2 == 0) return 0;
+    if (n3 > 0 && n3 * 192 < n2 * 128) return 3;
+    return 2;
+}
+
+inline int row_lds_bytes(int band_h) { return ROW_WAVES * band_h * 64; }
+
+// Rows per band and frames per work item.  A work item marches band_h + 2*HX
+// rows per frame over tt frames (plus the frame before them when the group
+// ends in the frame difference); items run in rounds of ROW_TARGET_ITEMS
+// wavefronts.  Pick the pair with the least (rounds x item length); explicit
+// requests (> 0) are kept.
+struct RowShape {
+    int band_h, tt;
+};
+inline RowShape row_shape(int H, int T, int nstrips, bool diff, int req_h, int req_tt)
+{
+    RowShape best{H, 1};
+    double best_cost = -1.0;
+    const int tts[] = {1, 2, 4, 8, 16, 32, 64};
+    for (int tt : tts) {
+        if (req_tt > 0 && tt != 1) break;
+        const int t = req_tt > 0 ? req_tt : tt;
+        if (!diff && t != 1 && req_tt <= 0) continue;
+        if (t > T && t != 1) continue;
+        for (int nb = 1; nb <= H; ++nb) {
+            int bh = req_h > 0 ? req_h : (H + nb - 1) / nb;
+            if (diff && bh > 256) continue;
+            if (bh < 16 && req_h <= 0 && nb > 1) break;
+            const long long items = (long long)nstrips * ((H + bh - 1) / bh) * ((T + t - 1) / t);
+            const long long rounds = (items + ROW_TARGET_ITEMS - 1) / ROW_TARGET_ITEMS;
+            const double cost = (double)rounds * (bh + 2 * ROW_HX) * (t + (diff ? 1 : 0));
+            if (best_cost < 0 || cost < best_cost) {
+                best_cost = cost;
+                best = RowShape{bh, t};
+            }
+            if (req_h > 0) break;
+        }
+    }
+    if (best.band_h > H) best.band_h = H;
+    return best;
+}
+
+}  // namespace fz

@@ -7,6 +7,7 @@
 #include <string>
 
 #include "fz_internal.h"
+#include "rowfuse.h"
 #include "tables.h"
 
 namespace fz {
@@ -62,9 +63,23 @@ fz_status run_plan(const fz_plan& p, const void* d_in, void* d_out, fz_point* d_
         bool group_has_nms = false;
         for (int j = g.first; j <= g.last; ++j) group_has_nms |= p.stages[j].op == FZ_OP_NMS3;
         if (!group_has_nms) sp.count = nullptr;
-        LaunchFn fn = lookup(p.chain, g.cfirst, g.clast);
-        if (!fn) return fail(FZ_E_UNSUPPORTED, "no kernel compiled for this group");
-        hipError_t e = fn(sp, g.tile, s);
+        hipError_t e;
+        if (g.engine == FZ_ENGINE_ROW) {
+            RowParams rp{};
+            rp.sp = sp;
+            rp.nstrips = g.nstrips;
+            rp.nbands = g.nbands;
+            rp.nchunks = g.nchunks;
+            rp.total = g.nstrips * g.nbands * g.nchunks;
+            rp.strip_step = 64 * g.row_k - 2 * ROW_HX;
+            rp.band_h = g.tile_h;
+            rp.tt = g.tpb;
+            e = launch_rowfuse(rp, g.row_k, g.cfirst == 0, g.clast == 8, s);
+        } else {
+            LaunchFn fn = lookup(p.chain, g.cfirst, g.clast);
+            if (!fn) return fail(FZ_E_UNSUPPORTED, "no kernel compiled for this group");
+            e = fn(sp, g.tile, s);
+        }
         if (e != hipSuccess)
             return fail(FZ_E_HIP, "launching group " + std::to_string(g.first) + ".." + std::to_string(g.last) +
                                       ": " + hipGetErrorString(e));

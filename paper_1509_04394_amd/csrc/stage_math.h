@@ -31,18 +31,22 @@ __device__ __forceinline__ float gauss5_taps(const Gauss5W& w, float m2, float m
     return __builtin_fmaf(w.w0, c, acc);
 }
 
-// Unnormalised Sobel from the 3x3 neighbourhood g[row][col] (row = y-1..y+1).
-// Ix: column difference smoothed (1,2,1) over rows; Iy: the transpose.
+// Unnormalised Sobel, evaluated column first.  Per column x:
+//   sv(x) = 2 G(y,x) + (G(y-1,x) + G(y+1,x))      (vertical 1-2-1 smoothing)
+//   e(x)  = G(y+1,x) - G(y-1,x)                    (vertical difference)
+// then Ix = sv(x+1) - sv(x-1) and Iy = 2 e(x) + (e(x-1) + e(x+1)).
+__device__ __forceinline__ float sobel_sv(float gm, float g0, float gp) { return __builtin_fmaf(2.0f, g0, gm + gp); }
+__device__ __forceinline__ float sobel_e(float gm, float gp) { return gp - gm; }
+__device__ __forceinline__ float sobel_ix(float sv_left, float sv_right) { return sv_right - sv_left; }
+__device__ __forceinline__ float sobel_iy(float e_left, float e0, float e_right)
+{
+    return __builtin_fmaf(2.0f, e0, e_left + e_right);
+}
+// The same from a 3x3 window g[row][col] (rows y-1..y+1, columns x-1..x+1).
 __device__ __forceinline__ void sobel3(const float g[3][3], float& ix, float& iy)
 {
-    float dm = g[0][2] - g[0][0];
-    float d0 = g[1][2] - g[1][0];
-    float dp = g[2][2] - g[2][0];
-    ix = __builtin_fmaf(2.0f, d0, dm + dp);
-    float em = g[2][0] - g[0][0];
-    float e0 = g[2][1] - g[0][1];
-    float ep = g[2][2] - g[0][2];
-    iy = __builtin_fmaf(2.0f, e0, em + ep);
+    ix = sobel_ix(sobel_sv(g[0][0], g[1][0], g[2][0]), sobel_sv(g[0][2], g[1][2], g[2][2]));
+    iy = sobel_iy(sobel_e(g[0][0], g[2][0]), sobel_e(g[0][1], g[2][1]), sobel_e(g[0][2], g[2][2]));
 }
 
 __device__ __forceinline__ float gradmag(float ix, float iy)

@@ -22,6 +22,8 @@ FZ_U8, FZ_F32 = 1, 2
 FZ_DEP_TT, FZ_DEP_TMT, FZ_DEP_KK = 0, 1, 2
 FZ_PART_OPTIMAL, FZ_PART_UNFUSED, FZ_PART_EXPLICIT = 0, 1, 2
 FZ_COST_ANALYTIC, FZ_COST_LEARNED, FZ_COST_MEASURED = 0, 1, 2
+FZ_ENGINE_AUTO, FZ_ENGINE_TILE, FZ_ENGINE_ROW, FZ_ENGINE_STREAM = 0, 1, 2, 3
+ENGINES = {"auto": FZ_ENGINE_AUTO, "tile": FZ_ENGINE_TILE, "row": FZ_ENGINE_ROW}
 
 OPS = {
     "rgb2gray": 1, "gauss5": 2, "sobel3": 3, "gradmag": 4, "products": 5,
@@ -54,14 +56,15 @@ class fz_plan_opts(ctypes.Structure):
     _fields_ = [("width", ctypes.c_int32), ("height", ctypes.c_int32), ("frames", ctypes.c_int32),
                 ("lds_budget_bytes", ctypes.c_int32), ("partition", ctypes.c_int32), ("n_cuts", ctypes.c_int32),
                 ("cuts", ctypes.POINTER(ctypes.c_int32)), ("cost_model", ctypes.c_int32),
-                ("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32), ("frames_per_block", ctypes.c_int32)]
+                ("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32), ("frames_per_block", ctypes.c_int32),
+                ("engine", ctypes.c_int32)]
 
 
 class fz_segment_info(ctypes.Structure):
     _fields_ = [("first", ctypes.c_int32), ("last", ctypes.c_int32), ("tile_w", ctypes.c_int32),
                 ("tile_h", ctypes.c_int32), ("frames_per_block", ctypes.c_int32), ("halo", ctypes.c_int32),
                 ("halo_t", ctypes.c_int32), ("lds_bytes", ctypes.c_int32), ("streaming", ctypes.c_int32),
-                ("bytes_per_px", ctypes.c_double), ("cost", ctypes.c_double)]
+                ("engine", ctypes.c_int32), ("bytes_per_px", ctypes.c_double), ("cost", ctypes.c_double)]
 
 
 _lib = None
@@ -188,7 +191,8 @@ def fz_run_chain(plan, d_in, d_out, d_points, d_point_count, point_capacity, d_w
 
 
 # ---------------------------------------------------------------- convenience wrapper
-def make_opts(W, H, T, partition="optimal", lds_budget=0, tile=None, frames_per_block=0, cost_model="analytic"):
+def make_opts(W, H, T, partition="optimal", lds_budget=0, tile=None, frames_per_block=0, cost_model="analytic",
+              engine="auto", band_h=0):
     o = fz_plan_opts()
     o.width, o.height, o.frames = int(W), int(H), int(T)
     o.lds_budget_bytes = int(lds_budget)
@@ -207,6 +211,9 @@ def make_opts(W, H, T, partition="optimal", lds_budget=0, tile=None, frames_per_
     if tile is not None:
         o.tile_w, o.tile_h = int(tile[0]), int(tile[1])
     o.frames_per_block = int(frames_per_block)
+    o.engine = ENGINES[engine]
+    if band_h:
+        o.tile_h = int(band_h)  # row engine: rows per band (tile_w stays 0)
     return o
 
 
@@ -219,7 +226,7 @@ class Plan:
     """
 
     def __init__(self, ops, W, H, T, partition="optimal", lds_budget=0, tile=None, frames_per_block=0,
-                 params=None, deps=None):
+                 params=None, deps=None, engine="auto", band_h=0):
         self.ops = list(ops)
         self.W, self.H, self.T = int(W), int(H), int(T)
         stages = []
@@ -231,7 +238,7 @@ class Plan:
                 s.dep = int(deps[i])
             stages.append(s)
         self.stages = stages
-        self.opts = make_opts(W, H, T, partition, lds_budget, tile, frames_per_block)
+        self.opts = make_opts(W, H, T, partition, lds_budget, tile, frames_per_block, engine=engine, band_h=band_h)
         self.handle = fz_plan_chain(stages, self.opts)
         self._ws = None
 

@@ -286,3 +286,38 @@ def test_rgb_config_full_size_sampled(dev):
         nex, _, _ = check_full_chain(ops, sub, gsub if t0 == t else np.stack([o[0, 0].astype(np.uint8), gsub[1]]),
                                      gps, o, op_)
         say("frame", t, "exempt", nex)
+
+
+# ---------------------------------------------------------------- row-marching engine
+ROW_SHAPES = [(128, 9, 3), (150, 70, 5), (192, 100, 4), (257, 33, 6), (300, 40, 3), (800, 64, 3)]
+
+
+@pytest.mark.parametrize("shape", ROW_SHAPES, ids=lambda s: "x".join(map(str, s)))
+def test_row_engine_equals_tile_engine(dev, shape):
+    """The row-marching kernel computes the same bytes and points as the LDS
+    tile engine for every group it implements, whatever the band height and
+    frames per work item."""
+    W, H, T = shape
+    rgb = synth.video(W, H, T, seed=W + H, rgb=True)
+    gray = synth.video(W, H, T, seed=W + H + 1)
+    key = lambda p: sorted(map(tuple, p.tolist()))
+    for ops, vol in [(fz.RGB_HARRIS_CHAIN, rgb), (fz.RGB_HARRIS_CHAIN[:8], rgb),
+                     (fz.HARRIS_CHAIN, gray), (fz.HARRIS_CHAIN[:7], gray)]:
+        ref, refp, _ = run_gpu(ops, vol, dev, engine="tile")
+        for band_h, tpb in [(0, 0), (8, 1), (17, 2), (H, T), (H // 2 + 1, 3)]:
+            say("row engine", shape, len(ops), band_h, tpb)
+            g, gp, plan = run_gpu(ops, vol, dev, engine="row", band_h=band_h, frames_per_block=tpb)
+            assert plan.segment_info()[0].engine == fz.FZ_ENGINE_ROW
+            assert np.array_equal(g, ref), (ops[-1], band_h, tpb)
+            assert key(gp) == key(refp), (ops[-1], band_h, tpb)
+
+
+def test_row_engine_vs_oracle(dev):
+    ops = fz.RGB_HARRIS_CHAIN
+    rgb = synth.video(300, 120, 7, seed=40, rgb=True)
+    g, gp, plan = run_gpu(ops, rgb, dev, engine="row")
+    assert plan.segment_info()[0].engine == fz.FZ_ENGINE_ROW
+    o, op_ = oracle_run(ops, rgb)
+    nex, ng, no = check_full_chain(ops, rgb, g, gp, o, op_)
+    say("row vs oracle exempt", nex, "points", ng, no)
+    assert no > 0
