@@ -40,17 +40,33 @@ struct RowParams {
     int tt;          // frames per work item
 };
 
+// Value of the lane to the left (wave_shr:1) / right (wave_shl:1).  At a
+// frame edge (EDGE) the edge lane keeps `edge`, its own edge column: the
+// replicate border.  Inside the frame the edge lane is a halo lane whose value
+// is never used, so it may read zero, which lets the compiler fold the shift
+// into the instruction that consumes it.
+template <bool EDGE>
 __device__ __forceinline__ float dpp_from_left(float v, float edge)
 {
-    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(edge), __float_as_int(v), 0x138, 0xf, 0xf, false));
+    if constexpr (EDGE)
+        return __int_as_float(
+            __builtin_amdgcn_update_dpp(__float_as_int(edge), __float_as_int(v), 0x138, 0xf, 0xf, false));
+    else
+        return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x138, 0xf, 0xf, true));
 }
+template <bool EDGE>
 __device__ __forceinline__ float dpp_from_right(float v, float edge)
 {
-    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(edge), __float_as_int(v), 0x130, 0xf, 0xf, false));
+    if constexpr (EDGE)
+        return __int_as_float(
+            __builtin_amdgcn_update_dpp(__float_as_int(edge), __float_as_int(v), 0x130, 0xf, 0xf, false));
+    else
+        return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x130, 0xf, 0xf, true));
 }
 
 // e[0 .. K+2R) = this lane's columns x-R .. x+K-1+R of a row held K per lane.
-template <int K, int R>
+// EL / ER: the strip's first / last column is the frame's.
+template <int K, int R, bool EL, bool ER>
 __device__ __forceinline__ void extend_row(const float (&v)[K], float (&e)[K + 2 * R])
 {
     static_assert(R <= K, "neighbour lanes must hold the halo");
@@ -58,8 +74,8 @@ __device__ __forceinline__ void extend_row(const float (&v)[K], float (&e)[K + 2
     for (int k = 0; k < K; ++k) e[R + k] = v[k];
 #pragma unroll
     for (int i = 1; i <= R; ++i) {
-        e[R - i] = dpp_from_left(v[K - i], v[0]);
-        e[R + K - 1 + i] = dpp_from_right(v[i - 1], v[K - 1]);
+        e[R - i] = dpp_from_left<EL>(v[K - i], v[0]);
+        e[R + K - 1 + i] = dpp_from_right<ER>(v[i - 1], v[K - 1]);
     }
 }
 
@@ -85,6 +101,8 @@ struct RowCtx {
     const uint8_t* in_frame;  // frame t of the input
     uint8_t* out_frame;       // frame t of the output
     int W, Hf, x0, lane, y0, y1, t;
+    int row_bytes;            // bytes per input row
+    int lane_in, lane_out;    // byte offset of this lane's first column in an input / output row
     bool real;
     uint32_t valid;           // bit k: column k of this lane is an output column of the strip
     int lo_in, hi_in, lo_g, hi_g, lo_s, hi_s, lo_b, hi_b;
@@ -95,12 +113,13 @@ template <int K, bool RGB>
 __device__ __forceinline__ void load_raw(const RowCtx& c, int row, uint32_t (&raw)[RowState<K, RGB>::NRAW])
 {
     constexpr int C = RGB ? 3 : 1;
-    const uint8_t* p = c.in_frame + ((size_t)row * c.W + c.x0 + K * c.lane) * C;
+    // wavefront-uniform row base (scalar registers) plus a 32-bit per-lane offset
+    const uint8_t* rowp = c.in_frame + (size_t)row * c.row_bytes;
 #pragma unroll
-    for (int i = 0; i < K * C; ++i) raw[i] = p[i];
+    for (int i = 0; i < K * C; ++i) raw[i] = rowp[c.lane_in + i];
 }
 
-template <int K, bool RGB, bool DIFF, int U>
+template <int K, bool RGB, bool DIFF, bool EL, bool ER, int U>
 __device__ __forceinline__ void row_step(RowState<K, RGB>& st, const RowCtx& c, const SegParams& p, int j)
 {
     constexpr int U3 = U % 3, U5 = U % 5;
@@ -122,7 +141,7 @@ __device__ __forceinline__ void row_step(RowState<K, RGB>& st, const RowCtx& c, 
                 gr[k] = (float)st.raw[U3][k];
         }
         float e[K + 4];
-        extend_row<K, 2>(gr, e);
+        extend_row<K, 2, EL, ER>(gr, e);
 #pragma unroll
         for (int k = 0; k < K; ++k) st.h[U5][k] = gauss5_taps(p.gw, e[k], e[k + 1], e[k + 2], e[k + 3], e[k + 4]);
         if (row_in == 0) {
@@ -150,8 +169,8 @@ __device__ __forceinline__ void row_step(RowState<K, RGB>& st, const RowCtx& c, 
             ev[k] = sobel_e(gm, gp);
         }
         float esv[K + 2], eev[K + 2];
-        extend_row<K, 1>(sv, esv);
-        extend_row<K, 1>(ev, eev);
+        extend_row<K, 1, EL, ER>(sv, esv);
+        extend_row<K, 1, EL, ER>(ev, eev);
         float pr[3][K];
 #pragma unroll
         for (int k = 0; k < K; ++k) {
@@ -162,7 +181,7 @@ __device__ __forceinline__ void row_step(RowState<K, RGB>& st, const RowCtx& c, 
 #pragma unroll
         for (int ch = 0; ch < 3; ++ch) {
             float e[K + 4];
-            extend_row<K, 2>(pr[ch], e);
+            extend_row<K, 2, EL, ER>(pr[ch], e);
 #pragma unroll
             for (int k = 0; k < K; ++k) st.b[U5][ch][k] = sum5(e[k], e[k + 1], e[k + 2], e[k + 3], e[k + 4]);
         }
@@ -187,7 +206,7 @@ __device__ __forceinline__ void row_step(RowState<K, RGB>& st, const RowCtx& c, 
 #pragma unroll
         for (int k = 0; k < K; ++k) st.rt[U3][k] = threshold(harris(s[0][k], s[1][k], s[2][k], p.k), p.thr);
         float e[K + 2];
-        extend_row<K, 1>(st.rt[U3], e);
+        extend_row<K, 1, EL, ER>(st.rt[U3], e);
 #pragma unroll
         for (int k = 0; k < K; ++k) st.m[U3][k] = max3(e[k], e[k + 1], e[k + 2]);
         if (rb == 0) {
@@ -206,12 +225,12 @@ __device__ __forceinline__ void row_step(RowState<K, RGB>& st, const RowCtx& c, 
             centre[k] = st.rt[(U + 2) % 3][k];
             bits |= (nms_keep(centre[k], wmax) != 0u ? 1u : 0u) << k;
         }
-        if (p.count != nullptr) {
+        const uint32_t pts = bits & c.valid;
+        if (p.count != nullptr && c.real && __ballot(pts != 0u) != 0ull) {
 #pragma unroll
-            for (int k = 0; k < K; ++k) {
-                const bool is_pt = c.real && ((bits & c.valid) >> k & 1u);
-                emit_points(p, is_pt, (uint32_t)c.t, (uint32_t)rn, (uint32_t)(c.x0 + K * c.lane + k), centre[k]);
-            }
+            for (int k = 0; k < K; ++k)
+                emit_points(p, (pts >> k & 1u) != 0u, (uint32_t)c.t, (uint32_t)rn, (uint32_t)(c.x0 + K * c.lane + k),
+                            centre[k]);
         }
         uint32_t outbits = bits;
         if constexpr (DIFF) {
@@ -221,10 +240,10 @@ __device__ __forceinline__ void row_step(RowState<K, RGB>& st, const RowCtx& c, 
             outbits = bits ^ prev;
         }
         if (c.real) {
-            uint8_t* o = c.out_frame + (size_t)rn * c.W + c.x0 + K * c.lane;
+            uint8_t* o = c.out_frame + (size_t)rn * c.W;
 #pragma unroll
             for (int k = 0; k < K; ++k)
-                if (c.valid >> k & 1u) o[k] = (outbits >> k & 1u) ? (uint8_t)255 : (uint8_t)0;
+                if (c.valid >> k & 1u) o[c.lane_out + k] = (outbits >> k & 1u) ? (uint8_t)255 : (uint8_t)0;
         }
     }
     // bottom replicate: after the last frame row, copy it into the next slot of
@@ -241,11 +260,33 @@ __device__ __forceinline__ void row_step(RowState<K, RGB>& st, const RowCtx& c, 
     }
 }
 
-template <int K, bool RGB, bool DIFF, int... U>
+template <int K, bool RGB, bool DIFF, bool EL, bool ER, int... U>
 __device__ __forceinline__ void row_block(RowState<K, RGB>& st, const RowCtx& c, const SegParams& p, int jb, int n,
                                           std::integer_sequence<int, U...>)
 {
-    ((jb + U < n ? row_step<K, RGB, DIFF, U>(st, c, p, jb + U) : void()), ...);
+    ((jb + U < n ? row_step<K, RGB, DIFF, EL, ER, U>(st, c, p, jb + U) : void()), ...);
+}
+
+// All frames of one work item.
+template <int K, bool RGB, bool DIFF, bool EL, bool ER>
+__device__ __forceinline__ void row_frames(RowCtx& c, const SegParams& p, int ts, int t0, int t1)
+{
+    constexpr int C = RGB ? 3 : 1;
+    const size_t plane = (size_t)p.W * p.H;
+    const int n = c.y1 - c.y0 + 2 * ROW_HX;
+    for (int t = ts; t < t1; ++t) {
+        c.t = t;
+        c.real = t >= t0;
+        c.in_frame = (const uint8_t*)p.in + (size_t)t * plane * C;
+        c.out_frame = (uint8_t*)p.out + (size_t)t * plane;
+        RowState<K, RGB> st;
+        // first two input rows
+        const int r0 = c.y0 - ROW_HX;
+        if (r0 >= c.lo_in && r0 < c.hi_in) load_raw<K, RGB>(c, r0, st.raw[0]);
+        if (r0 + 1 >= c.lo_in && r0 + 1 < c.hi_in) load_raw<K, RGB>(c, r0 + 1, st.raw[1]);
+        for (int jb = 0; jb < n; jb += ROW_UNROLL)
+            row_block<K, RGB, DIFF, EL, ER>(st, c, p, jb, n, std::make_integer_sequence<int, ROW_UNROLL>{});
+    }
 }
 
 template <int K, bool RGB, bool DIFF>
@@ -256,8 +297,11 @@ __global__ __launch_bounds__(ROW_WAVES * 64) void k_rowfuse(RowParams rp)
     const int item = blockIdx.x * ROW_WAVES + wave;
     if (item >= rp.total) return;  // whole wavefront leaves; no barrier is used
     const SegParams& p = rp.sp;
-    const int strip = item % rp.nstrips;
-    const int rest = item / rp.nstrips;
+    // strip-major order: neighbouring wavefronts run the same strip (same code
+    // variant, shared halo rows in L2)
+    const int per_strip = rp.nbands * rp.nchunks;
+    const int strip = item / per_strip;
+    const int rest = item - strip * per_strip;
     const int band = rest % rp.nbands;
     const int chunk = rest / rp.nbands;
 
@@ -267,6 +311,10 @@ __global__ __launch_bounds__(ROW_WAVES * 64) void k_rowfuse(RowParams rp)
     c.lane = threadIdx.x & 63;
     const int S = rp.strip_step;
     c.x0 = min(strip * S, p.W - 64 * K);
+    constexpr int CIN = RGB ? 3 : 1;
+    c.row_bytes = p.W * CIN;
+    c.lane_in = (c.x0 + K * c.lane) * CIN;
+    c.lane_out = c.x0 + K * c.lane;
     const int vx0 = strip == 0 ? 0 : (strip - 1) * S + 64 * K - ROW_HX;
     const int vx1 = strip == rp.nstrips - 1 ? p.W : strip * S + 64 * K - ROW_HX;
     c.valid = 0;
@@ -290,22 +338,15 @@ __global__ __launch_bounds__(ROW_WAVES * 64) void k_rowfuse(RowParams rp)
     const int t0 = chunk * rp.tt;
     const int t1 = min(t0 + rp.tt, p.T);
     const int ts = (DIFF && t0 > 0) ? t0 - 1 : t0;
-    constexpr int C = RGB ? 3 : 1;
-    const size_t plane = (size_t)p.W * p.H;
-    const int n = c.y1 - c.y0 + 2 * ROW_HX;
-    for (int t = ts; t < t1; ++t) {
-        c.t = t;
-        c.real = t >= t0;
-        c.in_frame = (const uint8_t*)p.in + (size_t)t * plane * C;
-        c.out_frame = (uint8_t*)p.out + (size_t)t * plane;
-        RowState<K, RGB> st;
-        // first two input rows
-        const int r0 = c.y0 - ROW_HX;
-        if (r0 >= c.lo_in && r0 < c.hi_in) load_raw<K, RGB>(c, r0, st.raw[0]);
-        if (r0 + 1 >= c.lo_in && r0 + 1 < c.hi_in) load_raw<K, RGB>(c, r0 + 1, st.raw[1]);
-        for (int jb = 0; jb < n; jb += ROW_UNROLL)
-            row_block<K, RGB, DIFF>(st, c, p, jb, n, std::make_integer_sequence<int, ROW_UNROLL>{});
-    }
+    const bool el = strip == 0, er = strip == rp.nstrips - 1;
+    if (el && er)
+        row_frames<K, RGB, DIFF, true, true>(c, p, ts, t0, t1);
+    else if (el)
+        row_frames<K, RGB, DIFF, true, false>(c, p, ts, t0, t1);
+    else if (er)
+        row_frames<K, RGB, DIFF, false, true>(c, p, ts, t0, t1);
+    else
+        row_frames<K, RGB, DIFF, false, false>(c, p, ts, t0, t1);
 }
 
 hipError_t launch_rowfuse(const RowParams& rp, int K, bool rgb, bool diff, hipStream_t s);
