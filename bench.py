@@ -39,6 +39,21 @@ WORKLOADS = {
 }
 METRIC = "Mpixel/s fused vs unfused and HBM GB/s (% of peak), 800×600×1000 chain"
 
+# HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE
+# passes, scaled by the plain-copy calibration (profiles/rowfuse_rgb800_counters.md).
+# Valid only for the kernel sources they were taken with: the key is a hash of them.
+COUNTER_TRAFFIC = {
+    ("rgb800", "05ed9308c8df6db4"): {"fetch_bytes": 2.645e9, "write_bytes": 0.598e9,
+                                     "source": "profiles/rowfuse_rgb800_counters.md"},
+}
+KERNEL_SOURCES = ["rowfuse.h", "rowgeom.h", "stage_math.h"]
+
+
+def kernel_source_hash():
+    import hashlib
+    d = os.path.join(ROOT, "paper_1509_04394_amd", "csrc")
+    return hashlib.sha256(b"".join(open(os.path.join(d, f), "rb").read() for f in KERNEL_SOURCES)).hexdigest()[:16]
+
 
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
@@ -180,8 +195,14 @@ def main():
     opx = ops_per_px(ops[dominant.first:dominant.last + 1])
     achieved_gops = npx * opx / (f_mean * 1e-3) / 1e9
     achieved_gbs = alg_bytes / (f_mean * 1e-3) / 1e9
+    traffic = None
+    ct = COUNTER_TRAFFIC.get((args.workload, kernel_source_hash()))
+    if ct is not None and dominant.engine == fz.FZ_ENGINE_ROW:
+        # measured HBM bytes per launch over this run's launch time, GB/s
+        traffic = round((ct["fetch_bytes"] + ct["write_bytes"]) / (f_mean * 1e-3) / 1e9, 1)
     roof = {"bound": "alu", "achieved": round(achieved_gops, 1), "peak": VALU_PEAK_GOPS, "unit": "Gop/s",
-            "frac": round(achieved_gops / VALU_PEAK_GOPS, 4), "traffic": None,
+            "frac": round(achieved_gops / VALU_PEAK_GOPS, 4), "traffic": traffic,
+            "traffic_unit": "GB/s (counter bytes per launch / launch time)",
             "ops_per_px": opx, "hbm_achieved_GBs": round(achieved_gbs, 1),
             "hbm_frac": round(achieved_gbs / HBM_PEAK_GBS, 4)}
     rec = {"metric": METRIC, "value": round(value, 1), "unit": "Mpixel/s", "n_gpus": 1, "steps": args.steps,
