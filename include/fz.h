@@ -100,10 +100,15 @@ typedef struct fz_plan_opts {
     int32_t n_cuts;                 /* FZ_PART_EXPLICIT: number of entries in cuts */
     const int32_t* cuts;            /* FZ_PART_EXPLICIT: last stage index of every group but the final,
                                        strictly increasing, each in [0, n-2] */
-    int32_t cost_model;             /* FZ_COST_*; only FZ_COST_ANALYTIC is implemented */
+    int32_t cost_model;             /* FZ_COST_ANALYTIC (bytes) or FZ_COST_LEARNED (predicted microseconds);
+                                       FZ_COST_MEASURED is not implemented in the library */
     int32_t tile_w, tile_h;         /* output box of one workgroup; 0 = planner's choice */
     int32_t frames_per_block;       /* frames one workgroup marches through; 0 = planner's choice */
     int32_t engine;                 /* FZ_ENGINE_*: kernel family for groups that have a choice */
+    const float* cost_weights;      /* FZ_COST_LEARNED: host copy of the trained cost network's parameters
+                                       (fz_mlp_param_count(fz_cost_n_features()) floats, layout of
+                                       fz_mlp_forward); read during fz_plan_chain only */
+    int32_t cost_n_features;        /* FZ_COST_LEARNED: must equal fz_cost_n_features() */
 } fz_plan_opts;
 
 /* Kernel families.  TILE: a workgroup loads its halo box into LDS and runs the
@@ -180,8 +185,69 @@ fz_status fz_run_chain(const fz_plan* plan, const void* d_in, void* d_out, fz_po
                        uint32_t* d_point_count, uint32_t point_capacity, void* d_workspace,
                        size_t ws_bytes, void* stream);
 
+/* One clip of a batch: its own input, output, size and feature-point buffer. */
+typedef struct fz_clip {
+    const void* d_in;               /* input video, layout of the plan's first stage */
+    void* d_out;                    /* output video, layout of the plan's last stage */
+    int32_t width, height, frames;  /* > 0 */
+    fz_point* d_points;             /* may be NULL (then capacity must be 0) */
+    uint32_t* d_point_count;        /* may be NULL; reset by the run, counts past the capacity */
+    uint32_t point_capacity;
+} fz_clip;
+
+/* Device workspace fz_run_batch() needs for these clips. */
+size_t fz_batch_workspace_bytes(const fz_plan* plan, const fz_clip* clips, int32_t n_clips);
+
+/* Run the plan's chain and partition over n_clips clips of possibly different
+ * sizes and lengths (host array of descriptors).  Every clip's output and point
+ * set equal those of fz_run_chain on that clip alone.  When the plan is a single
+ * group the row kernel implements, all clips go through one persistent launch
+ * whose wavefronts take (clip, strip, band, frame run) work items from a queue;
+ * otherwise the clips' groups are launched clip after clip.  The launches are
+ * captured once into a HIP graph, kept in the plan and replayed while the clip
+ * descriptors and workspace pointer stay the same (they are compared on every
+ * call; a change re-captures).  A plan must not run batches on two streams at
+ * once.  n_clips in [1, 1024]. */
+fz_status fz_run_batch(fz_plan* plan, const fz_clip* clips, int32_t n_clips, void* d_workspace, size_t ws_bytes,
+                       void* stream);
+
 /* Message for the calling thread's last failed call ("" if none). */
 const char* fz_last_error(void);
+
+/* ---------------------------------------------------------------- cost model
+ * The paper prices a candidate fused kernel by its predicted execution time
+ * (Sec. VI, Fig. 5).  fz can learn that price: a 3-layer FP32 perceptron
+ * F -> 64 -> 64 -> 1 (ReLU) maps the features of a group in one kernel
+ * configuration to the natural log of its launch time in microseconds.  The
+ * network is trained on the GPU with the calls below; fz_plan_chain with
+ * FZ_COST_LEARNED evaluates it on the host for every group and kernel
+ * configuration, keeps the fastest configuration per group, and partitions on
+ * the predicted times.
+ *
+ * Parameters: one float array, row-major [out][in]:
+ *   W1[64][F] b1[64] W2[64][64] b2[64] W3[64] b3[1]. */
+
+/* Number of features of a group (the network's F). */
+int32_t fz_cost_n_features(void);
+/* Features of group i of a plan, as the learned planner computes them, into
+ * out[0..cap); returns the count, or -1 on a bad argument. */
+int32_t fz_plan_segment_features(const fz_plan* plan, int32_t i, float* out, int32_t cap);
+/* Number of parameters for F features (F in [1, 32]), else -1. */
+int32_t fz_mlp_param_count(int32_t n_features);
+/* Device workspace of fz_mlp_loss_grad for n samples. */
+size_t fz_mlp_workspace_bytes(int32_t n_features, int32_t n);
+/* d_y[n] = network(d_x[n][F]) (device pointers).  Asynchronous on stream. */
+fz_status fz_mlp_forward(const float* d_params, int32_t n_features, const float* d_x, int32_t n, float* d_y,
+                         void* stream);
+/* Loss L = mean((y - target)^2) over n samples into *d_loss and its gradient
+ * with respect to every parameter into d_grad (device pointers; reductions in
+ * a fixed order, so the result is deterministic). */
+fz_status fz_mlp_loss_grad(const float* d_params, int32_t n_features, const float* d_x, const float* d_target,
+                           int32_t n, float* d_grad, float* d_loss, void* d_ws, size_t ws_bytes, void* stream);
+/* One Adam step (bias-corrected, step >= 1) on n_params parameters in place;
+ * d_m and d_v are the caller's first and second moment buffers. */
+fz_status fz_mlp_adam_step(float* d_params, const float* d_grad, float* d_m, float* d_v, int32_t n_params,
+                           int32_t step, float lr, float beta1, float beta2, float eps, void* stream);
 
 /* Library version string. */
 const char* fz_version(void);

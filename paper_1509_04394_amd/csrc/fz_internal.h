@@ -45,6 +45,14 @@ struct fz_plan {
     double total = 0.0;
     fz::Params prm;
     bool has_nms = false;
+    // requests the plan was made with (re-pricing for other clip sizes)
+    int req_w = 0, req_h = 0, req_tpb = 0, req_engine = 0;
+    // cached batch graph (hipGraph_t / hipGraphExec_t / hipStream_t) and its key
+    void* batch_graph = nullptr;
+    void* batch_exec = nullptr;
+    void* capture_stream = nullptr;
+    std::vector<uint64_t> batch_key;
+    ~fz_plan();
 };
 
 namespace fz {
@@ -56,6 +64,13 @@ fz_status fail(fz_status code, const std::string& msg);
 // Price of group [a..b] of plan p, with its tile / frames-per-block choice.
 Segment price_group(const fz_plan& p, int a, int b, int tile_req_w, int tile_req_h, int tpb_req, int engine_req);
 
+// Learned prices (cost.cpp)
+constexpr int COST_FEATURES = 18;
+void group_features(const fz_plan& p, const Segment& g, float* f);
+double mlp_predict(const float* prm, const float* x);
+Segment price_group_learned(const fz_plan& p, int a, int b, const float* prm, int req_w, int req_h, int req_tpb,
+                            int req_engine);
+
 // Exact partition DP (Fig. 5 model) with the tie rule: fewer groups, then later cuts.
 double partition_dp(const double* cost, int n, std::vector<int>& seg_last);
 
@@ -63,5 +78,12 @@ double partition_dp(const double* cost, int n, std::vector<int>& seg_last);
 fz_status run_plan(const fz_plan& p, const void* d_in, void* d_out, fz_point* d_points, uint32_t* d_count,
                    uint32_t cap, void* d_ws, size_t ws_bytes, void* stream);
 size_t workspace_bytes(const fz_plan& p);
+
+// The same partition re-priced for another video size (batch clips).
+fz_plan* plan_for_size(const fz_plan& base, int W, int H, int T);
+// Batch (batch.hip)
+fz_status run_batch(fz_plan& p, const fz_clip* clips, int n, void* ws, size_t ws_bytes, void* stream);
+size_t batch_workspace_bytes(const fz_plan& p, const fz_clip* clips, int n);
+void release_batch(fz_plan& p);
 
 }  // namespace fz

@@ -149,7 +149,43 @@ double partition_dp(const double* cost, int n, std::vector<int>& seg_last)
     return best[n];
 }
 
+fz_plan* plan_for_size(const fz_plan& base, int W, int H, int T)
+{
+    fz_plan* p = new fz_plan();
+    p->stages = base.stages;
+    p->n = base.n;
+    p->chain = base.chain;
+    p->offset = base.offset;
+    p->W = W;
+    p->H = H;
+    p->T = T;
+    p->lds_budget = base.lds_budget;
+    p->prm = base.prm;
+    p->has_nms = base.has_nms;
+    p->req_w = base.req_w;
+    p->req_h = base.req_h;
+    p->req_tpb = base.req_tpb;
+    p->req_engine = base.req_engine;
+    p->total = 0.0;
+    for (const Segment& g : base.segs) {
+        // keep each group's kernel family and tile; band / frame run re-chosen for the size
+        const int eng = g.engine == FZ_ENGINE_TILE ? FZ_ENGINE_TILE : p->req_engine;
+        const int rw = g.engine == FZ_ENGINE_TILE ? g.tile_w : 0;
+        const int rh = g.engine == FZ_ENGINE_TILE ? g.tile_h : p->req_h;
+        Segment s = price_group(*p, g.first, g.last, rw, rh, p->req_tpb, eng);
+        if (!(s.cost < kInf)) {
+            delete p;
+            return nullptr;
+        }
+        p->total += s.cost;
+        p->segs.push_back(s);
+    }
+    return p;
+}
+
 }  // namespace fz
+
+fz_plan::~fz_plan() { fz::release_batch(*this); }
 
 using namespace fz;
 
@@ -199,8 +235,13 @@ fz_status fz_plan_chain(const fz_stage* stages, int32_t n, const fz_plan_opts* o
         return fail(FZ_E_INVALID, "fz_plan_chain: width, height and frames must be positive");
     if ((int64_t)opts->width * opts->height > (int64_t)1 << 28)
         return fail(FZ_E_INVALID, "fz_plan_chain: frame larger than 2^28 pixels");
-    if (opts->cost_model != FZ_COST_ANALYTIC)
-        return fail(FZ_E_UNSUPPORTED, "fz_plan_chain: only the analytic cost model is available here");
+    if (opts->cost_model == FZ_COST_MEASURED)
+        return fail(FZ_E_UNSUPPORTED, "fz_plan_chain: the measured cost model is not implemented in the library");
+    if (opts->cost_model != FZ_COST_ANALYTIC && opts->cost_model != FZ_COST_LEARNED)
+        return fail(FZ_E_INVALID, "fz_plan_chain: unknown cost model");
+    if (opts->cost_model == FZ_COST_LEARNED && (!opts->cost_weights || opts->cost_n_features != COST_FEATURES))
+        return fail(FZ_E_INVALID, "fz_plan_chain: the learned cost model needs weights for " +
+                                      std::to_string(COST_FEATURES) + " features");
     if (opts->frames_per_block < 0) return fail(FZ_E_INVALID, "fz_plan_chain: negative frames_per_block");
     if (opts->engine < FZ_ENGINE_AUTO || opts->engine > FZ_ENGINE_ROW)
         return fail(FZ_E_INVALID, "fz_plan_chain: unknown engine");
@@ -279,7 +320,11 @@ fz_status fz_plan_chain(const fz_stage* stages, int32_t n, const fz_plan_opts* o
     std::vector<std::vector<Segment>> segtab(n, std::vector<Segment>(n));
     for (int a = 0; a < n; ++a)
         for (int b = a; b < n; ++b) {
-            segtab[a][b] = price_group(*p, a, b, opts->tile_w, opts->tile_h, opts->frames_per_block, opts->engine);
+            segtab[a][b] = opts->cost_model == FZ_COST_LEARNED
+                               ? price_group_learned(*p, a, b, opts->cost_weights, opts->tile_w, opts->tile_h,
+                                                     opts->frames_per_block, opts->engine)
+                               : price_group(*p, a, b, opts->tile_w, opts->tile_h, opts->frames_per_block,
+                                             opts->engine);
             p->cost[(size_t)a * n + b] = segtab[a][b].cost;
         }
     std::vector<int> seg_last;
@@ -325,6 +370,10 @@ fz_status fz_plan_chain(const fz_stage* stages, int32_t n, const fz_plan_opts* o
         a = last + 1;
     }
     p->total = total;
+    p->req_w = opts->tile_w;
+    p->req_h = opts->tile_h;
+    p->req_tpb = opts->frames_per_block;
+    p->req_engine = opts->engine;
     *out = p;
     return FZ_OK;
 }
@@ -361,6 +410,18 @@ fz_status fz_plan_segment_info(const fz_plan* plan, int32_t i, fz_segment_info* 
     return FZ_OK;
 }
 
+int32_t fz_cost_n_features(void) { return COST_FEATURES; }
+
+int32_t fz_plan_segment_features(const fz_plan* plan, int32_t i, float* out, int32_t cap)
+{
+    if (!plan || !out || i < 0 || i >= (int32_t)plan->segs.size() || cap < COST_FEATURES) {
+        set_error("fz_plan_segment_features: bad argument");
+        return -1;
+    }
+    group_features(*plan, plan->segs[i], out);
+    return COST_FEATURES;
+}
+
 double fz_plan_cost(const fz_plan* plan) { return plan ? plan->total : kInf; }
 
 fz_status fz_plan_group_cost(const fz_plan* plan, int32_t a, int32_t b, double* cost)
@@ -372,6 +433,32 @@ fz_status fz_plan_group_cost(const fz_plan* plan, int32_t a, int32_t b, double* 
 }
 
 size_t fz_workspace_bytes(const fz_plan* plan) { return plan ? workspace_bytes(*plan) : 0; }
+
+size_t fz_batch_workspace_bytes(const fz_plan* plan, const fz_clip* clips, int32_t n_clips)
+{
+    if (!plan || !clips || n_clips <= 0) return 0;
+    return batch_workspace_bytes(*plan, clips, n_clips);
+}
+
+fz_status fz_run_batch(fz_plan* plan, const fz_clip* clips, int32_t n_clips, void* d_workspace, size_t ws_bytes,
+                       void* stream)
+{
+    if (!plan || !clips) return fail(FZ_E_INVALID, "fz_run_batch: null plan or clip array");
+    if (n_clips < 1 || n_clips > 1024) return fail(FZ_E_INVALID, "fz_run_batch: n_clips must be in [1, 1024]");
+    for (int i = 0; i < n_clips; ++i) {
+        const fz_clip& c = clips[i];
+        const std::string where = "fz_run_batch: clip " + std::to_string(i) + ": ";
+        if (!c.d_in || !c.d_out) return fail(FZ_E_INVALID, where + "null input or output");
+        if (c.width <= 0 || c.height <= 0 || c.frames <= 0) return fail(FZ_E_INVALID, where + "bad size");
+        if ((int64_t)c.width * c.height > (int64_t)1 << 28) return fail(FZ_E_INVALID, where + "frame too large");
+        if (c.point_capacity > 0 && !c.d_points) return fail(FZ_E_INVALID, where + "capacity without a point buffer");
+    }
+    const size_t need = batch_workspace_bytes(*plan, clips, n_clips);
+    if (need == (size_t)-1) return fail(FZ_E_LDS, "fz_run_batch: the partition does not fit some clip's size");
+    if (need > 0 && (!d_workspace || ws_bytes < need))
+        return fail(FZ_E_WORKSPACE, "fz_run_batch: workspace needs " + std::to_string(need) + " bytes");
+    return run_batch(*plan, clips, n_clips, d_workspace, ws_bytes, stream);
+}
 
 fz_status fz_run_chain(const fz_plan* plan, const void* d_in, void* d_out, fz_point* d_points, uint32_t* d_point_count,
                        uint32_t point_capacity, void* d_workspace, size_t ws_bytes, void* stream)

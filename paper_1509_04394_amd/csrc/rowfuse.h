@@ -289,42 +289,36 @@ __device__ __forceinline__ void row_frames(RowCtx& c, const SegParams& p, int ts
     }
 }
 
-template <int K, bool RGB, bool DIFF>
-__global__ __launch_bounds__(ROW_WAVES * 64) void k_rowfuse(RowParams rp)
-{
-    extern __shared__ uint8_t row_lds[];
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wavefront-uniform
-    const int item = blockIdx.x * ROW_WAVES + wave;
-    if (item >= rp.total) return;  // whole wavefront leaves; no barrier is used
-    const SegParams& p = rp.sp;
-    // strip-major order: neighbouring wavefronts run the same strip (same code
-    // variant, shared halo rows in L2)
-    const int per_strip = rp.nbands * rp.nchunks;
-    const int strip = item / per_strip;
-    const int rest = item - strip * per_strip;
-    const int band = rest % rp.nbands;
-    const int chunk = rest / rp.nbands;
+// Geometry of one work item: strip, band and frame run of one clip.
+struct RowItem {
+    int strip, band, chunk;
+    int nstrips, band_h, tt, strip_step;
+};
 
+// One work item of one wavefront (all of it wavefront-uniform).
+template <int K, bool RGB, bool DIFF>
+__device__ __forceinline__ void row_item(const SegParams& p, const RowItem& it, uint8_t* prev_lds)
+{
     RowCtx c;
     c.W = p.W;
     c.Hf = p.H;
     c.lane = threadIdx.x & 63;
-    const int S = rp.strip_step;
-    c.x0 = min(strip * S, p.W - 64 * K);
+    const int S = it.strip_step;
+    c.x0 = min(it.strip * S, p.W - 64 * K);
     constexpr int CIN = RGB ? 3 : 1;
     c.row_bytes = p.W * CIN;
     c.lane_in = (c.x0 + K * c.lane) * CIN;
     c.lane_out = c.x0 + K * c.lane;
-    const int vx0 = strip == 0 ? 0 : (strip - 1) * S + 64 * K - ROW_HX;
-    const int vx1 = strip == rp.nstrips - 1 ? p.W : strip * S + 64 * K - ROW_HX;
+    const int vx0 = it.strip == 0 ? 0 : (it.strip - 1) * S + 64 * K - ROW_HX;
+    const int vx1 = it.strip == it.nstrips - 1 ? p.W : it.strip * S + 64 * K - ROW_HX;
     c.valid = 0;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         const int x = c.x0 + K * c.lane + k;
         c.valid |= (x >= vx0 && x < vx1 ? 1u : 0u) << k;
     }
-    c.y0 = band * rp.band_h;
-    c.y1 = min(c.y0 + rp.band_h, p.H);
+    c.y0 = it.band * it.band_h;
+    c.y1 = min(c.y0 + it.band_h, p.H);
     c.lo_in = max(0, c.y0 - 6);
     c.hi_in = min(p.H, c.y1 + 6);
     c.lo_g = max(0, c.y0 - 4);
@@ -333,12 +327,12 @@ __global__ __launch_bounds__(ROW_WAVES * 64) void k_rowfuse(RowParams rp)
     c.hi_s = min(p.H, c.y1 + 3);
     c.lo_b = max(0, c.y0 - 1);
     c.hi_b = min(p.H, c.y1 + 1);
-    c.prev = row_lds + wave * rp.band_h * 64;
+    c.prev = prev_lds;
 
-    const int t0 = chunk * rp.tt;
-    const int t1 = min(t0 + rp.tt, p.T);
+    const int t0 = it.chunk * it.tt;
+    const int t1 = min(t0 + it.tt, p.T);
     const int ts = (DIFF && t0 > 0) ? t0 - 1 : t0;
-    const bool el = strip == 0, er = strip == rp.nstrips - 1;
+    const bool el = it.strip == 0, er = it.strip == it.nstrips - 1;
     if (el && er)
         row_frames<K, RGB, DIFF, true, true>(c, p, ts, t0, t1);
     else if (el)
@@ -348,6 +342,97 @@ __global__ __launch_bounds__(ROW_WAVES * 64) void k_rowfuse(RowParams rp)
     else
         row_frames<K, RGB, DIFF, false, false>(c, p, ts, t0, t1);
 }
+
+// Decompose a clip-local item index, strip-major: neighbouring wavefronts run
+// the same strip (same code variant, shared halo rows in L2).
+__device__ __forceinline__ RowItem row_decompose(int item, int nstrips, int nbands, int nchunks, int band_h, int tt,
+                                                 int strip_step)
+{
+    RowItem it;
+    const int per_strip = nbands * nchunks;
+    it.strip = item / per_strip;
+    const int rest = item - it.strip * per_strip;
+    it.band = rest % nbands;
+    it.chunk = rest / nbands;
+    it.nstrips = nstrips;
+    it.band_h = band_h;
+    it.tt = tt;
+    it.strip_step = strip_step;
+    return it;
+}
+
+template <int K, bool RGB, bool DIFF>
+__global__ __launch_bounds__(ROW_WAVES * 64) void k_rowfuse(RowParams rp)
+{
+    extern __shared__ uint8_t row_lds[];
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wavefront-uniform
+    const int item = blockIdx.x * ROW_WAVES + wave;
+    if (item >= rp.total) return;  // whole wavefront leaves; no barrier is used
+    const RowItem it = row_decompose(item, rp.nstrips, rp.nbands, rp.nchunks, rp.band_h, rp.tt, rp.strip_step);
+    row_item<K, RGB, DIFF>(rp.sp, it, row_lds + wave * rp.band_h * 64);
+}
+
+// ---------------------------------------------------------------- batches
+// Many clips of different sizes in one persistent launch: every wavefront
+// takes work items (clip, strip, band, frame run) from a queue counter until
+// none are left.  Clip descriptors travel by value in the kernel arguments.
+constexpr int FZ_BATCH_MAX = 32;
+constexpr int BATCH_BAND_H = 64;
+constexpr int BATCH_TT = 16;
+
+struct BatchClip {
+    const void* in;
+    void* out;
+    fz_point* points;
+    uint32_t* count;
+    int W, H, T;
+    uint32_t cap;
+    int nstrips, nbands, nchunks, item_begin;
+};
+
+struct BatchParams {
+    Gauss5W gw;
+    float k, thr;
+    int n_clips, total;
+    uint32_t* queue;  // work counter, zero at launch
+    BatchClip clip[FZ_BATCH_MAX];
+};
+
+template <int K, bool RGB, bool DIFF>
+__global__ __launch_bounds__(ROW_WAVES * 64) void k_rowfuse_batch(BatchParams bp)
+{
+    extern __shared__ uint8_t row_lds[];
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    for (;;) {
+        uint32_t v = 0;
+        if (lane == 0) v = atomicAdd(bp.queue, 1u);
+        const int item = __builtin_amdgcn_readfirstlane(__shfl(v, 0));
+        if (item >= bp.total) break;  // every wave ends once the queue is drained
+        int ci = 0;
+        while (ci + 1 < bp.n_clips && item >= bp.clip[ci + 1].item_begin) ++ci;
+        const BatchClip& bc = bp.clip[ci];
+        SegParams sp{};
+        sp.in = bc.in;
+        sp.out = bc.out;
+        sp.W = bc.W;
+        sp.H = bc.H;
+        sp.T = bc.T;
+        sp.tpb = BATCH_TT;
+        sp.gw = bp.gw;
+        sp.k = bp.k;
+        sp.thr = bp.thr;
+        sp.points = bc.points;
+        sp.count = bc.count;
+        sp.cap = bc.cap;
+        const RowItem it = row_decompose(item - bc.item_begin, bc.nstrips, bc.nbands, bc.nchunks, BATCH_BAND_H,
+                                         BATCH_TT, 64 * K - 2 * ROW_HX);
+        row_item<K, RGB, DIFF>(sp, it, row_lds + wave * BATCH_BAND_H * 64);
+    }
+}
+
+hipError_t launch_rowfuse_batch(const BatchParams& bp, int K, bool rgb, bool diff, int blocks, hipStream_t s);
+int rowfuse_batch_blocks_per_cu(int K, bool rgb, bool diff);
 
 hipError_t launch_rowfuse(const RowParams& rp, int K, bool rgb, bool diff, hipStream_t s);
 

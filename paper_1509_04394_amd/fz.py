@@ -57,7 +57,8 @@ class fz_plan_opts(ctypes.Structure):
                 ("lds_budget_bytes", ctypes.c_int32), ("partition", ctypes.c_int32), ("n_cuts", ctypes.c_int32),
                 ("cuts", ctypes.POINTER(ctypes.c_int32)), ("cost_model", ctypes.c_int32),
                 ("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32), ("frames_per_block", ctypes.c_int32),
-                ("engine", ctypes.c_int32)]
+                ("engine", ctypes.c_int32), ("cost_weights", ctypes.POINTER(ctypes.c_float)),
+                ("cost_n_features", ctypes.c_int32)]
 
 
 class fz_segment_info(ctypes.Structure):
@@ -65,6 +66,12 @@ class fz_segment_info(ctypes.Structure):
                 ("tile_h", ctypes.c_int32), ("frames_per_block", ctypes.c_int32), ("halo", ctypes.c_int32),
                 ("halo_t", ctypes.c_int32), ("lds_bytes", ctypes.c_int32), ("streaming", ctypes.c_int32),
                 ("engine", ctypes.c_int32), ("bytes_per_px", ctypes.c_double), ("cost", ctypes.c_double)]
+
+
+class fz_clip(ctypes.Structure):
+    _fields_ = [("d_in", ctypes.c_void_p), ("d_out", ctypes.c_void_p), ("width", ctypes.c_int32),
+                ("height", ctypes.c_int32), ("frames", ctypes.c_int32), ("d_points", ctypes.c_void_p),
+                ("d_point_count", ctypes.c_void_p), ("point_capacity", ctypes.c_uint32)]
 
 
 _lib = None
@@ -88,6 +95,22 @@ SIGNATURES = [
     ("fz_run_chain", ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                       ctypes.c_void_p, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_size_t,
                                       ctypes.c_void_p]),
+    ("fz_batch_workspace_bytes", ctypes.c_size_t, [ctypes.c_void_p, ctypes.POINTER(fz_clip), ctypes.c_int32]),
+    ("fz_run_batch", ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(fz_clip), ctypes.c_int32, ctypes.c_void_p,
+                                      ctypes.c_size_t, ctypes.c_void_p]),
+    ("fz_cost_n_features", ctypes.c_int32, []),
+    ("fz_plan_segment_features", ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_float),
+                                                  ctypes.c_int32]),
+    ("fz_mlp_param_count", ctypes.c_int32, [ctypes.c_int32]),
+    ("fz_mlp_workspace_bytes", ctypes.c_size_t, [ctypes.c_int32, ctypes.c_int32]),
+    ("fz_mlp_forward", ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int32,
+                                        ctypes.c_void_p, ctypes.c_void_p]),
+    ("fz_mlp_loss_grad", ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                                          ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                          ctypes.c_size_t, ctypes.c_void_p]),
+    ("fz_mlp_adam_step", ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                          ctypes.c_int32, ctypes.c_int32, ctypes.c_float, ctypes.c_float,
+                                          ctypes.c_float, ctypes.c_float, ctypes.c_void_p]),
     ("fz_last_error", ctypes.c_char_p, []),
     ("fz_version", ctypes.c_char_p, []),
 ]
@@ -190,9 +213,52 @@ def fz_run_chain(plan, d_in, d_out, d_points, d_point_count, point_capacity, d_w
                               stream))
 
 
+def fz_batch_workspace_bytes(plan, clips) -> int:
+    arr = (fz_clip * len(clips))(*clips)
+    return int(lib().fz_batch_workspace_bytes(plan, arr, len(clips)))
+
+
+def fz_run_batch(plan, clips, d_workspace, ws_bytes, stream):
+    arr = (fz_clip * len(clips))(*clips)
+    _check(lib().fz_run_batch(plan, arr, len(clips), d_workspace, ws_bytes, stream))
+
+
+def fz_cost_n_features() -> int:
+    return int(lib().fz_cost_n_features())
+
+
+def fz_plan_segment_features(plan, i):
+    n = fz_cost_n_features()
+    buf = (ctypes.c_float * n)()
+    r = lib().fz_plan_segment_features(plan, i, buf, n)
+    if r < 0:
+        raise FzError(FZ_E_INVALID, fz_last_error())
+    return list(buf[:r])
+
+
+def fz_mlp_param_count(n_features) -> int:
+    return int(lib().fz_mlp_param_count(n_features))
+
+
+def fz_mlp_workspace_bytes(n_features, n) -> int:
+    return int(lib().fz_mlp_workspace_bytes(n_features, n))
+
+
+def fz_mlp_forward(d_params, n_features, d_x, n, d_y, stream):
+    _check(lib().fz_mlp_forward(d_params, n_features, d_x, n, d_y, stream))
+
+
+def fz_mlp_loss_grad(d_params, n_features, d_x, d_target, n, d_grad, d_loss, d_ws, ws_bytes, stream):
+    _check(lib().fz_mlp_loss_grad(d_params, n_features, d_x, d_target, n, d_grad, d_loss, d_ws, ws_bytes, stream))
+
+
+def fz_mlp_adam_step(d_params, d_grad, d_m, d_v, n_params, step, lr, beta1, beta2, eps, stream):
+    _check(lib().fz_mlp_adam_step(d_params, d_grad, d_m, d_v, n_params, step, lr, beta1, beta2, eps, stream))
+
+
 # ---------------------------------------------------------------- convenience wrapper
 def make_opts(W, H, T, partition="optimal", lds_budget=0, tile=None, frames_per_block=0, cost_model="analytic",
-              engine="auto", band_h=0):
+              engine="auto", band_h=0, cost_weights=None):
     o = fz_plan_opts()
     o.width, o.height, o.frames = int(W), int(H), int(T)
     o.lds_budget_bytes = int(lds_budget)
@@ -212,6 +278,10 @@ def make_opts(W, H, T, partition="optimal", lds_budget=0, tile=None, frames_per_
         o.tile_w, o.tile_h = int(tile[0]), int(tile[1])
     o.frames_per_block = int(frames_per_block)
     o.engine = ENGINES[engine]
+    if cost_weights is not None:
+        o._w = (ctypes.c_float * len(cost_weights))(*[float(v) for v in cost_weights])
+        o.cost_weights = ctypes.cast(o._w, ctypes.POINTER(ctypes.c_float))
+        o.cost_n_features = fz_cost_n_features()
     if band_h:
         o.tile_h = int(band_h)  # row engine: rows per band (tile_w stays 0)
     return o
@@ -226,7 +296,7 @@ class Plan:
     """
 
     def __init__(self, ops, W, H, T, partition="optimal", lds_budget=0, tile=None, frames_per_block=0,
-                 params=None, deps=None, engine="auto", band_h=0):
+                 params=None, deps=None, engine="auto", band_h=0, cost_weights=None):
         self.ops = list(ops)
         self.W, self.H, self.T = int(W), int(H), int(T)
         stages = []
@@ -238,7 +308,9 @@ class Plan:
                 s.dep = int(deps[i])
             stages.append(s)
         self.stages = stages
-        self.opts = make_opts(W, H, T, partition, lds_budget, tile, frames_per_block, engine=engine, band_h=band_h)
+        self.opts = make_opts(W, H, T, partition, lds_budget, tile, frames_per_block,
+                              cost_model="learned" if cost_weights is not None else "analytic",
+                              engine=engine, band_h=band_h, cost_weights=cost_weights)
         self.handle = fz_plan_chain(stages, self.opts)
         self._ws = None
 
@@ -323,6 +395,32 @@ class Plan:
                      count.data_ptr() if count is not None else None, cap,
                      workspace.data_ptr(), workspace.numel(), stream)
         return out, points, count
+
+
+def make_clip(x, out, points=None, count=None, width=None, height=None, frames=None):
+    """fz_clip for device tensors x (input) and out (output); sizes from out's shape
+    unless given."""
+    c = fz_clip()
+    c.d_in = x.data_ptr()
+    c.d_out = out.data_ptr()
+    shp = out.shape[-3:]
+    c.frames, c.height, c.width = (int(frames or shp[0]), int(height or shp[1]), int(width or shp[2]))
+    c.d_points = points.data_ptr() if points is not None else None
+    c.d_point_count = count.data_ptr() if count is not None else None
+    c.point_capacity = int(points.shape[0]) if points is not None else 0
+    return c
+
+
+def run_batch(plan: "Plan", clips, workspace=None, stream=None):
+    """Run `plan` over fz_clip descriptors (device buffers owned by the caller)."""
+    import torch
+    need = fz_batch_workspace_bytes(plan.handle, clips)
+    if workspace is None:
+        workspace = torch.empty((max(need, 1),), dtype=torch.uint8, device="cuda")
+    if stream is None:
+        stream = torch.cuda.current_stream().cuda_stream
+    fz_run_batch(plan.handle, clips, workspace.data_ptr(), workspace.numel(), stream)
+    return workspace
 
 
 def points_to_numpy(points, count):

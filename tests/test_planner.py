@@ -171,3 +171,26 @@ def test_stage_describe_access_patterns():
     assert fz.fz_stage_describe("framediff").rt == 1
     with pytest.raises(fz.FzError):
         fz.fz_stage_describe(99)
+
+
+def test_batch_argument_errors_without_launch():
+    plan = fz.Plan(fz.HARRIS_CHAIN, 320, 240, 10)
+    c = fz.fz_clip()
+    c.d_in, c.d_out, c.width, c.height, c.frames = 1, 1, 320, 240, 10
+    assert fz.fz_batch_workspace_bytes(plan.handle, [c]) > 0
+    with pytest.raises(fz.FzError) as e:
+        fz.fz_run_batch(plan.handle, [c], None, 0, None)
+    assert e.value.code == fz.FZ_E_WORKSPACE
+    bad = fz.fz_clip()
+    bad.d_in, bad.d_out, bad.width, bad.height, bad.frames = 1, None, 320, 240, 10
+    with pytest.raises(fz.FzError) as e:
+        fz.fz_run_batch(plan.handle, [c, bad], 1, 1 << 20, None)
+    assert e.value.code == fz.FZ_E_INVALID and "clip 1" in fz.fz_last_error()
+    bad.d_out, bad.frames = 1, 0
+    with pytest.raises(fz.FzError):
+        fz.fz_run_batch(plan.handle, [bad], 1, 1 << 20, None)
+    bad.frames, bad.point_capacity = 3, 10
+    with pytest.raises(fz.FzError):
+        fz.fz_run_batch(plan.handle, [bad], 1, 1 << 20, None)
+    with pytest.raises(fz.FzError):
+        fz.fz_run_batch(plan.handle, [], 1, 1 << 20, None)
