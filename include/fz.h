@@ -155,6 +155,16 @@ int32_t fz_plan_num_segments(const fz_plan* plan);
 /* Copy the last stage index of each group into seg_last[0..cap). */
 fz_status fz_plan_segments(const fz_plan* plan, int32_t* seg_last, int32_t cap);
 fz_status fz_plan_segment_info(const fz_plan* plan, int32_t i, fz_segment_info* out);
+/* Override the kernel configuration of group i (autotuning): engine
+ * (FZ_ENGINE_TILE / FZ_ENGINE_ROW / FZ_ENGINE_AUTO), tile_w x tile_h for the
+ * tile engine (a compiled tile) or tile_h = rows per band for the row engine,
+ * frames_per_block (0 = the planner's choice).  The group is re-priced with the
+ * analytic model; FZ_E_UNSUPPORTED if the configuration does not exist for the
+ * group, FZ_E_LDS if it does not fit the plan's budget.  A cached batch graph
+ * is dropped. */
+fz_status fz_plan_set_segment_config(fz_plan* plan, int32_t i, int32_t engine, int32_t tile_w, int32_t tile_h,
+                                     int32_t frames_per_block);
+
 /* Planner objective of the chosen partition (bytes for the analytic model). */
 double fz_plan_cost(const fz_plan* plan);
 /* The planner's price of the group a..b (inclusive); +inf if not allowed. */

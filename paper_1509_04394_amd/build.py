@@ -41,15 +41,27 @@ def _compile(src: str, obj: str, hip: bool) -> tuple[str, int, str]:
     return src, p.returncode, out
 
 
-def build(jobs: int | None = None, verbose: bool = False) -> str:
+def _stale(obj: str, newest_source: float) -> bool:
+    return not os.path.exists(obj) or os.path.getmtime(obj) < newest_source
+
+
+def build(jobs: int | None = None, verbose: bool = False, incremental: bool = False) -> str:
+    """Compile every translation unit and link libfz.so.  With `incremental`,
+    objects newer than every source and header are reused (development aid)."""
     os.makedirs(BUILD_DIR, exist_ok=True)
     hip, cpp = sources()
     tasks = [(os.path.join(CSRC, f), os.path.join(BUILD_DIR, f + ".o"), True) for f in hip]
     tasks += [(os.path.join(CSRC, f), os.path.join(BUILD_DIR, f + ".o"), False) for f in cpp]
-    jobs = jobs or min(len(tasks), max(1, (os.cpu_count() or 4)))
+    all_tasks = tasks
+    if incremental:
+        deps = [os.path.join(CSRC, f) for f in os.listdir(CSRC)] + [os.path.join(ROOT, "include", "fz.h")]
+        newest = max(os.path.getmtime(d) for d in deps)
+        tasks = [t for t in tasks if _stale(t[1], newest)]
+    jobs = jobs or min(max(len(tasks), 1), max(1, (os.cpu_count() or 4)))
     with cf.ThreadPoolExecutor(jobs) as ex:
         results = list(ex.map(lambda t: _compile(*t), tasks))
     failed = [r for r in results if r[1] != 0]
+    tasks = all_tasks
     for src, rc, out in results:
         if out.strip() and (verbose or rc != 0):
             print(f"--- {os.path.basename(src)} (rc={rc})\n{out}", file=sys.stderr)
@@ -67,5 +79,5 @@ def clean():
 
 
 if __name__ == "__main__":
-    build(verbose="-v" in sys.argv)
+    build(verbose="-v" in sys.argv, incremental="--incremental" in sys.argv)
     print(LIB)

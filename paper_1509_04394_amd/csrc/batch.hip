@@ -17,7 +17,7 @@ static bool batch_persistent(const fz_plan& p, const fz_clip* clips, int n)
 {
     if (p.segs.size() != 1) return false;
     const Segment& g = p.segs[0];
-    if (!row_group(p.chain, g.cfirst, g.clast) || p.req_engine == FZ_ENGINE_TILE || p.req_w > 0) return false;
+    if (!row_group(p.chain, g.cfirst, g.clast) || g.engine != FZ_ENGINE_ROW || g.row_gen) return false;
     for (int i = 0; i < n; ++i)
         if (clips[i].width < 128 || clips[i].height < 8) return false;
     return true;

@@ -31,7 +31,7 @@ void group_features(const fz_plan& p, const Segment& g, float* f)
     if (g.engine == FZ_ENGINE_TILE && g.tile_w > 0)
         recompute = (double)(g.tile_w + 2 * g.halo) * (g.tile_h + 2 * g.halo) / ((double)g.tile_w * g.tile_h);
     if (g.engine == FZ_ENGINE_ROW)
-        recompute = (double)g.nstrips * 64 * g.row_k / W * (g.tile_h + 2.0 * ROW_HX) / g.tile_h;
+        recompute = (double)g.nstrips * 64 * g.row_k / W * (g.tile_h + 2.0 * g.halo) / g.tile_h;
     const double temporal = g.halo_t > 0 ? (g.tpb + (double)g.halo_t) / g.tpb : 1.0;
     int i = 0;
     f[i++] = (float)((B - A + 1) / 9.0);
@@ -52,6 +52,7 @@ void group_features(const fz_plan& p, const Segment& g, float* f)
     f[i++] = (float)(log2p(T) / 10.0);
     f[i++] = (float)log2p(recompute * temporal);
     f[i++] = (float)(log2p(W * H * T * ops) / 40.0);
+    f[i++] = (g.engine == FZ_ENGINE_ROW && !g.row_gen) ? 1.0f : 0.0f;  // the Harris-chain row kernel
 }
 
 // Forward pass of the cost network (parameter layout of mlp.hip).

@@ -391,26 +391,103 @@ __global__ __launch_bounds__(BLOCK_THREADS) void k_group(SegParams p)
         group_body<CH, A, B, TW, TH, false>(p, lds, ox0, oy0);
 }
 
-// Groups without a window stage: one pass over the pixels.
+// Groups without a window stage: one pass over the pixels.  Point stages need
+// no coordinates, so a frame is a flat array of W*H pixels; each thread takes
+// 4 consecutive pixels with vector loads and stores when the frame size is a
+// multiple of 4 and the buffers are 16-byte aligned (every plane then starts
+// 16-byte aligned for floats and 4-byte aligned for bytes), else one pixel.
+template <int CH, int A, int B, int V>
+__device__ __forceinline__ void stream_px(const SegParams& p, size_t plane, int t, size_t i)
+{
+    constexpr OpInfo oa = op_info(chain_op(CH, A));
+    constexpr OpInfo ob = op_info(chain_op(CH, B));
+    constexpr bool TEMPORAL = chain_op(CH, B) == FZ_OP_FRAMEDIFF;
+    constexpr int E = pw_end(CH, A, B);
+    const size_t vol = plane * p.T;
+    float v[V][3];
+    auto load = [&](int tt, float (&dst)[V][3]) {
+        const size_t off = (size_t)tt * plane + i;
+        if constexpr (oa.op == FZ_OP_RGB2GRAY) {
+            const uint8_t* s = (const uint8_t*)p.in + 3 * off;
+            if constexpr (V == 4) {
+                const uint3 w = *(const uint3*)s;
+                const uint32_t b[3] = {w.x, w.y, w.z};
+#pragma unroll
+                for (int k = 0; k < 12; ++k) dst[k / 3][k % 3] = (float)((b[k / 4] >> (8 * (k % 4))) & 255u);
+            } else {
+                for (int c = 0; c < 3; ++c) dst[0][c] = (float)s[c];
+            }
+        } else if constexpr (oa.in_dt == FZ_U8) {
+            const uint8_t* s = (const uint8_t*)p.in + off;
+            if constexpr (V == 4) {
+                const uint32_t w = *(const uint32_t*)s;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) dst[k][0] = (float)((w >> (8 * k)) & 255u);
+            } else {
+                dst[0][0] = (float)s[0];
+            }
+        } else {
+#pragma unroll
+            for (int c = 0; c < oa.in_ch; ++c) {
+                const float* s = (const float*)p.in + c * vol + off;
+                if constexpr (V == 4) {
+                    const float4 w = *(const float4*)s;
+                    dst[0][c] = w.x;
+                    dst[1][c] = w.y;
+                    dst[2][c] = w.z;
+                    dst[3][c] = w.w;
+                } else {
+                    dst[0][c] = s[0];
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < V; ++k) point_run<CH, A, E>(dst[k], p);
+    };
+    load(t, v);
+    if constexpr (TEMPORAL) {
+        float u[V][3];
+        load(t > 0 ? t - 1 : 0, u);
+#pragma unroll
+        for (int k = 0; k < V; ++k) v[k][0] = (float)framediff((uint32_t)v[k][0], (uint32_t)u[k][0]);
+    }
+    const size_t off = (size_t)t * plane + i;
+    if constexpr (ob.out_dt == FZ_U8) {
+        uint8_t* d = (uint8_t*)p.out + off;
+        if constexpr (V == 4) {
+            uint32_t w = 0;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) w |= ((uint32_t)v[k][0] & 255u) << (8 * k);
+            *(uint32_t*)d = w;
+        } else {
+            d[0] = (uint8_t)(uint32_t)v[0][0];
+        }
+    } else {
+#pragma unroll
+        for (int c = 0; c < ob.out_ch; ++c) {
+            float* d = (float*)p.out + c * vol + off;
+            if constexpr (V == 4)
+                *(float4*)d = make_float4(v[0][c], v[1][c], v[2][c], v[3][c]);
+            else
+                d[0] = v[0][c];
+        }
+    }
+}
+
 template <int CH, int A, int B>
 __global__ __launch_bounds__(BLOCK_THREADS) void k_stream(SegParams p)
 {
-    constexpr bool TEMPORAL = chain_op(CH, B) == FZ_OP_FRAMEDIFF;
-    constexpr int E = pw_end(CH, A, B);
-    const int n = p.W * p.H;
+    const size_t plane = (size_t)p.W * p.H;
     const int t = blockIdx.y;
-    for (int i = blockIdx.x * BLOCK_THREADS + threadIdx.x; i < n; i += gridDim.x * BLOCK_THREADS) {
-        const int y = i / p.W, x = i - y * p.W;
-        float v[3];
-        load_px<CH, A>(p, t, y, x, v);
-        point_run<CH, A, E>(v, p);
-        if constexpr (TEMPORAL) {
-            float u[3];
-            load_px<CH, A>(p, t > 0 ? t - 1 : 0, y, x, u);
-            point_run<CH, A, E>(u, p);
-            v[0] = (float)framediff((uint32_t)v[0], (uint32_t)u[0]);
-        }
-        store_px<CH, B>(p, t, y, x, v);
+    const size_t stride = (size_t)gridDim.x * BLOCK_THREADS;
+    const bool aligned = (((uintptr_t)p.in | (uintptr_t)p.out) & 15u) == 0;
+    if (plane % 4 == 0 && aligned) {
+        const size_t n4 = plane / 4;
+        for (size_t q = (size_t)blockIdx.x * BLOCK_THREADS + threadIdx.x; q < n4; q += stride)
+            stream_px<CH, A, B, 4>(p, plane, t, 4 * q);
+    } else {
+        for (size_t i = (size_t)blockIdx.x * BLOCK_THREADS + threadIdx.x; i < plane; i += stride)
+            stream_px<CH, A, B, 1>(p, plane, t, i);
     }
 }
 
@@ -422,7 +499,8 @@ hipError_t launch_group(const SegParams& p, int tile, hipStream_t s)
         return hipErrorInvalidValue;
     } else if constexpr (!group_has_window(CH, A, B)) {
         const int n = p.W * p.H;
-        int bx = (n + BLOCK_THREADS - 1) / BLOCK_THREADS;
+        const int per = n % 4 == 0 ? n / 4 : n;
+        int bx = (per + BLOCK_THREADS - 1) / BLOCK_THREADS;
         if (bx > 65535) bx = 65535;
         hipLaunchKernelGGL((k_stream<CH, A, B>), dim3(bx, p.T), dim3(BLOCK_THREADS), 0, s, p);
         return hipGetLastError();

@@ -23,6 +23,7 @@ struct Segment {
     int streaming;
     int engine;             // FZ_ENGINE_TILE / ROW / STREAM
     int row_k, nstrips, nbands, nchunks;  // row-marching geometry
+    int row_gen;            // 1: generic row kernel, 0: the Harris-chain kernel
     double bytes_per_px;
     double cost;
 };
@@ -65,7 +66,7 @@ fz_status fail(fz_status code, const std::string& msg);
 Segment price_group(const fz_plan& p, int a, int b, int tile_req_w, int tile_req_h, int tpb_req, int engine_req);
 
 // Learned prices (cost.cpp)
-constexpr int COST_FEATURES = 18;
+constexpr int COST_FEATURES = 19;
 void group_features(const fz_plan& p, const Segment& g, float* f);
 double mlp_predict(const float* prm, const float* x);
 Segment price_group_learned(const fz_plan& p, int a, int b, const float* prm, int req_w, int req_h, int req_tpb,

@@ -67,17 +67,22 @@ Segment price_group(const fz_plan& p, int a, int b, int req_w, int req_h, int re
     s.streaming = group_has_window(ch, A, B) ? 0 : 1;
     s.tpb = req_tpb > 0 ? req_tpb : (s.halo_t > 0 ? 8 : 1);
     if (s.tpb > p.T) s.tpb = p.T;
-    const bool row_ok = !s.streaming && row_group(ch, A, B) && row_strips_best(p.W) > 0 && p.H >= 8 &&
-                        req_engine != FZ_ENGINE_TILE && req_w == 0;
+    // row-marching: the Harris-chain kernel for its groups, the generic kernel
+    // (two columns per lane) for every other group with a window stage
+    const bool row_special = row_group(ch, A, B) && row_strips_best(p.W) > 0;
+    const bool row_generic = !row_special && rowgen_group(ch, A, B) && row_strips(p.W, 2, s.halo) > 0;
+    const bool row_ok = !s.streaming && (row_special || row_generic) && p.H >= 8 && req_engine != FZ_ENGINE_TILE &&
+                        req_w == 0;
     if (s.streaming) {
         s.engine = FZ_ENGINE_STREAM;
         s.lds_bytes = 0;
         s.tile_w = s.tile_h = 0;
     } else if (row_ok) {
         s.engine = FZ_ENGINE_ROW;
+        s.row_gen = row_generic ? 1 : 0;
         const bool diff = chain_op(ch, B) == FZ_OP_FRAMEDIFF;
-        s.row_k = row_strips_best(p.W);
-        s.nstrips = row_strips(p.W, s.row_k);
+        s.row_k = row_generic ? 2 : row_strips_best(p.W);
+        s.nstrips = row_strips(p.W, s.row_k, row_generic ? s.halo : ROW_HX);
         const RowShape rs = row_shape(p.H, p.T, s.nstrips, diff, req_h, req_tpb);
         s.tpb = rs.tt;
         s.nchunks = (p.T + s.tpb - 1) / s.tpb;
@@ -407,6 +412,34 @@ fz_status fz_plan_segment_info(const fz_plan* plan, int32_t i, fz_segment_info* 
     out->engine = s.engine;
     out->bytes_per_px = s.bytes_per_px;
     out->cost = s.cost;
+    return FZ_OK;
+}
+
+fz_status fz_plan_set_segment_config(fz_plan* plan, int32_t i, int32_t engine, int32_t tile_w, int32_t tile_h,
+                                     int32_t frames_per_block)
+{
+    if (!plan) return fail(FZ_E_INVALID, "fz_plan_set_segment_config: null plan");
+    if (i < 0 || i >= (int32_t)plan->segs.size()) return fail(FZ_E_INVALID, "fz_plan_set_segment_config: bad index");
+    if (engine < FZ_ENGINE_AUTO || engine > FZ_ENGINE_ROW || tile_w < 0 || tile_h < 0 || frames_per_block < 0)
+        return fail(FZ_E_INVALID, "fz_plan_set_segment_config: bad configuration");
+    if (engine == FZ_ENGINE_TILE && tile_w > 0 && tile_h <= 0)
+        return fail(FZ_E_INVALID, "fz_plan_set_segment_config: a tile width needs a tile height");
+    if (engine == FZ_ENGINE_TILE && tile_w > 0) {
+        bool compiled = false;
+        for (int t = 0; t < N_TILES; ++t) compiled |= fz::tile_w(t) == tile_w && fz::tile_h(t) == tile_h;
+        if (!compiled) return fail(FZ_E_UNSUPPORTED, "fz_plan_set_segment_config: tile not compiled");
+    }
+    const Segment& old = plan->segs[i];
+    Segment s = price_group(*plan, old.first, old.last, engine == FZ_ENGINE_TILE ? tile_w : 0, tile_h,
+                            frames_per_block, engine);
+    if (!(s.cost < kInf)) return fail(FZ_E_LDS, "fz_plan_set_segment_config: configuration does not fit the budget");
+    if (engine == FZ_ENGINE_ROW && s.engine != FZ_ENGINE_ROW)
+        return fail(FZ_E_UNSUPPORTED, "fz_plan_set_segment_config: the row engine does not apply to this group");
+    if (engine == FZ_ENGINE_TILE && tile_w > 0 && (s.tile_w != tile_w || s.tile_h != tile_h))
+        return fail(FZ_E_UNSUPPORTED, "fz_plan_set_segment_config: tile not compiled");
+    plan->total += s.cost - old.cost;
+    plan->segs[i] = s;
+    release_batch(*plan);
     return FZ_OK;
 }
 

@@ -106,6 +106,9 @@ struct RowCtx {
     bool real;
     uint32_t valid;           // bit k: column k of this lane is an output column of the strip
     int lo_in, hi_in, lo_g, hi_g, lo_s, hi_s, lo_b, hi_b;
+    // iteration j computes a stage's row iff (unsigned)(j - j*) < n*: the rows
+    // [lo, hi) of each stage mapped to iterations (row = y0 - 6 + j - lag)
+    int jp, np_, ji, ni, jg, ng, js, ns, jb, nb, jn, nn;
     uint8_t* prev;            // LDS previous-frame mask bits of this wavefront (DIFF)
 };
 
@@ -128,10 +131,10 @@ __device__ __forceinline__ void row_step(RowState<K, RGB>& st, const RowCtx& c, 
     // prefetch the input row two iterations ahead
     {
         const int rp = row_in + 2;
-        if (rp >= c.lo_in && rp < c.hi_in) load_raw<K, RGB>(c, rp, st.raw[(U + 2) % 3]);
+        if ((unsigned)(j - c.jp) < (unsigned)c.np_) load_raw<K, RGB>(c, rp, st.raw[(U + 2) % 3]);
     }
     // Gaussian, horizontal pass, on the gray input row
-    if (row_in >= c.lo_in && row_in < c.hi_in) {
+    if ((unsigned)(j - c.ji) < (unsigned)c.ni) {
         float gr[K];
 #pragma unroll
         for (int k = 0; k < K; ++k) {
@@ -151,7 +154,7 @@ __device__ __forceinline__ void row_step(RowState<K, RGB>& st, const RowCtx& c, 
     }
     // Gaussian, vertical pass: row row_in - 2
     const int rg = row_in - 2;
-    if (rg >= c.lo_g && rg < c.hi_g) {
+    if ((unsigned)(j - c.jg) < (unsigned)c.ng) {
 #pragma unroll
         for (int k = 0; k < K; ++k)
             st.g[U3][k] = gauss5_taps(p.gw, st.h[(U + 1) % 5][k], st.h[(U + 2) % 5][k], st.h[(U + 3) % 5][k],
@@ -160,7 +163,7 @@ __device__ __forceinline__ void row_step(RowState<K, RGB>& st, const RowCtx& c, 
     }
     // Sobel, products and the horizontal pass of the window sums: row row_in - 3
     const int rs = row_in - 3;
-    if (rs >= c.lo_s && rs < c.hi_s) {
+    if ((unsigned)(j - c.js) < (unsigned)c.ns) {
         float sv[K], ev[K];
 #pragma unroll
         for (int k = 0; k < K; ++k) {
@@ -195,7 +198,7 @@ __device__ __forceinline__ void row_step(RowState<K, RGB>& st, const RowCtx& c, 
     }
     // Window sums (vertical), Harris, threshold, 3-wide maximum: row row_in - 5
     const int rb = row_in - 5;
-    if (rb >= c.lo_b && rb < c.hi_b) {
+    if ((unsigned)(j - c.jb) < (unsigned)c.nb) {
         float s[3][K];
 #pragma unroll
         for (int ch = 0; ch < 3; ++ch)
@@ -216,7 +219,7 @@ __device__ __forceinline__ void row_step(RowState<K, RGB>& st, const RowCtx& c, 
     }
     // Suppression, feature points, output: row row_in - 6
     const int rn = row_in - 6;
-    if (rn >= c.y0 && rn < c.y1) {
+    if ((unsigned)(j - c.jn) < (unsigned)c.nn) {
         uint32_t bits = 0;
         float centre[K];
 #pragma unroll
@@ -327,6 +330,21 @@ __device__ __forceinline__ void row_item(const SegParams& p, const RowItem& it, 
     c.hi_s = min(p.H, c.y1 + 3);
     c.lo_b = max(0, c.y0 - 1);
     c.hi_b = min(p.H, c.y1 + 1);
+    // row r of a stage with lag L (rows behind the input row) is computed at
+    // iteration j = r - y0 + 6 + L
+    const int base = ROW_HX - c.y0;
+    c.jp = c.lo_in + base - 2;  // prefetch of row j + 2
+    c.np_ = c.hi_in - c.lo_in;
+    c.ji = c.lo_in + base;
+    c.ni = c.hi_in - c.lo_in;
+    c.jg = c.lo_g + base + 2;
+    c.ng = c.hi_g - c.lo_g;
+    c.js = c.lo_s + base + 3;
+    c.ns = c.hi_s - c.lo_s;
+    c.jb = c.lo_b + base + 5;
+    c.nb = c.hi_b - c.lo_b;
+    c.jn = c.y0 + base + 6;
+    c.nn = c.y1 - c.y0;
     c.prev = prev_lds;
 
     const int t0 = it.chunk * it.tt;

@@ -13,13 +13,17 @@ constexpr int ROW_TARGET_ITEMS = 4096;  // enough wavefronts to fill 256 CUs sev
 // or frame difference last, of the Harris chain.
 inline bool row_group(int ch, int A, int B) { return ch == CHAIN_HARRIS && (A == 0 || A == 1) && (B == 7 || B == 8); }
 
-// Strips of 64*K columns that overlap by 2*ROW_HX cover a frame of width W.
-inline int row_strips(int W, int K)
+// Strips of 64*K columns that overlap by 2*halo cover a frame of width W.
+inline int row_strips(int W, int K, int halo = ROW_HX)
 {
-    const int span = 64 * K, S = span - 2 * ROW_HX;
+    const int span = 64 * K, S = span - 2 * halo;
     if (W < span) return 0;
     return 1 + (W - span + S - 1) / S;
 }
+
+// Groups the generic row kernel implements: any group with a window stage
+// (one column per lane pair, K = 2).
+inline bool rowgen_group(int ch, int A, int B) { return group_has_window(ch, A, B); }
 
 // Columns per lane (2 or 3) that compute the fewest columns in total; 0 if the
 // frame is narrower than 128 columns.

@@ -9,6 +9,7 @@
 #include "fz_internal.h"
 #include "rowfuse.h"
 #include "tables.h"
+#include "tables_rowgen.h"
 
 namespace fz {
 
@@ -71,10 +72,17 @@ fz_status run_plan(const fz_plan& p, const void* d_in, void* d_out, fz_point* d_
             rp.nbands = g.nbands;
             rp.nchunks = g.nchunks;
             rp.total = g.nstrips * g.nbands * g.nchunks;
-            rp.strip_step = 64 * g.row_k - 2 * ROW_HX;
             rp.band_h = g.tile_h;
             rp.tt = g.tpb;
-            e = launch_rowfuse(rp, g.row_k, g.cfirst == 0, g.clast == 8, s);
+            if (g.row_gen) {
+                rp.strip_step = 64 * g.row_k - 2 * g.halo;
+                RowGenFn fn = lookup_rowgen(p.chain, g.cfirst, g.clast);
+                if (!fn) return fail(FZ_E_UNSUPPORTED, "no row kernel compiled for this group");
+                e = fn(rp, s);
+            } else {
+                rp.strip_step = 64 * g.row_k - 2 * ROW_HX;
+                e = launch_rowfuse(rp, g.row_k, g.cfirst == 0, g.clast == 8, s);
+            }
         } else {
             LaunchFn fn = lookup(p.chain, g.cfirst, g.clast);
             if (!fn) return fail(FZ_E_UNSUPPORTED, "no kernel compiled for this group");

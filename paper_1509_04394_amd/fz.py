@@ -86,6 +86,8 @@ SIGNATURES = [
     ("fz_plan_segments", ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32), ctypes.c_int32]),
     ("fz_plan_segment_info", ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(fz_segment_info)]),
     ("fz_plan_cost", ctypes.c_double, [ctypes.c_void_p]),
+    ("fz_plan_set_segment_config", ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                                    ctypes.c_int32, ctypes.c_int32]),
     ("fz_plan_group_cost", ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
                                             ctypes.POINTER(ctypes.c_double)]),
     ("fz_partition_min", ctypes.c_int32, [ctypes.POINTER(ctypes.c_double), ctypes.c_int32,
@@ -177,6 +179,11 @@ def fz_plan_segment_info(plan, i) -> fz_segment_info:
     s = fz_segment_info()
     _check(lib().fz_plan_segment_info(plan, i, ctypes.byref(s)))
     return s
+
+
+def fz_plan_set_segment_config(plan, i, engine, tile_w=0, tile_h=0, frames_per_block=0):
+    eng = ENGINES[engine] if isinstance(engine, str) else int(engine)
+    _check(lib().fz_plan_set_segment_config(plan, i, eng, tile_w, tile_h, frames_per_block))
 
 
 def fz_plan_cost(plan) -> float:

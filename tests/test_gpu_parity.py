@@ -321,3 +321,54 @@ def test_row_engine_vs_oracle(dev):
     nex, ng, no = check_full_chain(ops, rgb, g, gp, o, op_)
     say("row vs oracle exempt", nex, "points", ng, no)
     assert no > 0
+
+
+GEN_SHAPES = [(128, 8, 3), (150, 70, 5), (257, 40, 4)]
+
+
+@pytest.mark.parametrize("shape", GEN_SHAPES, ids=lambda s: "x".join(map(str, s)))
+@pytest.mark.parametrize("chain", ["rgb", "grad"])
+def test_generic_row_groups_equal_tile_engine(dev, shape, chain):
+    """Every contiguous group with a window stage: the generic row kernel gives
+    the tile engine's bytes and points on real intermediate inputs."""
+    W, H, T = shape
+    ops = fz.RGB_HARRIS_CHAIN if chain == "rgb" else fz.GRAD_CHAIN
+    vid = torch.from_numpy(synth.video(W, H, T, seed=W * 7 + H, rgb=chain == "rgb")).to(dev)
+    ins = [vid]
+    for a in range(1, len(ops)):
+        out, _, _ = fz.Plan(ops[:a], W, H, T, engine="tile").run(vid)
+        ins.append(out)
+    torch.cuda.synchronize()
+    windows = {"gauss5", "sobel3", "boxsum5", "nms3"}
+    key = lambda p: sorted(map(tuple, p.tolist()))
+    n = 0
+    for a in range(len(ops)):
+        for b in range(a, len(ops)):
+            if not windows & set(ops[a:b + 1]):
+                continue
+            sub = ops[a:b + 1]
+            pr = fz.Plan(sub, W, H, T, partition=[], engine="row")
+            pt = fz.Plan(sub, W, H, T, partition=[], engine="tile")
+            assert pr.segment_info()[0].engine == fz.FZ_ENGINE_ROW
+            assert pt.segment_info()[0].engine == fz.FZ_ENGINE_TILE
+            ro, rp, rc = pr.run(ins[a])
+            to, tp, tc = pt.run(ins[a])
+            torch.cuda.synchronize()
+            assert torch.equal(ro, to), (sub, shape)
+            if rp is not None:
+                assert key(fz.points_to_numpy(rp, rc)) == key(fz.points_to_numpy(tp, tc)), (sub, shape)
+            n += 1
+    say("generic row groups", chain, shape, n)
+
+
+def test_every_partition_bitwise_equal_row_width(dev):
+    """All 2^8 partitions at a width where every group runs row-marching."""
+    ops = fz.RGB_HARRIS_CHAIN
+    rgb = synth.video(150, 40, 4, seed=31, rgb=True)
+    ref, refp, _ = run_gpu(ops, rgb, dev, partition="unfused", engine="tile")
+    key = lambda p: sorted(map(tuple, p.tolist()))
+    for bits in itertools.product((0, 1), repeat=len(ops) - 1):
+        cuts = [i for i, b in enumerate(bits) if b]
+        g, gp, plan = run_gpu(ops, rgb, dev, partition=cuts)
+        assert np.array_equal(g, ref), cuts
+        assert key(gp) == key(refp), cuts

@@ -194,3 +194,25 @@ def test_batch_argument_errors_without_launch():
         fz.fz_run_batch(plan.handle, [bad], 1, 1 << 20, None)
     with pytest.raises(fz.FzError):
         fz.fz_run_batch(plan.handle, [], 1, 1 << 20, None)
+
+
+def test_segment_config_override():
+    p = fz.Plan(fz.RGB_HARRIS_CHAIN, 800, 600, 100, partition=[0, 7])
+    info = p.segment_info()
+    assert [s.engine for s in info] == [fz.FZ_ENGINE_STREAM, fz.FZ_ENGINE_ROW, fz.FZ_ENGINE_STREAM]
+    fz.fz_plan_set_segment_config(p.handle, 1, "tile", 32, 32)
+    s = p.segment_info()[1]
+    assert (s.engine, s.tile_w, s.tile_h) == (fz.FZ_ENGINE_TILE, 32, 32)
+    fz.fz_plan_set_segment_config(p.handle, 1, "row", 0, 50, 0)
+    s = p.segment_info()[1]
+    assert (s.engine, s.tile_h) == (fz.FZ_ENGINE_ROW, 50)
+    with pytest.raises(fz.FzError) as e:
+        fz.fz_plan_set_segment_config(p.handle, 1, "tile", 48, 48)
+    assert e.value.code == fz.FZ_E_UNSUPPORTED
+    with pytest.raises(fz.FzError) as e:
+        fz.fz_plan_set_segment_config(p.handle, 0, "row", 0, 50, 0)
+    assert e.value.code == fz.FZ_E_UNSUPPORTED
+    with pytest.raises(fz.FzError):
+        fz.fz_plan_set_segment_config(p.handle, 3, "auto")
+    # the plan's total follows the group prices
+    assert p.cost == sum(s.cost for s in p.segment_info())
