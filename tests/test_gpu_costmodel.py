@@ -1,0 +1,46 @@
+"""The learned price against the analytic one, measured.
+
+For held-out workloads (seeded chain, frame size and length not used in
+training) every group is timed in every configuration; the best partition
+under measured prices (exact DP over the table) is the reference.  The
+partition the planner chooses with the trained network must be within 5% of
+it (geometric mean), and the test prints what that gains over the planner's
+analytic (bytes) prices."""
+import math
+import os
+
+import numpy as np
+import pytest
+
+from paper_1509_04394_amd import costmodel, fz
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def weights():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    if not os.path.exists(costmodel.WEIGHTS_PATH):
+        pytest.skip("no trained cost weights")
+    return costmodel.load_weights()
+
+
+def test_learned_partitions_near_best_measured(weights):
+    params, meta = weights
+    cases = costmodel.cases(seed=424242, n_cases=4)
+    rows = []
+    for name, W, H, T in cases:
+        ops = costmodel.CHAINS[name]
+        table = costmodel.measure_table(ops, W, H, T, seed=77)
+        r = costmodel.evaluate_case(ops, W, H, T, params, table)
+        rows.append(r)
+        print(f"[costmodel] {name} {W}x{H}x{T}: best {r['best_us']:.0f} us {r['best_partition']}, "
+              f"learned {r['learned_ratio']:.3f} {r['learned_partition']}, "
+              f"analytic {r['analytic_ratio']:.3f} {r['analytic_partition']}", flush=True)
+    geo = lambda k: math.exp(np.mean([math.log(r[k]) for r in rows]))
+    print(f"[costmodel] geomean over best: learned {geo('learned_ratio'):.4f}, "
+          f"analytic {geo('analytic_ratio'):.4f}", flush=True)
+    assert geo("learned_ratio") <= 1.05
+    assert geo("learned_ratio") <= geo("analytic_ratio") * 1.02
