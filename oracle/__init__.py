@@ -6,6 +6,8 @@ never imports it.
 
 * ``chain``: the plain, unfused, frame-by-frame FP64 chain (``oracle.c``),
   Sec. III composition I_out = K_n(...K_1(I_in)).
+* ``gchain``: the same for a chain of generic single-channel stages (point,
+  weighted stencil, window sum; the Table I classes with free parameters).
 * ``partition``: brute-force enumeration of every contiguous partition of a
   kernel sequence (Sec. VI, Fig. 5 model).
 * ``mlp``: FP64 forward / backward of the cost-model network.
@@ -56,6 +58,10 @@ def _load():
                                  ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, d, ctypes.c_int32,
                                  ctypes.c_double, ctypes.c_double, ctypes.c_double, d, ctypes.c_int64,
                                  ctypes.POINTER(ctypes.c_int64), ctypes.c_int32]
+        i32 = ctypes.POINTER(ctypes.c_int32)
+        lib.or_gchain.restype = ctypes.c_int
+        lib.or_gchain.argtypes = [i32, i32, i32, i32, d, d, d, ctypes.c_int32, d, ctypes.c_int32, ctypes.c_int32,
+                                  ctypes.c_int32, d, ctypes.c_int32]
         _lib = lib
     return _lib
 
@@ -110,3 +116,54 @@ def chain(ops, volume, in_ch=None, sigma=SIGMA, k=HARRIS_K, thr=THRESHOLD,
         raise RuntimeError(f"oracle point buffer overflow ({n} > {cap})")
     return out, pts[:n].copy()
 
+
+GKINDS = {"point": 0, "stencil": 1, "box": 2}
+POINT_KINDS = {"affine": 0, "abs": 1, "square": 2, "sqrtabs": 3, "clamp": 4}
+
+
+def gchain(stages, volume, nthreads=None):
+    """Run a generic chain over ``volume`` [T][H][W] (any real dtype).
+
+    ``stages`` is a list of tuples:
+      ("point", kind, a, b)       kind in POINT_KINDS; affine is a*v + b,
+                                  clamp is min(max(v, a), b)
+      ("stencil", rx, ry, w)      w has shape (2ry+1, 2rx+1): correlation
+                                  weights, w[v+ry][u+rx] multiplies in(x+u, y+v)
+      ("box", rx, ry)             unweighted (2rx+1) x (2ry+1) window sum
+    Window stages clamp their reads to the frame (replicate borders).  Returns
+    out [T][H][W] float64.
+    """
+    v = np.ascontiguousarray(np.asarray(volume), dtype=np.float64)
+    if v.ndim != 3:
+        raise ValueError("volume must be [T][H][W]")
+    T, H, W = v.shape
+    n = len(stages)
+    kind = (ctypes.c_int32 * n)()
+    rx = (ctypes.c_int32 * n)()
+    ry = (ctypes.c_int32 * n)()
+    pk = (ctypes.c_int32 * n)()
+    pa = np.zeros(n, np.float64)
+    pb = np.zeros(n, np.float64)
+    ws = []
+    for i, st in enumerate(stages):
+        kind[i] = GKINDS[st[0]]
+        if st[0] == "point":
+            pk[i] = POINT_KINDS[st[1]]
+            pa[i] = st[2] if len(st) > 2 else 0.0
+            pb[i] = st[3] if len(st) > 3 else 0.0
+        else:
+            rx[i], ry[i] = int(st[1]), int(st[2])
+            if st[0] == "stencil":
+                w = np.asarray(st[3], np.float64)
+                if w.shape != (2 * ry[i] + 1, 2 * rx[i] + 1):
+                    raise ValueError(f"stage {i}: weights must have shape {(2 * ry[i] + 1, 2 * rx[i] + 1)}")
+                ws.append(w.ravel())
+    wcat = np.ascontiguousarray(np.concatenate(ws) if ws else np.zeros(1), dtype=np.float64)
+    out = np.zeros_like(v)
+    if nthreads is None:
+        nthreads = min(os.cpu_count() or 1, T)
+    rc = _load().or_gchain(kind, rx, ry, pk, _dp(pa), _dp(pb), _dp(wcat), n, _dp(v), W, H, T, _dp(out),
+                           int(nthreads))
+    if rc != 0:
+        raise RuntimeError(f"oracle generic chain failed with code {rc}")
+    return out

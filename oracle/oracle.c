@@ -22,8 +22,14 @@
  *   9 nms3       255 iff v > 0 and v >= its 3x3 neighbours, else 0; emits points
  *  10 framediff  |m[t] - m[max(t-1,0)]|          1 -> 1   (multi-frame, Table I)
  *
- * Parity status of each function: pinned by tests/test_oracle.py (closed forms,
- * invariants, library routines, brute force); see the module docstring there.
+ * Generic single-channel stages (or_gchain): the three access classes of
+ * Table I with free parameters -- a point operation (affine, absolute value,
+ * square, square root of the absolute value, clamp), a weighted
+ * (2rx+1) x (2ry+1) stencil and an unweighted (2rx+1) x (2ry+1) window sum.
+ *
+ * Parity status of each function: pinned by tests/test_oracle.py and, for the
+ * generic stages, tests/test_generic_oracle.py (closed forms, invariants,
+ * library routines, brute force); see the module docstrings there.
  */
 #include <math.h>
 #include <pthread.h>
@@ -104,16 +110,53 @@ void or_products(const double* ix, const double* iy, double* pxx, double* pxy, d
     }
 }
 
-/* Rectangular operation: unweighted (2r+1)^2 window sum, replicate borders. */
-void or_boxsum(const double* in, double* out, int W, int H, int r)
+/* Rectangular operation: unweighted (2rx+1) x (2ry+1) window sum, replicate
+ * borders. */
+void or_box(const double* in, double* out, int W, int H, int rx, int ry)
 {
     for (int y = 0; y < H; ++y)
         for (int x = 0; x < W; ++x) {
             double acc = 0.0;
-            for (int v = -r; v <= r; ++v)
-                for (int u = -r; u <= r; ++u) acc += px(in, W, H, x + u, y + v);
+            for (int v = -ry; v <= ry; ++v)
+                for (int u = -rx; u <= rx; ++u) acc += px(in, W, H, x + u, y + v);
             out[(size_t)y * W + x] = acc;
         }
+}
+
+void or_boxsum(const double* in, double* out, int W, int H, int r) { or_box(in, out, W, H, r, r); }
+
+/* Rectangular operation with free weights: the correlation
+ * out(x, y) = sum_{v,u} w[v + ry][u + rx] * in(x + u, y + v), replicate
+ * borders, w row-major with 2rx+1 entries per row. */
+void or_stencil(const double* in, double* out, int W, int H, int rx, int ry, const double* w)
+{
+    const int kw = 2 * rx + 1;
+    for (int y = 0; y < H; ++y)
+        for (int x = 0; x < W; ++x) {
+            double acc = 0.0;
+            for (int v = -ry; v <= ry; ++v)
+                for (int u = -rx; u <= rx; ++u) acc += w[(v + ry) * kw + (u + rx)] * px(in, W, H, x + u, y + v);
+            out[(size_t)y * W + x] = acc;
+        }
+}
+
+/* Point operations of the generic chain. */
+enum { OR_P_AFFINE = 0, OR_P_ABS = 1, OR_P_SQUARE = 2, OR_P_SQRTABS = 3, OR_P_CLAMP = 4 };
+
+static double or_point_value(int kind, double a, double b, double v)
+{
+    switch (kind) {
+    case OR_P_AFFINE: return a * v + b;
+    case OR_P_ABS: return fabs(v);
+    case OR_P_SQUARE: return v * v;
+    case OR_P_SQRTABS: return sqrt(fabs(v));
+    default: return fmin(fmax(v, a), b);  /* clamp to [a, b] */
+    }
+}
+
+void or_point(const double* in, double* out, int W, int H, int kind, double a, double b)
+{
+    for (size_t i = 0; i < (size_t)W * H; ++i) out[i] = or_point_value(kind, a, b, in[i]);
 }
 
 /* Harris corner response from the window sums of the structure tensor. */
@@ -326,5 +369,81 @@ int or_chain(const int32_t* ops, int32_t n, const double* in, int32_t in_ch, int
     }
     if (has_fd && n > 1) free(prefd);
     free(jobs); free(th); free(jpts);
+    return status;
+}
+
+/* ------------------------------------------------------------------ generic chains */
+
+enum { OR_G_POINT = 0, OR_G_STENCIL = 1, OR_G_BOX = 2 };
+
+typedef struct {
+    const int32_t* kind; const int32_t* rx; const int32_t* ry; const int32_t* pk;
+    const double* pa; const double* pb; const double* w;
+    int n;
+    const double* in; double* out;
+    int W, H, T, t_begin, t_end, status;
+} gjob_t;
+
+static void* gworker(void* arg)
+{
+    gjob_t* j = (gjob_t*)arg;
+    size_t P = (size_t)j->W * j->H;
+    double* a = (double*)malloc(sizeof(double) * P);
+    double* b = (double*)malloc(sizeof(double) * P);
+    if (!a || !b) { free(a); free(b); j->status = -1; return NULL; }
+    for (int t = j->t_begin; t < j->t_end; ++t) {
+        memcpy(a, j->in + (size_t)t * P, sizeof(double) * P);
+        size_t woff = 0;
+        for (int s = 0; s < j->n; ++s) {
+            switch (j->kind[s]) {
+            case OR_G_POINT: or_point(a, b, j->W, j->H, j->pk[s], j->pa[s], j->pb[s]); break;
+            case OR_G_STENCIL:
+                or_stencil(a, b, j->W, j->H, j->rx[s], j->ry[s], j->w + woff);
+                woff += (size_t)(2 * j->rx[s] + 1) * (2 * j->ry[s] + 1);
+                break;
+            case OR_G_BOX: or_box(a, b, j->W, j->H, j->rx[s], j->ry[s]); break;
+            default: j->status = -3; free(a); free(b); return NULL;
+            }
+            double* tmp = a; a = b; b = tmp;
+        }
+        memcpy(j->out + (size_t)t * P, a, sizeof(double) * P);
+    }
+    free(a); free(b);
+    return NULL;
+}
+
+/*
+ * Generic chain: stages 0..n-1 of kinds OR_G_*, applied in order to every
+ * frame of in[T][H][W] (frames are independent: no generic stage looks at
+ * other frames), result in out[T][H][W].  rx/ry are the window radii of the
+ * window stages; pk/pa/pb the kind and parameters of the point stages; w the
+ * weights of the stencil stages, concatenated in stage order.
+ */
+int or_gchain(const int32_t* kind, const int32_t* rx, const int32_t* ry, const int32_t* pk, const double* pa,
+              const double* pb, const double* w, int32_t n, const double* in, int32_t W, int32_t H, int32_t T,
+              double* out, int32_t nthreads)
+{
+    if (n <= 0 || W <= 0 || H <= 0 || T <= 0) return -10;
+    for (int s = 0; s < n; ++s)
+        if (kind[s] != OR_G_POINT && (rx[s] < 0 || ry[s] < 0)) return -12;
+    if (nthreads < 1) nthreads = 1;
+    if (nthreads > T) nthreads = T;
+    gjob_t* jobs = (gjob_t*)calloc(nthreads, sizeof(gjob_t));
+    pthread_t* th = (pthread_t*)calloc(nthreads, sizeof(pthread_t));
+    if (!jobs || !th) { free(jobs); free(th); return -1; }
+    for (int i = 0; i < nthreads; ++i) {
+        gjob_t* j = &jobs[i];
+        j->kind = kind; j->rx = rx; j->ry = ry; j->pk = pk; j->pa = pa; j->pb = pb; j->w = w; j->n = n;
+        j->in = in; j->out = out; j->W = W; j->H = H; j->T = T;
+        j->t_begin = (int)((int64_t)T * i / nthreads);
+        j->t_end = (int)((int64_t)T * (i + 1) / nthreads);
+        pthread_create(&th[i], NULL, gworker, j);
+    }
+    int status = 0;
+    for (int i = 0; i < nthreads; ++i) {
+        pthread_join(th[i], NULL);
+        if (jobs[i].status) status = jobs[i].status;
+    }
+    free(jobs); free(th);
     return status;
 }

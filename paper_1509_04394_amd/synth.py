@@ -164,3 +164,48 @@ def ramp(width: int, height: int, frames: int, a: float, b: float, c: float) -> 
     if f.min() < 0 or f.max() > 255 or np.any(f != np.round(f)):
         raise ValueError("ramp must be integral in [0, 255]")
     return np.broadcast_to(f.astype(np.uint8), (frames, height, width)).copy()
+
+
+POINT_KINDS = ("affine", "abs", "square", "sqrtabs", "clamp")
+
+
+def random_chain(seed: int, length: int | None = None, max_r: int = 3):
+    """A random chain of generic single-channel stages, for planner and cost
+    model workloads.
+
+    Recipe (numpy PCG64 seeded by ``seed``): length ~ U{4..16} unless given;
+    each stage's class uniform over {stencil, point, box}:
+      * stencil: radius r ~ U{0..max_r} on both axes, weights N(0, 1) scaled so
+        that their absolute values sum to 1;
+      * point: kind uniform over POINT_KINDS; affine a = +-U[0.5, 2],
+        b ~ U[-20, 20]; clamp lo ~ U[-50, 50], hi = lo + U[10, 200];
+      * box: radius r ~ U{1..max_r} on both axes.
+    Every number is rounded to float32 here, so the values any consumer sees
+    are exactly representable in single precision.  Stages are tuples
+    ("stencil", rx, ry, w[2ry+1][2rx+1]), ("point", kind, a, b), ("box", rx, ry).
+    """
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(4, 17)) if length is None else int(length)
+    f32 = lambda v: float(np.float32(v))
+    out = []
+    for _ in range(n):
+        cls = int(rng.integers(0, 3))
+        if cls == 0:
+            r = int(rng.integers(0, max_r + 1))
+            w = rng.standard_normal((2 * r + 1, 2 * r + 1))
+            w = (w / np.abs(w).sum()).astype(np.float32)
+            out.append(("stencil", r, r, w))
+        elif cls == 1:
+            kind = POINT_KINDS[int(rng.integers(0, len(POINT_KINDS)))]
+            if kind == "affine":
+                a = rng.uniform(0.5, 2.0) * (1 if rng.random() < 0.5 else -1)
+                out.append(("point", kind, f32(a), f32(rng.uniform(-20, 20))))
+            elif kind == "clamp":
+                lo = f32(rng.uniform(-50, 50))
+                out.append(("point", kind, lo, f32(lo + rng.uniform(10, 200))))
+            else:
+                out.append(("point", kind, 0.0, 0.0))
+        else:
+            r = int(rng.integers(1, max_r + 1))
+            out.append(("box", r, r))
+    return out
