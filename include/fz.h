@@ -61,7 +61,29 @@ enum {
     FZ_OP_HARRIS = 7,     /* point op: 3 x f32 -> f32, Sxx*Syy - Sxy^2 - k (Sxx+Syy)^2, param[0] = k */
     FZ_OP_THRESHOLD = 8,  /* point op: f32 -> f32, v >= param[0] ? v : 0 */
     FZ_OP_NMS3 = 9,       /* rectangular, radius 1: f32 -> u8 mask (255 = feature) + feature points */
-    FZ_OP_FRAMEDIFF = 10  /* multi-frame point op, 1 frame back: u8 -> u8, |m[t] - m[t-1]| (m[-1] = m[0]) */
+    FZ_OP_FRAMEDIFF = 10, /* multi-frame point op, 1 frame back: u8 -> u8, |m[t] - m[t-1]| (m[-1] = m[0]) */
+
+    /* Generic single-channel stages: the Table I classes with free parameters.
+     * A chain is either a contiguous part of the Harris chain above
+     * (FZ_OP_RGB2GRAY .. FZ_OP_FRAMEDIFF in that order, or FZ_OP_GAUSS5,
+     * FZ_OP_SOBEL3, FZ_OP_GRADMAG) or made of generic stages only.  Generic
+     * stages read u8 (first stage only) or f32 and write f32, one channel;
+     * window reads use replicate borders. */
+    FZ_OP_STENCIL = 11,   /* rectangular, radii rx, ry in [0, 3]: out(x,y) = sum_{v,u} w[v+ry][u+rx] in(x+u, y+v),
+                             `weights` = (2ry+1) x (2rx+1) floats, row-major; summed in row order v = -ry..ry,
+                             each row u = -rx..rx, by fused multiply-adds from 0 */
+    FZ_OP_BOX = 12,       /* rectangular, radii rx, ry in [0, 3]: unweighted window sum; each row summed
+                             left to right, the row sums added top to bottom */
+    FZ_OP_POINT = 13      /* point op: param[0] = FZ_POINT_* kind, param[1] = a, param[2] = b */
+};
+
+/* Kinds of FZ_OP_POINT. */
+enum {
+    FZ_POINT_AFFINE = 0,  /* fmaf(a, v, b) */
+    FZ_POINT_ABS = 1,     /* |v| */
+    FZ_POINT_SQUARE = 2,  /* v * v */
+    FZ_POINT_SQRTABS = 3, /* sqrt(|v|), correctly rounded */
+    FZ_POINT_CLAMP = 4    /* min(max(v, a), b), a <= b */
 };
 
 enum { FZ_U8 = 1, FZ_F32 = 2 };
@@ -82,6 +104,7 @@ typedef struct fz_stage {
     int32_t in_dtype, out_dtype;
     int32_t dep;
     float param[4];
+    const float* weights;  /* FZ_OP_STENCIL: host array, copied by fz_plan_chain; NULL otherwise */
 } fz_stage;
 
 /* Feature point emitted by FZ_OP_NMS3 (frame, row, column, corner response). */
@@ -135,7 +158,10 @@ typedef struct fz_segment_info {
 } fz_segment_info;
 
 /* Fill `out` with the access pattern and default parameters of `op`
- * (sigma 1, k 0.04, threshold 1e8).  FZ_E_INVALID for an unknown op. */
+ * (sigma 1, k 0.04, threshold 1e8; generic stages: f32 in and out, radius 1
+ * for FZ_OP_STENCIL and FZ_OP_BOX with no weights set, the identity
+ * FZ_POINT_AFFINE a = 1, b = 0 for FZ_OP_POINT).  FZ_E_INVALID for an
+ * unknown op. */
 fz_status fz_stage_describe(int32_t op, fz_stage* out);
 
 /* Plan a chain (Sec. VI-A): validate the n stage descriptors (host array),
@@ -146,7 +172,10 @@ fz_status fz_stage_describe(int32_t op, fz_stage* out);
  * smallest tile does not fit `lds_budget_bytes` is not allowed.  On success
  * *out owns a new plan the caller frees with fz_plan_destroy().  The chain must
  * be a contiguous part of  rgb2gray, gauss5, sobel3, products, boxsum5,
- * harris, threshold, nms3, framediff  or of  gauss5, sobel3, gradmag. */
+ * harris, threshold, nms3, framediff  or of  gauss5, sobel3, gradmag, or a
+ * sequence of generic stages (FZ_OP_STENCIL / FZ_OP_BOX / FZ_OP_POINT; a
+ * window stage must declare FZ_DEP_TMT or FZ_DEP_KK); other sequences give
+ * FZ_E_UNSUPPORTED.  Stencil weights must be finite and are copied. */
 fz_status fz_plan_chain(const fz_stage* stages, int32_t n, const fz_plan_opts* opts, fz_plan** out);
 
 void fz_plan_destroy(fz_plan* plan);

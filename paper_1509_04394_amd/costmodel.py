@@ -34,10 +34,21 @@ CHAINS = {"rgb_harris": fz.RGB_HARRIS_CHAIN, "harris": fz.HARRIS_CHAIN, "grad": 
 TILES = [(64, 16), (32, 32), (64, 32)]
 
 
+def _is_window(op):
+    if isinstance(op, tuple):
+        return op[0] != "point"
+    return op in ("gauss5", "sobel3", "boxsum5", "nms3")
+
+
+def _in_dtype(ops, a):
+    """Input type of a generic group starting at stage a (u8 video or f32 intermediate)."""
+    return "u8" if a == 0 else "f32"
+
+
 def group_configs(ops, a, b):
     """Kernel configurations of group a..b: the planner's automatic choice and
     every compiled LDS tile (groups with a window stage)."""
-    window = any(op in ("gauss5", "sobel3", "boxsum5", "nms3") for op in ops[a:b + 1])
+    window = any(_is_window(op) for op in ops[a:b + 1])
     cfgs = [dict(engine="auto")]
     if window:
         cfgs += [dict(engine="tile", tile=t) for t in TILES]
@@ -51,7 +62,7 @@ def _inputs(ops, W, H, T, seed, dev):
     vid = torch.from_numpy(synth.video(W, H, T, seed=seed, rgb=rgb)).to(dev)
     ins = [vid]
     for a in range(1, len(ops)):
-        plan = fz.Plan(ops[:a], W, H, T)
+        plan = fz.Plan(ops[:a], W, H, T)  # generic chains: u8 video in, f32 out
         out, pts, cnt = plan.run(vid)
         ins.append(out)
     torch.cuda.synchronize()
@@ -86,8 +97,9 @@ def measure_table(ops, W, H, T, seed=0, reps=5, dev=None):
     for a in range(n):
         for b in range(a, n):
             for cfg in group_configs(ops, a, b):
+                extra = {"in_dtype": _in_dtype(ops, a)} if isinstance(ops[0], tuple) else {}
                 try:
-                    plan = fz.Plan(ops[a:b + 1], W, H, T, partition=[], **cfg)
+                    plan = fz.Plan(ops[a:b + 1], W, H, T, partition=[], **cfg, **extra)
                 except fz.FzError:
                     continue
                 s = plan.segment_info()[0]
@@ -208,7 +220,7 @@ def evaluate_case(ops, W, H, T, params, table):
 
 
 def cases(seed, n_cases):
-    """Seeded (chain name, W, H, T) workloads."""
+    """Seeded (chain name, W, H, T) workloads of the fixed chains."""
     rng = np.random.default_rng(seed)
     out = []
     names = sorted(CHAINS)
@@ -220,14 +232,38 @@ def cases(seed, n_cases):
     return out
 
 
-def build(n_train=24, n_test=8, seed=5, steps=4000, out=WEIGHTS_PATH, log=print):
-    """Measure, train and evaluate; write the weights (with the evaluation) to `out`."""
+RANDOM_T = 64
+
+
+def random_cases(first_seed, n_cases):
+    """Random generic chains: chain k drawn by synth.random_chain(first_seed + k),
+    frame size uniform over FRAME_SIZES (from the same seed), 64 frames.  Each
+    case is ("random:<seed>", W, H, T)."""
+    out = []
+    for k in range(n_cases):
+        sd = first_seed + k
+        W, H = FRAME_SIZES[int(np.random.default_rng([sd, 1]).integers(0, len(FRAME_SIZES)))]
+        out.append((f"random:{sd}", W, H, RANDOM_T))
+    return out
+
+
+def case_ops(name):
+    """Stage list of a case name: a fixed chain or a random generic chain."""
+    if name.startswith("random:"):
+        return synth.random_chain(int(name.split(":")[1]))
+    return CHAINS[name]
+
+
+def build(n_train=24, n_test=8, seed=5, steps=4000, out=WEIGHTS_PATH, log=print, n_random_train=0,
+          n_random_test=0, reps=5):
+    """Measure, train and evaluate; write the weights (with the evaluation) to `out`.
+    Random generic chains are seeded from 5000 (training) and 9000 (test)."""
     t0 = time.time()
-    train_cases = cases(seed, n_train)
-    test_cases = cases(seed + 1000, n_test)
+    train_cases = cases(seed, n_train) + random_cases(5000, n_random_train)
+    test_cases = cases(seed + 1000, n_test) + random_cases(9000, n_random_test)
     X, y = [], []
     for i, (name, W, H, T) in enumerate(train_cases):
-        tab = measure_table(CHAINS[name], W, H, T, seed=seed + i)
+        tab = measure_table(case_ops(name), W, H, T, seed=seed + i, reps=reps)
         Xi, yi = table_rows(tab)
         X.append(Xi)
         y.append(yi)
@@ -240,11 +276,12 @@ def build(n_train=24, n_test=8, seed=5, steps=4000, out=WEIGHTS_PATH, log=print)
     evals = []
     Xt, yt = [], []
     for j, (name, W, H, T) in enumerate(test_cases):
-        tab = measure_table(CHAINS[name], W, H, T, seed=seed + 5000 + j)
+        ops = case_ops(name)
+        tab = measure_table(ops, W, H, T, seed=seed + 5000 + j, reps=reps)
         Xi, yi = table_rows(tab)
         Xt.append(Xi)
         yt.append(yi)
-        r = evaluate_case(CHAINS[name], W, H, T, params, tab)
+        r = evaluate_case(ops, W, H, T, params, tab)
         r["chain"] = name
         evals.append(r)
         log(f"[costmodel] test {name} {W}x{H}x{T}: learned {r['learned_ratio']:.3f} analytic "
@@ -252,12 +289,18 @@ def build(n_train=24, n_test=8, seed=5, steps=4000, out=WEIGHTS_PATH, log=print)
     Xt = np.concatenate(Xt)
     yt = np.concatenate(yt)
     test_rmse = float(np.sqrt(np.mean((predict(params, Xt) - yt) ** 2)))
-    geo = lambda k: float(np.exp(np.mean([math.log(r[k]) for r in evals])))
+    geo = lambda k, rs=None: float(np.exp(np.mean([math.log(r[k]) for r in (evals if rs is None else rs)])))
+    rnd = [r for r in evals if r["chain"].startswith("random:")]
+    fixed = [r for r in evals if not r["chain"].startswith("random:")]
     meta = {"train_samples": int(len(y)), "test_samples": int(len(yt)), "train_rmse_log_us": train_rmse,
             "test_rmse_log_us": test_rmse, "steps": steps, "final_loss": losses[-1][1],
             "train_cases": train_cases, "test_cases": test_cases, "evaluation": evals,
             "geomean_learned_over_best": geo("learned_ratio"), "geomean_analytic_over_best": geo("analytic_ratio"),
             "seconds": time.time() - t0}
+    for tag, rs in (("random", rnd), ("fixed", fixed)):
+        if rs:
+            meta[f"geomean_learned_over_best_{tag}"] = geo("learned_ratio", rs)
+            meta[f"geomean_analytic_over_best_{tag}"] = geo("analytic_ratio", rs)
     save_weights(params, meta, out)
     log(f"[costmodel] geomean learned/best {meta['geomean_learned_over_best']:.4f}, "
         f"analytic/best {meta['geomean_analytic_over_best']:.4f}; test rmse {test_rmse:.4f}")
@@ -265,6 +308,15 @@ def build(n_train=24, n_test=8, seed=5, steps=4000, out=WEIGHTS_PATH, log=print)
 
 
 if __name__ == "__main__":
-    import sys
-    out = sys.argv[1] if len(sys.argv) > 1 else WEIGHTS_PATH
-    build(out=out)
+    import argparse
+    ap = argparse.ArgumentParser(description="measure group times, train the cost network, evaluate")
+    ap.add_argument("out", nargs="?", default=WEIGHTS_PATH)
+    ap.add_argument("--fixed-train", type=int, default=24)
+    ap.add_argument("--fixed-test", type=int, default=8)
+    ap.add_argument("--random-train", type=int, default=0)
+    ap.add_argument("--random-test", type=int, default=0)
+    ap.add_argument("--steps", type=int, default=4000)
+    ap.add_argument("--reps", type=int, default=5)
+    a = ap.parse_args()
+    build(n_train=a.fixed_train, n_test=a.fixed_test, n_random_train=a.random_train, n_random_test=a.random_test,
+          steps=a.steps, reps=a.reps, out=a.out, log=lambda m: print(m, flush=True))

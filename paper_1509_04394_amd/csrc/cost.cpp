@@ -8,6 +8,7 @@
 #include <vector>
 
 #include "fz_internal.h"
+#include "generic.h"
 #include "rowgeom.h"
 
 namespace fz {
@@ -19,27 +20,40 @@ static double log2p(double v) { return log2(v > 0 ? v : 1e-30); }
 void group_features(const fz_plan& p, const Segment& g, float* f)
 {
     const int ch = p.chain, A = g.cfirst, B = g.clast;
-    int nwin = 0, ops = 0;
-    for (int j = A; j <= B; ++j) {
-        const OpInfo o = op_info(chain_op(ch, j));
-        nwin += o.r > 0;
-        ops += o.ops_per_px;
+    int nwin = 0, ops = 0, bytes_in, bytes_out;
+    if (p.generic) {
+        for (int j = g.first; j <= g.last; ++j) {
+            const fz_stage& s = p.stages[j];
+            const int kind = s.op == FZ_OP_POINT ? G_POINT : (s.op == FZ_OP_STENCIL ? G_STENCIL : G_BOX);
+            nwin += kind != G_POINT;
+            ops += generic_ops(kind, s.rx, s.ry, (int)s.param[0]);
+        }
+        bytes_in = dt_bytes(p.stages[g.first].in_dtype);
+        bytes_out = 4;
+    } else {
+        for (int j = A; j <= B; ++j) {
+            const OpInfo o = op_info(chain_op(ch, j));
+            nwin += o.r > 0;
+            ops += o.ops_per_px;
+        }
+        const OpInfo oa = op_info(chain_op(ch, A)), ob = op_info(chain_op(ch, B));
+        bytes_in = oa.in_ch * dt_bytes(oa.in_dt);
+        bytes_out = ob.out_ch * dt_bytes(ob.out_dt);
     }
-    const OpInfo oa = op_info(chain_op(ch, A)), ob = op_info(chain_op(ch, B));
     const double W = p.W, H = p.H, T = p.T;
     double recompute = 1.0;
     if (g.engine == FZ_ENGINE_TILE && g.tile_w > 0)
-        recompute = (double)(g.tile_w + 2 * g.halo) * (g.tile_h + 2 * g.halo) / ((double)g.tile_w * g.tile_h);
+        recompute = (double)(g.tile_w + 2 * g.halo) * (g.tile_h + 2 * g.halo_y) / ((double)g.tile_w * g.tile_h);
     if (g.engine == FZ_ENGINE_ROW)
         recompute = (double)g.nstrips * 64 * g.row_k / W * (g.tile_h + 2.0 * g.halo) / g.tile_h;
     const double temporal = g.halo_t > 0 ? (g.tpb + (double)g.halo_t) / g.tpb : 1.0;
     int i = 0;
     f[i++] = (float)((B - A + 1) / 9.0);
     f[i++] = (float)(nwin / 4.0);
-    f[i++] = (float)(g.halo / 6.0);
+    f[i++] = (float)((g.halo + g.halo_y) / 12.0);
     f[i++] = (float)g.halo_t;
-    f[i++] = (float)(oa.in_ch * dt_bytes(oa.in_dt) / 12.0);
-    f[i++] = (float)(ob.out_ch * dt_bytes(ob.out_dt) / 12.0);
+    f[i++] = (float)(bytes_in / 12.0);
+    f[i++] = (float)(bytes_out / 12.0);
     f[i++] = (float)(ops / 73.0);
     f[i++] = g.engine == FZ_ENGINE_TILE ? 1.0f : 0.0f;
     f[i++] = g.engine == FZ_ENGINE_ROW ? 1.0f : 0.0f;
@@ -53,6 +67,7 @@ void group_features(const fz_plan& p, const Segment& g, float* f)
     f[i++] = (float)log2p(recompute * temporal);
     f[i++] = (float)(log2p(W * H * T * ops) / 40.0);
     f[i++] = (g.engine == FZ_ENGINE_ROW && !g.row_gen) ? 1.0f : 0.0f;  // the Harris-chain row kernel
+    f[i++] = p.generic ? 1.0f : 0.0f;                                     // the generic-stage kernels
 }
 
 // Forward pass of the cost network (parameter layout of mlp.hip).

@@ -19,6 +19,7 @@ struct Segment {
     int tile_w, tile_h;
     int tpb;                // frames per workgroup
     int halo, halo_t;
+    int halo_y;             // halo along y (equal to halo except for generic groups with rx != ry)
     int lds_bytes;
     int streaming;
     int engine;             // FZ_ENGINE_TILE / ROW / STREAM
@@ -39,6 +40,11 @@ struct fz_plan {
     std::vector<fz_stage> stages;
     int n = 0;
     int chain = 0, offset = 0;
+    // generic chains (FZ_OP_STENCIL / BOX / POINT): chain = -1; the stencil
+    // weights copied at plan time and each stage's first weight
+    bool generic = false;
+    std::vector<float> gweights;
+    std::vector<int> gwoff;
     int W = 0, H = 0, T = 0;
     int lds_budget = 0;
     std::vector<double> cost;  // n x n, +inf where not allowed
@@ -65,8 +71,12 @@ fz_status fail(fz_status code, const std::string& msg);
 // Price of group [a..b] of plan p, with its tile / frames-per-block choice.
 Segment price_group(const fz_plan& p, int a, int b, int tile_req_w, int tile_req_h, int tpb_req, int engine_req);
 
+// Generic chains: price of group [a..b] (planner.cpp) and its launch (generic.hip)
+Segment price_generic(const fz_plan& p, int a, int b, int req_w, int req_h, int req_engine);
+int launch_generic(const fz_plan& p, const Segment& g, const void* in, void* out, void* stream);  // hipError_t
+
 // Learned prices (cost.cpp)
-constexpr int COST_FEATURES = 19;
+constexpr int COST_FEATURES = 20;
 void group_features(const fz_plan& p, const Segment& g, float* f);
 double mlp_predict(const float* prm, const float* x);
 Segment price_group_learned(const fz_plan& p, int a, int b, const float* prm, int req_w, int req_h, int req_tpb,

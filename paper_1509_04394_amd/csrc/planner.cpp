@@ -11,11 +11,13 @@
 #include <string.h>
 
 #include <algorithm>
+#include <cmath>
 #include <limits>
 #include <string>
 #include <vector>
 
 #include "fz_internal.h"
+#include "generic.h"
 #include "rowgeom.h"
 
 namespace fz {
@@ -61,8 +63,9 @@ Segment price_group(const fz_plan& p, int a, int b, int req_w, int req_h, int re
     s.tile = -1;
     for (int j = a + 1; j <= b; ++j)
         if (p.stages[j].dep == FZ_DEP_KK) return s;  // kernel-to-kernel: never fused (Sec. VI-A)
+    if (p.generic) return price_generic(p, a, b, req_w, req_h, req_engine);
     const int ch = p.chain, A = s.cfirst, B = s.clast;
-    s.halo = group_halo(ch, A, B);
+    s.halo = s.halo_y = group_halo(ch, A, B);
     s.halo_t = group_halo_t(ch, A, B);
     s.streaming = group_has_window(ch, A, B) ? 0 : 1;
     s.tpb = req_tpb > 0 ? req_tpb : (s.halo_t > 0 ? 8 : 1);
@@ -120,6 +123,58 @@ Segment price_group(const fz_plan& p, int a, int b, int req_w, int req_h, int re
     return s;
 }
 
+// A generic group: halos are the sums of its window radii per axis; a group
+// with a window stage runs in the generic LDS tile kernel (the tile of best
+// data utilisation, Eq. 3, that fits the budget), a group of point stages in
+// one streaming pass.  Cost: compulsory bytes, input once and output once.
+Segment price_generic(const fz_plan& p, int a, int b, int req_w, int req_h, int req_engine)
+{
+    (void)req_engine;  // one kernel family per kind of group
+    Segment s{};
+    s.first = s.cfirst = a;
+    s.last = s.clast = b;
+    s.cost = kInf;
+    s.tile = -1;
+    for (int j = a + 1; j <= b; ++j)
+        if (p.stages[j].dep == FZ_DEP_KK) return s;
+    int hx = 0, hy = 0, nwin = 0;
+    for (int j = a; j <= b; ++j)
+        if (p.stages[j].op != FZ_OP_POINT) {
+            hx += p.stages[j].rx;
+            hy += p.stages[j].ry;
+            ++nwin;
+        }
+    s.halo = hx;
+    s.halo_y = hy;
+    s.halo_t = 0;
+    s.tpb = 1;
+    s.streaming = nwin == 0;
+    if (s.streaming) {
+        s.engine = FZ_ENGINE_STREAM;
+    } else {
+        s.engine = FZ_ENGINE_TILE;
+        double best_du = -1.0;
+        for (int t = 0; t < N_TILES; ++t) {
+            const int tw = tile_w(t), th = tile_h(t);
+            if (req_w > 0 && (tw != req_w || th != req_h)) continue;
+            const int lds = generic_lds_bytes(tw, th, hx, hy, nwin);
+            if (lds > p.lds_budget) continue;
+            const double du = (double)tw * th / ((double)(tw + 2 * hx) * (th + 2 * hy));
+            if (du > best_du) {
+                best_du = du;
+                s.tile = t;
+                s.tile_w = tw;
+                s.tile_h = th;
+                s.lds_bytes = lds;
+            }
+        }
+        if (s.tile < 0) return s;
+    }
+    s.bytes_per_px = dt_bytes(p.stages[a].in_dtype) + 4.0;
+    s.cost = s.bytes_per_px * (double)p.W * p.H * p.T;
+    return s;
+}
+
 double partition_dp(const double* cost, int n, std::vector<int>& seg_last)
 {
     // best[e]: optimum over stages 0..e-1; key (cost, groups, cut list)
@@ -161,6 +216,9 @@ fz_plan* plan_for_size(const fz_plan& base, int W, int H, int T)
     p->n = base.n;
     p->chain = base.chain;
     p->offset = base.offset;
+    p->generic = base.generic;
+    p->gweights = base.gweights;
+    p->gwoff = base.gwoff;
     p->W = W;
     p->H = H;
     p->T = T;
@@ -192,6 +250,47 @@ fz_plan* plan_for_size(const fz_plan& base, int W, int H, int T)
 
 fz_plan::~fz_plan() { fz::release_batch(*this); }
 
+namespace fz {
+
+// Generic stages: one channel, f32 out, u8 or f32 into the first stage and
+// f32 into the others, radii in [0, G_MAX_R], finite stencil weights, a known
+// point kind with finite parameters.
+static fz_status validate_generic(const fz_stage* stages, int n)
+{
+    for (int i = 0; i < n; ++i) {
+        const fz_stage& s = stages[i];
+        const std::string where = "stage " + std::to_string(i) + ": ";
+        if (s.in_ch != 1 || s.out_ch != 1 || s.out_dtype != FZ_F32 || s.rt != 0)
+            return fail(FZ_E_INVALID, where + "generic stages have one channel, f32 output and no frame window");
+        if (!(s.in_dtype == FZ_F32 || (i == 0 && s.in_dtype == FZ_U8)))
+            return fail(FZ_E_INVALID, where + "input must be f32 (u8 allowed for the first stage)");
+        if (s.dep < FZ_DEP_TT || s.dep > FZ_DEP_KK) return fail(FZ_E_INVALID, where + "bad dependence type");
+        if (s.op == FZ_OP_POINT) {
+            const float k = s.param[0];
+            if (s.rx != 0 || s.ry != 0) return fail(FZ_E_INVALID, where + "a point stage has radius 0");
+            if (!(k >= 0.0f && k <= (float)FZ_POINT_CLAMP) || k != (float)(int)k)
+                return fail(FZ_E_INVALID, where + "unknown point kind");
+            if (!std::isfinite(s.param[1]) || !std::isfinite(s.param[2]))
+                return fail(FZ_E_INVALID, where + "point parameters must be finite");
+            if ((int)k == FZ_POINT_CLAMP && !(s.param[1] <= s.param[2]))
+                return fail(FZ_E_INVALID, where + "clamp needs a <= b");
+            continue;
+        }
+        if (s.rx < 0 || s.ry < 0 || s.rx > G_MAX_R || s.ry > G_MAX_R)
+            return fail(FZ_E_INVALID, where + "window radii must be in [0, " + std::to_string(G_MAX_R) + "]");
+        if ((s.rx > 0 || s.ry > 0) && s.dep == FZ_DEP_TT)
+            return fail(FZ_E_INVALID, where + "a window stage cannot have a thread-to-thread dependence");
+        if (s.op == FZ_OP_STENCIL) {
+            if (!s.weights) return fail(FZ_E_INVALID, where + "stencil without weights");
+            for (int q = 0; q < (2 * s.rx + 1) * (2 * s.ry + 1); ++q)
+                if (!std::isfinite(s.weights[q])) return fail(FZ_E_INVALID, where + "stencil weights must be finite");
+        }
+    }
+    return FZ_OK;
+}
+
+}  // namespace fz
+
 using namespace fz;
 
 extern "C" {
@@ -217,6 +316,11 @@ fz_status fz_stage_describe(int32_t op, fz_stage* out)
     if (op == FZ_OP_GAUSS5) out->param[0] = 1.0f;
     if (op == FZ_OP_HARRIS) out->param[0] = 0.04f;
     if (op == FZ_OP_THRESHOLD) out->param[0] = 1.0e8f;
+    if (op == FZ_OP_STENCIL || op == FZ_OP_BOX) out->rx = out->ry = 1;
+    if (op == FZ_OP_POINT) {
+        out->param[0] = (float)FZ_POINT_AFFINE;
+        out->param[1] = 1.0f;
+    }
     return FZ_OK;
 }
 
@@ -254,8 +358,17 @@ fz_status fz_plan_chain(const fz_stage* stages, int32_t n, const fz_plan_opts* o
         return fail(FZ_E_INVALID, "fz_plan_chain: a tile width needs a tile height");
     if (opts->tile_w < 0 || opts->tile_h < 0) return fail(FZ_E_INVALID, "fz_plan_chain: negative tile size");
 
+    int n_generic = 0;
+    for (int i = 0; i < n; ++i) n_generic += is_generic_op(stages[i].op);
+    if (n_generic > 0 && n_generic < n)
+        return fail(FZ_E_UNSUPPORTED, "fz_plan_chain: generic stages cannot be mixed with the fixed operations");
+    const bool generic = n_generic == n;
+    if (generic) {
+        fz_status st = validate_generic(stages, n);
+        if (st != FZ_OK) return st;
+    }
     // validate the descriptors against the operation registry (Sec. IV access patterns)
-    for (int i = 0; i < n; ++i) {
+    for (int i = 0; i < n && !generic; ++i) {
         const fz_stage& s = stages[i];
         const OpInfo o = op_info(s.op);
         if (o.op == 0) return fail(FZ_E_INVALID, "stage " + std::to_string(i) + ": unknown op");
@@ -268,8 +381,8 @@ fz_status fz_plan_chain(const fz_stage* stages, int32_t n, const fz_plan_opts* o
             return fail(FZ_E_INVALID, "stage " + std::to_string(i) + ": input does not match the previous output");
     }
     // locate the chain among the compiled sequences
-    int chain = -1, offset = -1;
-    for (int c = 0; c < N_CHAINS && chain < 0; ++c)
+    int chain = -1, offset = generic ? 0 : -1;
+    for (int c = 0; c < N_CHAINS && chain < 0 && !generic; ++c)
         for (int o = 0; o + n <= chain_len(c); ++o) {
             bool ok = true;
             for (int i = 0; i < n && ok; ++i) ok = chain_op(c, o + i) == stages[i].op;
@@ -279,11 +392,24 @@ fz_status fz_plan_chain(const fz_stage* stages, int32_t n, const fz_plan_opts* o
                 break;
             }
         }
-    if (chain < 0) return fail(FZ_E_UNSUPPORTED, "fz_plan_chain: stage sequence is not one the kernels are built for");
+    if (chain < 0 && !generic)
+        return fail(FZ_E_UNSUPPORTED, "fz_plan_chain: stage sequence is not one the kernels are built for");
 
     fz_plan* p = new fz_plan();
     p->stages.assign(stages, stages + n);
     p->n = n;
+    p->generic = generic;
+    if (generic) {
+        // the plan keeps its own copy of the stencil weights
+        p->gwoff.assign(n, 0);
+        for (int i = 0; i < n; ++i) {
+            p->gwoff[i] = (int)p->gweights.size();
+            if (stages[i].op == FZ_OP_STENCIL)
+                p->gweights.insert(p->gweights.end(), stages[i].weights,
+                                   stages[i].weights + (2 * stages[i].rx + 1) * (2 * stages[i].ry + 1));
+        }
+    }
+    for (fz_stage& st : p->stages) st.weights = nullptr;
     p->chain = chain;
     p->offset = offset;
     p->W = opts->width;

@@ -65,7 +65,9 @@ fz_status run_plan(const fz_plan& p, const void* d_in, void* d_out, fz_point* d_
         for (int j = g.first; j <= g.last; ++j) group_has_nms |= p.stages[j].op == FZ_OP_NMS3;
         if (!group_has_nms) sp.count = nullptr;
         hipError_t e;
-        if (g.engine == FZ_ENGINE_ROW) {
+        if (p.generic) {
+            e = (hipError_t)launch_generic(p, g, sp.in, sp.out, s);
+        } else if (g.engine == FZ_ENGINE_ROW) {
             RowParams rp{};
             rp.sp = sp;
             rp.nstrips = g.nstrips;

@@ -28,7 +28,9 @@ ENGINES = {"auto": FZ_ENGINE_AUTO, "tile": FZ_ENGINE_TILE, "row": FZ_ENGINE_ROW}
 OPS = {
     "rgb2gray": 1, "gauss5": 2, "sobel3": 3, "gradmag": 4, "products": 5,
     "boxsum5": 6, "harris": 7, "threshold": 8, "nms3": 9, "framediff": 10,
+    "stencil": 11, "box": 12, "point": 13,
 }
+POINT_KINDS = {"affine": 0, "abs": 1, "square": 2, "sqrtabs": 3, "clamp": 4}
 OP_NAMES = {v: k for k, v in OPS.items()}
 
 HARRIS_CHAIN = ["gauss5", "sobel3", "products", "boxsum5", "harris", "threshold", "nms3", "framediff"]
@@ -45,7 +47,8 @@ class FzError(RuntimeError):
 class fz_stage(ctypes.Structure):
     _fields_ = [("op", ctypes.c_int32), ("rx", ctypes.c_int32), ("ry", ctypes.c_int32), ("rt", ctypes.c_int32),
                 ("in_ch", ctypes.c_int32), ("out_ch", ctypes.c_int32), ("in_dtype", ctypes.c_int32),
-                ("out_dtype", ctypes.c_int32), ("dep", ctypes.c_int32), ("param", ctypes.c_float * 4)]
+                ("out_dtype", ctypes.c_int32), ("dep", ctypes.c_int32), ("param", ctypes.c_float * 4),
+                ("weights", ctypes.POINTER(ctypes.c_float))]
 
 
 class fz_point(ctypes.Structure):
@@ -294,31 +297,68 @@ def make_opts(W, H, T, partition="optimal", lds_budget=0, tile=None, frames_per_
     return o
 
 
-class Plan:
-    """A planned chain of named ops for videos of W x H x T.
+def generic_stages(spec, in_dtype="u8"):
+    """fz_stage descriptors for a generic chain given as tuples
+    ("stencil", rx, ry, w[2ry+1][2rx+1]), ("box", rx, ry) or ("point", kind, a, b)
+    (kind a name of POINT_KINDS).  The first stage reads `in_dtype` ("u8" or
+    "f32").  Returns (stages, keep): `keep` holds the weight arrays the
+    descriptors point to until the plan has copied them."""
+    stages, keep = [], []
+    for i, st in enumerate(spec):
+        s = fz_stage_describe(st[0])
+        if st[0] == "point":
+            s.param[0] = float(POINT_KINDS[st[1]])
+            s.param[1] = float(st[2]) if len(st) > 2 else 0.0
+            s.param[2] = float(st[3]) if len(st) > 3 else 0.0
+        else:
+            s.rx, s.ry = int(st[1]), int(st[2])
+            if st[0] == "stencil":
+                w = [float(v) for row in st[3] for v in row]
+                arr = (ctypes.c_float * len(w))(*w)
+                keep.append(arr)
+                s.weights = ctypes.cast(arr, ctypes.POINTER(ctypes.c_float))
+        if i == 0 and in_dtype == "u8":
+            s.in_dtype = FZ_U8
+        stages.append(s)
+    return stages, keep
 
+
+class Plan:
+    """A planned chain for videos of W x H x T.
+
+    ops: op names of the fixed chains, or generic stage tuples (see
+    generic_stages; `in_dtype` then gives the input type).
     partition: "optimal" (planner), "unfused" (one kernel per stage) or a list
     of cut positions (last stage index of every group but the final).
     params: optional dict op name -> param[0] (sigma, k or threshold).
     """
 
     def __init__(self, ops, W, H, T, partition="optimal", lds_budget=0, tile=None, frames_per_block=0,
-                 params=None, deps=None, engine="auto", band_h=0, cost_weights=None):
+                 params=None, deps=None, engine="auto", band_h=0, cost_weights=None, in_dtype="u8"):
         self.ops = list(ops)
         self.W, self.H, self.T = int(W), int(H), int(T)
-        stages = []
-        for i, op in enumerate(self.ops):
-            s = fz_stage_describe(op)
-            if params and op in params:
-                s.param[0] = float(params[op])
-            if deps and i in deps:
-                s.dep = int(deps[i])
-            stages.append(s)
+        self.generic = bool(self.ops) and isinstance(self.ops[0], tuple)
+        keep = None
+        if self.generic:
+            stages, keep = generic_stages(self.ops, in_dtype)
+            for i, s in enumerate(stages):
+                if deps and i in deps:
+                    s.dep = int(deps[i])
+        else:
+            stages = []
+            for i, op in enumerate(self.ops):
+                s = fz_stage_describe(op)
+                if params and op in params:
+                    s.param[0] = float(params[op])
+                if deps and i in deps:
+                    s.dep = int(deps[i])
+                stages.append(s)
         self.stages = stages
         self.opts = make_opts(W, H, T, partition, lds_budget, tile, frames_per_block,
                               cost_model="learned" if cost_weights is not None else "analytic",
                               engine=engine, band_h=band_h, cost_weights=cost_weights)
         self.handle = fz_plan_chain(stages, self.opts)
+        del keep  # the plan holds its own copy of the weights
         self._ws = None
 
     def __del__(self):
@@ -367,6 +407,9 @@ class Plan:
 
     def has_points(self):
         return any(s.op == OPS["nms3"] for s in self.stages)
+
+    def set_segment_config(self, i, engine="tile", tile=(0, 0), frames_per_block=0):
+        fz_plan_set_segment_config(self.handle, i, engine, tile[0], tile[1], frames_per_block)
 
     def alloc(self, device="cuda", point_capacity=1 << 20):
         """Allocate (out, points, count, workspace) tensors for a run."""

@@ -95,3 +95,76 @@ def compare_points(gpu, ora, exempt, tol_r):
         err = max(abs(float(g[k]) - float(o[k])) for k in common)
         assert err <= tol_r, f"point response error {err} > {tol_r}"
     return len(g), len(o)
+
+
+# ---------------------------------------------------------------- generic chains
+U32 = 2.0 ** -24  # unit roundoff of FP32
+
+
+def _gamma(n):
+    return n * U32 / (1.0 - n * U32)
+
+
+def generic_reference(oracle_lib, spec, volume):
+    """Oracle output of a generic chain and a per-pixel bound on the error of
+    any FP32 evaluation that rounds each stage's result once per operation in
+    the stated order.
+
+    The bound is propagated stage by stage from the oracle's exact
+    intermediates X and the incoming bound E (the input is exact, E = 0):
+      stencil, n taps, fused multiply-adds: E' = |w| * E + gamma_n |w| * (|X| + E)
+      window sum of nx x ny values (rows, then the row sums):
+                                           E' = box(E) + gamma_{nx+ny} box(|X| + E)
+      affine fma(a, x, b):                 E' = |a| E + u (|a| (|X| + E) + |b|)
+      abs, clamp (1-Lipschitz, exact):     E' = E
+      square:                              E' = E (2|X| + E) + u (|X| + E)^2
+      sqrt(|x|), correctly rounded:        E' = min(sqrt(E), E / sqrt|X|) + u sqrt(|X| + E)
+    where * is correlation with replicate borders and gamma_n = n u / (1 - n u)
+    (the standard bound for a recursive sum; Higham, Accuracy and Stability of
+    Numerical Algorithms, Sec. 3.1).  Returns (X_final, E_final), [T][H][W]
+    float64.
+    """
+    from scipy import ndimage
+
+    X = np.asarray(volume, np.float64)
+    E = np.zeros_like(X)
+    for st in spec:
+        Y = oracle_lib.gchain([st], X)
+        A = np.abs(X) + E
+        if st[0] == "stencil":
+            aw = np.abs(np.asarray(st[3], np.float64))
+            g = _gamma(aw.size)
+            corr = lambda Z: np.stack([ndimage.correlate(z, aw, mode="nearest") for z in Z])
+            E = corr(E) + g * corr(A)
+        elif st[0] == "box":
+            size = (2 * st[2] + 1, 2 * st[1] + 1)
+            area = size[0] * size[1]
+            g = _gamma(size[0] + size[1])
+            box = lambda Z: np.stack([ndimage.uniform_filter(z, size=size, mode="nearest") * area for z in Z])
+            E = box(E) + g * box(A)
+        else:
+            kind = st[1]
+            if kind == "affine":
+                a, b = abs(st[2]), abs(st[3])
+                E = a * E + U32 * (a * A + b)
+            elif kind == "square":
+                E = E * (2.0 * np.abs(X) + E) + U32 * A * A
+            elif kind == "sqrtabs":
+                with np.errstate(divide="ignore", invalid="ignore"):
+                    lip = np.where(np.abs(X) > 0, E / np.sqrt(np.abs(X)), np.inf)
+                E = np.minimum(np.sqrt(E), lip) + U32 * np.sqrt(A)
+            # abs and clamp leave E unchanged
+        X = Y
+    return X, E
+
+
+def assert_within_bound(gpu, ref, bound, what=""):
+    """|gpu - ref| <= bound (with 1% slack for evaluating the bound itself in
+    FP64), everywhere; reports the worst ratio."""
+    err = np.abs(np.asarray(gpu, np.float64) - ref)
+    lim = bound * 1.01 + 1e-30
+    bad = err > lim
+    assert not bad.any(), (f"{what}: {int(bad.sum())} pixels outside the FP32 error bound, worst "
+                           f"err {err[bad].max():.3e} at bound {lim[bad][np.argmax(err[bad])]:.3e}")
+    nz = bound > 0
+    return float((err[nz] / bound[nz]).max()) if nz.any() else 0.0

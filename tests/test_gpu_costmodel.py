@@ -1,7 +1,7 @@
 """The learned price against the analytic one, measured.
 
 For held-out workloads (seeded chain, frame size and length not used in
-training) every group is timed in every configuration; the best partition
+training; fixed chains and random generic chains) every group is timed in every configuration; the best partition
 under measured prices (exact DP over the table) is the reference.  The
 partition the planner chooses with the trained network must be within 5% of
 it (geometric mean), and the test prints what that gains over the planner's
@@ -29,10 +29,11 @@ def weights():
 
 def test_learned_partitions_near_best_measured(weights):
     params, meta = weights
-    cases = costmodel.cases(seed=424242, n_cases=4)
+    # held out: fixed chains at unseen sizes, random generic chains of unseen seeds
+    cases = costmodel.cases(seed=424242, n_cases=4) + costmodel.random_cases(9500, 3)
     rows = []
     for name, W, H, T in cases:
-        ops = costmodel.CHAINS[name]
+        ops = costmodel.case_ops(name)
         table = costmodel.measure_table(ops, W, H, T, seed=77)
         r = costmodel.evaluate_case(ops, W, H, T, params, table)
         rows.append(r)
