@@ -123,8 +123,9 @@ typedef struct fz_plan_opts {
     int32_t n_cuts;                 /* FZ_PART_EXPLICIT: number of entries in cuts */
     const int32_t* cuts;            /* FZ_PART_EXPLICIT: last stage index of every group but the final,
                                        strictly increasing, each in [0, n-2] */
-    int32_t cost_model;             /* FZ_COST_ANALYTIC (bytes) or FZ_COST_LEARNED (predicted microseconds);
-                                       FZ_COST_MEASURED is not implemented in the library */
+    int32_t cost_model;             /* FZ_COST_ANALYTIC (bytes), FZ_COST_LEARNED (predicted microseconds) or
+                                       FZ_COST_MEASURED (planned with bytes; fz_plan_measure then
+                                       replaces the prices with measured microseconds) */
     int32_t tile_w, tile_h;         /* output box of one workgroup; 0 = planner's choice */
     int32_t frames_per_block;       /* frames one workgroup marches through; 0 = planner's choice */
     int32_t engine;                 /* FZ_ENGINE_*: kernel family for groups that have a choice */
@@ -209,6 +210,26 @@ fz_status fz_partition_min(const double* cost, int32_t n, int32_t* seg_last, int
 
 /* Device workspace the run needs for intermediates between groups. */
 size_t fz_workspace_bytes(const fz_plan* plan);
+
+/* Measured prices (Sec. VI-A: the price of a candidate fused kernel is its
+ * execution time).  Runs every contiguous group of the plan in every kernel
+ * configuration it can run in (the planner's choice and each compiled tile)
+ * on the device: the groups starting at stage a read the chain's real input
+ * of stage a, made from d_in (the plan's input video, caller-owned, layout of
+ * fz_run_chain) by the stages before a.  Each configuration runs once untimed
+ * and `reps` (1..1000) times bracketed by HIP events on `stream`; its price
+ * is the median in microseconds.  Then each group takes its fastest
+ * configuration and the partition becomes the exact optimum over those
+ * prices (fz_plan_cost returns microseconds from then on), whatever partition
+ * mode the plan was made with.  d_workspace: caller-owned device memory of at
+ * least fz_measure_workspace_bytes() bytes (three buffers of the largest
+ * stage output and a counter); its contents are scratch.  Blocks until the
+ * stream has drained.  FZ_E_WORKSPACE if the workspace is too small (checked
+ * before any launch), FZ_E_HIP on a failed launch or event call; the plan is
+ * unchanged unless FZ_OK is returned.  A cached batch graph is dropped. */
+size_t fz_measure_workspace_bytes(const fz_plan* plan);
+fz_status fz_plan_measure(fz_plan* plan, const void* d_in, void* d_workspace, size_t ws_bytes, int32_t reps,
+                          void* stream);
 
 /* Run the planned chain on the device (Sec. VI-B, Algorithm 1 per group):
  *   d_in:   input video in the layout of the first stage's input type

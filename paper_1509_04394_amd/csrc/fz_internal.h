@@ -90,6 +90,10 @@ fz_status run_plan(const fz_plan& p, const void* d_in, void* d_out, fz_point* d_
                    uint32_t cap, void* d_ws, size_t ws_bytes, void* stream);
 size_t workspace_bytes(const fz_plan& p);
 
+// Measured prices (measure.hip)
+size_t measure_workspace_bytes(const fz_plan& p);
+fz_status plan_measure(fz_plan& p, const void* d_in, void* ws, size_t ws_bytes, int reps, void* stream);
+
 // The same partition re-priced for another video size (batch clips).
 fz_plan* plan_for_size(const fz_plan& base, int W, int H, int T);
 // Batch (batch.hip)

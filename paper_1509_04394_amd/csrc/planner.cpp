@@ -344,9 +344,8 @@ fz_status fz_plan_chain(const fz_stage* stages, int32_t n, const fz_plan_opts* o
         return fail(FZ_E_INVALID, "fz_plan_chain: width, height and frames must be positive");
     if ((int64_t)opts->width * opts->height > (int64_t)1 << 28)
         return fail(FZ_E_INVALID, "fz_plan_chain: frame larger than 2^28 pixels");
-    if (opts->cost_model == FZ_COST_MEASURED)
-        return fail(FZ_E_UNSUPPORTED, "fz_plan_chain: the measured cost model is not implemented in the library");
-    if (opts->cost_model != FZ_COST_ANALYTIC && opts->cost_model != FZ_COST_LEARNED)
+    if (opts->cost_model != FZ_COST_ANALYTIC && opts->cost_model != FZ_COST_LEARNED &&
+        opts->cost_model != FZ_COST_MEASURED)
         return fail(FZ_E_INVALID, "fz_plan_chain: unknown cost model");
     if (opts->cost_model == FZ_COST_LEARNED && (!opts->cost_weights || opts->cost_n_features != COST_FEATURES))
         return fail(FZ_E_INVALID, "fz_plan_chain: the learned cost model needs weights for " +
@@ -592,6 +591,16 @@ fz_status fz_plan_group_cost(const fz_plan* plan, int32_t a, int32_t b, double* 
 }
 
 size_t fz_workspace_bytes(const fz_plan* plan) { return plan ? workspace_bytes(*plan) : 0; }
+
+size_t fz_measure_workspace_bytes(const fz_plan* plan) { return plan ? measure_workspace_bytes(*plan) : 0; }
+
+fz_status fz_plan_measure(fz_plan* plan, const void* d_in, void* d_workspace, size_t ws_bytes, int32_t reps,
+                          void* stream)
+{
+    if (!plan || !d_in) return fail(FZ_E_INVALID, "fz_plan_measure: null plan or input");
+    if (reps < 1 || reps > 1000) return fail(FZ_E_INVALID, "fz_plan_measure: reps must be in [1, 1000]");
+    return plan_measure(*plan, d_in, d_workspace, ws_bytes, reps, stream);
+}
 
 size_t fz_batch_workspace_bytes(const fz_plan* plan, const fz_clip* clips, int32_t n_clips)
 {

@@ -79,6 +79,16 @@ __device__ __forceinline__ void extend_row(const float (&v)[K], float (&e)[K + 2
     }
 }
 
+// Raw buffer over `bytes` bytes at `base`: a store whose offset is at or past
+// `bytes` is dropped by the hardware, which lets every lane issue its store
+// with no divergent branch (columns outside the strip's output range get an
+// out-of-range offset).  Word 3 selects 32-bit raw access.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t out_rsrc(void* base, uint32_t bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(base, (short)0, (int)bytes, 0x00020000);
+}
+constexpr int DROP = 0x7fffffff;  // an offset past any frame
+
 template <int K>
 __device__ __forceinline__ void copy_row(float (&d)[K], const float (&s)[K])
 {
@@ -243,10 +253,12 @@ __device__ __forceinline__ void row_step(RowState<K, RGB>& st, const RowCtx& c, 
             outbits = bits ^ prev;
         }
         if (c.real) {
-            uint8_t* o = c.out_frame + (size_t)rn * c.W;
+            const __amdgpu_buffer_rsrc_t r = out_rsrc(c.out_frame, (uint32_t)(c.W * c.Hf));
+            const int row_off = rn * c.W + c.lane_out;
 #pragma unroll
             for (int k = 0; k < K; ++k)
-                if (c.valid >> k & 1u) o[c.lane_out + k] = (outbits >> k & 1u) ? (uint8_t)255 : (uint8_t)0;
+                __builtin_amdgcn_raw_buffer_store_b8((outbits >> k & 1u) ? (uint8_t)255 : (uint8_t)0, r,
+                                                     (c.valid >> k & 1u) ? row_off + k : DROP, 0, 0);
         }
     }
     // bottom replicate: after the last frame row, copy it into the next slot of

@@ -141,29 +141,33 @@ __device__ __forceinline__ void apply_points_row(float (&v)[3][K], Fn&& f)
     }
 }
 
-// Store the final row (or its frame difference) for the valid columns.
+// Store the final row (or its frame difference) for the valid columns; the
+// other lanes' stores get an out-of-range offset and are dropped.
 template <int CH, int A, int B, int K>
 __device__ __forceinline__ void gen_store(const GenCtx& c, int row, const float (&v)[3][K], uint32_t outbits)
 {
     using I = GenInfo<CH, A, B>;
-    const size_t base = (size_t)c.t * c.plane + (size_t)row * c.W + c.lane_in;
+    const size_t fbase = (size_t)c.t * c.plane;
+    const int off = row * c.W + c.lane_in;
     if constexpr (I::DIFF || I::OUT.out_dt == FZ_U8) {
-        uint8_t* o = (uint8_t*)c.out + base;
+        const __amdgpu_buffer_rsrc_t r = out_rsrc((uint8_t*)c.out + fbase, (uint32_t)c.plane);
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-            if (!(c.valid >> k & 1u)) continue;
+            uint8_t b;
             if constexpr (I::DIFF || I::OUT.op == FZ_OP_NMS3)
-                o[k] = (outbits >> k & 1u) ? (uint8_t)255 : (uint8_t)0;
+                b = (outbits >> k & 1u) ? (uint8_t)255 : (uint8_t)0;
             else
-                o[k] = (uint8_t)(uint32_t)v[0][k];
+                b = (uint8_t)(uint32_t)v[0][k];
+            __builtin_amdgcn_raw_buffer_store_b8(b, r, (c.valid >> k & 1u) ? off + k : DROP, 0, 0);
         }
     } else {
 #pragma unroll
         for (int ch = 0; ch < I::OUT_CH; ++ch) {
-            float* o = (float*)c.out + ch * c.vol + base;
+            const __amdgpu_buffer_rsrc_t r = out_rsrc((float*)c.out + ch * c.vol + fbase, (uint32_t)(c.plane * 4));
 #pragma unroll
             for (int k = 0; k < K; ++k)
-                if (c.valid >> k & 1u) o[k] = v[ch][k];
+                __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v[ch][k]), r,
+                                                      (c.valid >> k & 1u) ? 4 * (off + k) : DROP, 0, 0);
         }
     }
 }

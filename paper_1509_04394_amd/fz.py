@@ -97,6 +97,9 @@ SIGNATURES = [
                                           ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                                           ctypes.POINTER(ctypes.c_double)]),
     ("fz_workspace_bytes", ctypes.c_size_t, [ctypes.c_void_p]),
+    ("fz_measure_workspace_bytes", ctypes.c_size_t, [ctypes.c_void_p]),
+    ("fz_plan_measure", ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
+                                         ctypes.c_int32, ctypes.c_void_p]),
     ("fz_run_chain", ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                       ctypes.c_void_p, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_size_t,
                                       ctypes.c_void_p]),
@@ -216,6 +219,14 @@ def fz_partition_min(cost) -> tuple[float, list[int]]:
 
 def fz_workspace_bytes(plan) -> int:
     return int(lib().fz_workspace_bytes(plan))
+
+
+def fz_measure_workspace_bytes(plan) -> int:
+    return int(lib().fz_measure_workspace_bytes(plan))
+
+
+def fz_plan_measure(plan, d_in, d_workspace, ws_bytes, reps, stream):
+    _check(lib().fz_plan_measure(plan, d_in, d_workspace, ws_bytes, reps, stream))
 
 
 def fz_run_chain(plan, d_in, d_out, d_points, d_point_count, point_capacity, d_workspace, ws_bytes, stream):
@@ -407,6 +418,18 @@ class Plan:
 
     def has_points(self):
         return any(s.op == OPS["nms3"] for s in self.stages)
+
+    def measure(self, x, reps=3, stream=None):
+        """Replace the prices by measured microseconds on input `x` (a device
+        tensor of input_shape()) and re-plan (fz_plan_measure)."""
+        import torch
+        if tuple(x.shape) != self.input_shape() or not x.is_cuda or not x.is_contiguous():
+            raise ValueError("input must be a contiguous CUDA tensor of the plan's input shape")
+        ws = torch.empty((fz_measure_workspace_bytes(self.handle),), dtype=torch.uint8, device=x.device)
+        if stream is None:
+            stream = torch.cuda.current_stream(x.device).cuda_stream
+        fz_plan_measure(self.handle, x.data_ptr(), ws.data_ptr(), ws.numel(), int(reps), stream)
+        del ws
 
     def set_segment_config(self, i, engine="tile", tile=(0, 0), frames_per_block=0):
         fz_plan_set_segment_config(self.handle, i, engine, tile[0], tile[1], frames_per_block)

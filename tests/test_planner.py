@@ -216,3 +216,24 @@ def test_segment_config_override():
         fz.fz_plan_set_segment_config(p.handle, 3, "auto")
     # the plan's total follows the group prices
     assert p.cost == sum(s.cost for s in p.segment_info())
+
+
+def test_measure_workspace_and_errors_before_any_launch():
+    plan = fz.Plan(fz.RGB_HARRIS_CHAIN, 800, 600, 10)
+    # three buffers of the largest stage output (3 x f32 = 12 B/px) and a counter
+    slot = (800 * 600 * 10 * 12 + 255) // 256 * 256
+    assert fz.fz_measure_workspace_bytes(plan.handle) == 3 * slot + 256
+    fake = 0x1000  # never dereferenced: the checks come first
+    with pytest.raises(fz.FzError) as e:
+        fz.fz_plan_measure(plan.handle, fake, fake, 100, 3, None)
+    assert e.value.code == fz.FZ_E_WORKSPACE
+    with pytest.raises(fz.FzError) as e:
+        fz.fz_plan_measure(plan.handle, fake, fake, 1 << 40, 0, None)
+    assert e.value.code == fz.FZ_E_INVALID
+    with pytest.raises(fz.FzError) as e:
+        fz.fz_plan_measure(plan.handle, None, fake, 1 << 40, 3, None)
+    assert e.value.code == fz.FZ_E_INVALID
+    # the measured model plans with bytes until measured
+    p2 = fz.fz_plan_chain(plan.stages, fz.make_opts(800, 600, 10, cost_model="measured"))
+    assert fz.fz_plan_cost(p2) == plan.cost
+    fz.fz_plan_destroy(p2)
