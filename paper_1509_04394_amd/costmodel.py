@@ -8,7 +8,7 @@ prediction is learned from the planner's own kernels:
   configuration the planner may choose (row-marching, LDS tile with each
   compiled tile, streaming), is timed on the GPU with HIP events on real
   intermediate inputs; each sample is (group features, microseconds);
-* ``train``: the library's HIP kernels (``fz_mlp_loss_grad``, ``fz_mlp_adam_step``)
+* ``train_mlp``: the library's HIP kernels (``fz_mlp_loss_grad``, ``fz_mlp_adam_step``)
   fit the cost network to log(microseconds), full batch, Adam;
 * ``evaluate_case``: the partitions chosen with learned prices and with the
   analytic (bytes) prices, timed from the measured table, against the best
@@ -130,8 +130,11 @@ def init_params(F, seed):
     return np.concatenate([W1.ravel(), np.zeros(H), W2.ravel(), np.full(H, 0.01), W3, [0.0]]).astype(np.float32)
 
 
-def train(X, y, steps=4000, lr=3e-3, seed=0, log_every=0):
-    """Full-batch Adam with the library's GPU kernels; returns (params, losses)."""
+def train_mlp(X, y, steps=4000, lr=3e-3, seed=0, log_every=0, batch=0, X_val=None, y_val=None, eval_every=250):
+    """Adam with the library's GPU kernels: full batch (batch = 0) or mini-batches
+    of `batch` rows drawn from a seeded shuffle.  With a validation set, the
+    parameters of least validation loss (checked every `eval_every` steps) are
+    returned.  Returns (params, {"best_step", "val": [(step, loss)]})."""
     import torch
     dev = torch.device("cuda:0")
     F = X.shape[1]
@@ -139,26 +142,46 @@ def train(X, y, steps=4000, lr=3e-3, seed=0, log_every=0):
     P = fz.fz_mlp_param_count(F)
     p0 = init_params(F, seed)
     p0[-1] = float(np.mean(y))  # start the output bias at the mean target
+    rng = np.random.default_rng(seed)
+    perm = rng.permutation(n) if batch else np.arange(n)
     dp = torch.tensor(p0, device=dev)
-    dx = torch.tensor(X, device=dev)
-    dt = torch.tensor(y, device=dev)
+    dx = torch.tensor(np.ascontiguousarray(X[perm]), device=dev)
+    dt = torch.tensor(np.ascontiguousarray(y[perm]), device=dev)
+    B = min(batch, n) if batch else n
     g = torch.empty(P, device=dev)
     L = torch.empty(1, device=dev)
     m = torch.zeros(P, device=dev)
     v = torch.zeros(P, device=dev)
-    ws = torch.empty(fz.fz_mlp_workspace_bytes(F, n), dtype=torch.uint8, device=dev)
+    ws = torch.empty(fz.fz_mlp_workspace_bytes(F, B), dtype=torch.uint8, device=dev)
+    if X_val is not None:
+        dxv = torch.tensor(np.asarray(X_val, np.float32), device=dev)
+        dyv = torch.tensor(np.asarray(y_val, np.float32), device=dev)
+        gv = torch.empty(P, device=dev)
+        Lv = torch.empty(1, device=dev)
+        wsv = torch.empty(fz.fz_mlp_workspace_bytes(F, dxv.shape[0]), dtype=torch.uint8, device=dev)
     s = torch.cuda.current_stream(dev).cuda_stream
-    losses = []
+    nb = max(1, n // B)
+    best, best_step, curve = None, 0, []
     for step in range(1, steps + 1):
-        fz.fz_mlp_loss_grad(dp.data_ptr(), F, dx.data_ptr(), dt.data_ptr(), n, g.data_ptr(), L.data_ptr(),
-                            ws.data_ptr(), ws.numel(), s)
+        off = ((step - 1) % nb) * B
+        fz.fz_mlp_loss_grad(dp.data_ptr(), F, dx[off:off + B].data_ptr(), dt[off:off + B].data_ptr(), B,
+                            g.data_ptr(), L.data_ptr(), ws.data_ptr(), ws.numel(), s)
         fz.fz_mlp_adam_step(dp.data_ptr(), g.data_ptr(), m.data_ptr(), v.data_ptr(), P, step, lr, 0.9, 0.999, 1e-8,
                             s)
-        if step % 50 == 0 or step == 1:
-            losses.append((step, L.item()))
-            if log_every and step % log_every == 0:
-                print(f"[costmodel] step {step} loss {losses[-1][1]:.5f}", flush=True)
-    return dp.cpu().numpy(), losses
+        if X_val is not None and (step % eval_every == 0 or step == steps):
+            fz.fz_mlp_loss_grad(dp.data_ptr(), F, dxv.data_ptr(), dyv.data_ptr(), dxv.shape[0], gv.data_ptr(),
+                                Lv.data_ptr(), wsv.data_ptr(), wsv.numel(), s)
+            lv = Lv.item()
+            curve.append((step, lv))
+            if best is None or lv < best[0]:
+                best = (lv, dp.clone())
+                best_step = step
+            if log_every:
+                print(f"[costmodel] step {step} val loss {lv:.5f}", flush=True)
+        elif log_every and step % log_every == 0:
+            print(f"[costmodel] step {step} loss {L.item():.5f}", flush=True)
+    params = (best[1] if best is not None else dp).cpu().numpy()
+    return params, {"best_step": best_step if best is not None else steps, "val": curve}
 
 
 def predict(params, X):
@@ -254,69 +277,135 @@ def case_ops(name):
     return CHAINS[name]
 
 
-def build(n_train=24, n_test=8, seed=5, steps=4000, out=WEIGHTS_PATH, log=print, n_random_train=0,
-          n_random_test=0, reps=5):
-    """Measure, train and evaluate; write the weights (with the evaluation) to `out`.
-    Random generic chains are seeded from 5000 (training) and 9000 (test)."""
+def save_table(path, case, table):
+    """Write one case's measured table (.npz: configuration keys, features, microseconds)."""
+    keys = np.array([list(k) for k in table], np.int32).reshape(-1, 5)
+    feats = np.array([f for f, _ in table.values()], np.float32).reshape(len(table), -1)
+    us = np.array([u for _, u in table.values()], np.float64)
+    tmp = path + ".tmp.npz"
+    np.savez_compressed(tmp, case=np.array([str(c) for c in case]), keys=keys, feats=feats, us=us,
+                        n_features=np.int32(fz.fz_cost_n_features()))
+    os.replace(tmp, path)
+
+
+def load_table(path):
+    d = np.load(path, allow_pickle=False)
+    if int(d["n_features"]) != fz.fz_cost_n_features():
+        raise ValueError(f"{path}: measured for another feature set")
+    c = [str(v) for v in d["case"]]
+    case = (c[0], int(c[1]), int(c[2]), int(c[3]))
+    table = {tuple(int(v) for v in k): (list(map(float, f)), float(u))
+             for k, f, u in zip(d["keys"], d["feats"], d["us"])}
+    return case, table
+
+
+def campaign():
+    """The measured workloads, split by chain: training = the fixed chains at 24
+    seeded sizes and 4000 random generic chains (seeds 5000..8999); validation =
+    500 random chains (9000..9499), used to pick the number of training steps;
+    test = the fixed chains at 8 other sizes and 500 random chains (9500..9999)."""
+    return {"train": cases(5, 24) + random_cases(5000, 4000),
+            "val": random_cases(9000, 500),
+            "test": cases(1005, 8) + random_cases(9500, 500)}
+
+
+def measure_cases(directory, split, first=0, count=None, reps=3, max_seconds=None, log=print):
+    """Measure cases [first, first+count) of a campaign split into
+    directory/<split>_NNNN.npz, skipping files that exist; stops starting new
+    cases after max_seconds.  Returns True when the range is complete."""
+    os.makedirs(directory, exist_ok=True)
     t0 = time.time()
-    train_cases = cases(seed, n_train) + random_cases(5000, n_random_train)
-    test_cases = cases(seed + 1000, n_test) + random_cases(9000, n_random_test)
-    X, y = [], []
-    for i, (name, W, H, T) in enumerate(train_cases):
-        tab = measure_table(case_ops(name), W, H, T, seed=seed + i, reps=reps)
-        Xi, yi = table_rows(tab)
-        X.append(Xi)
-        y.append(yi)
-        log(f"[costmodel] train case {i} {name} {W}x{H}x{T}: {len(yi)} samples ({time.time() - t0:.0f} s)")
-    X = np.concatenate(X)
-    y = np.concatenate(y)
-    params, losses = train(X, y, steps=steps, seed=seed)
-    train_rmse = float(np.sqrt(np.mean((predict(params, X) - y) ** 2)))
-    log(f"[costmodel] trained on {len(y)} samples, rmse(log us) {train_rmse:.4f}")
+    todo = campaign()[split]
+    last = len(todo) if count is None else min(len(todo), first + count)
+    base = {"train": 0, "val": 20000, "test": 40000}[split]
+    done = 0
+    for i in range(first, last):
+        path = os.path.join(directory, f"{split}_{i:04d}.npz")
+        if os.path.exists(path):
+            continue
+        if max_seconds is not None and time.time() - t0 > max_seconds:
+            log(f"[costmodel] time budget reached at {split} {i}; {done} cases measured in this call")
+            return False
+        name, W, H, T = todo[i]
+        tab = measure_table(case_ops(name), W, H, T, seed=5 + base + i, reps=reps)
+        save_table(path, todo[i], tab)
+        done += 1
+        if done % 25 == 0 or i == last - 1:
+            log(f"[costmodel] {split} {i} {name} {W}x{H}x{T}: {len(tab)} samples ({time.time() - t0:.0f} s)")
+    return True
+
+
+def _load_split(directory, split):
+    files = sorted(f for f in os.listdir(directory) if f.startswith(split + "_") and f.endswith(".npz"))
+    return [load_table(os.path.join(directory, f)) for f in files]
+
+
+def _rows(tables):
+    X = np.concatenate([table_rows(t)[0] for _, t in tables])
+    y = np.concatenate([table_rows(t)[1] for _, t in tables])
+    return X, y
+
+
+def train_from_tables(directory, steps=6000, batch=8192, seed=5, out=WEIGHTS_PATH, log=print):
+    """Train on the training split (mini-batch Adam on the GPU kernels), keep
+    the parameters of least validation loss, evaluate plan quality on the test
+    split, and write the weights with the evaluation to `out`."""
+    t0 = time.time()
+    train, val, test = (_load_split(directory, s) for s in ("train", "val", "test"))
+    X, y = _rows(train)
+    Xv, yv = _rows(val) if val else (X, y)
+    params, curve = train_mlp(X, y, steps=steps, seed=seed, batch=batch, X_val=Xv, y_val=yv)
+    rmse = lambda A, b: float(np.sqrt(np.mean((predict(params, A) - b) ** 2)))
+    train_rmse, val_rmse = rmse(X, y), rmse(Xv, yv)
+    log(f"[costmodel] {len(y)} training rows from {len(train)} chains; rmse(log us) train {train_rmse:.4f} "
+        f"val {val_rmse:.4f} ({time.time() - t0:.0f} s)")
     evals = []
-    Xt, yt = [], []
-    for j, (name, W, H, T) in enumerate(test_cases):
-        ops = case_ops(name)
-        tab = measure_table(ops, W, H, T, seed=seed + 5000 + j, reps=reps)
-        Xi, yi = table_rows(tab)
-        Xt.append(Xi)
-        yt.append(yi)
-        r = evaluate_case(ops, W, H, T, params, tab)
+    for (name, W, H, T), tab in test:
+        r = evaluate_case(case_ops(name), W, H, T, params, tab)
         r["chain"] = name
         evals.append(r)
-        log(f"[costmodel] test {name} {W}x{H}x{T}: learned {r['learned_ratio']:.3f} analytic "
-            f"{r['analytic_ratio']:.3f} of best")
-    Xt = np.concatenate(Xt)
-    yt = np.concatenate(yt)
-    test_rmse = float(np.sqrt(np.mean((predict(params, Xt) - yt) ** 2)))
-    geo = lambda k, rs=None: float(np.exp(np.mean([math.log(r[k]) for r in (evals if rs is None else rs)])))
-    rnd = [r for r in evals if r["chain"].startswith("random:")]
-    fixed = [r for r in evals if not r["chain"].startswith("random:")]
-    meta = {"train_samples": int(len(y)), "test_samples": int(len(yt)), "train_rmse_log_us": train_rmse,
-            "test_rmse_log_us": test_rmse, "steps": steps, "final_loss": losses[-1][1],
-            "train_cases": train_cases, "test_cases": test_cases, "evaluation": evals,
-            "geomean_learned_over_best": geo("learned_ratio"), "geomean_analytic_over_best": geo("analytic_ratio"),
-            "seconds": time.time() - t0}
-    for tag, rs in (("random", rnd), ("fixed", fixed)):
+    Xt, yt = _rows(test)
+    test_rmse = rmse(Xt, yt)
+    geo = lambda k, rs: float(np.exp(np.mean([math.log(r[k]) for r in rs])))
+    worst = lambda k, rs: float(max(r[k] for r in rs))
+    meta = {"train_chains": len(train), "val_chains": len(val), "test_chains": len(test),
+            "train_rows": int(len(y)), "val_rows": int(len(yv)), "test_rows": int(len(yt)),
+            "rmse_log_us": {"train": train_rmse, "val": val_rmse, "test": test_rmse},
+            "steps": steps, "batch": batch, "best_step": curve["best_step"], "val_curve": curve["val"],
+            "test_cases": [list(c) for c, _ in test], "evaluation": evals, "seconds": time.time() - t0}
+    for tag, rs in (("all", evals), ("random", [r for r in evals if r["chain"].startswith("random:")]),
+                    ("fixed", [r for r in evals if not r["chain"].startswith("random:")])):
         if rs:
             meta[f"geomean_learned_over_best_{tag}"] = geo("learned_ratio", rs)
             meta[f"geomean_analytic_over_best_{tag}"] = geo("analytic_ratio", rs)
+            meta[f"worst_learned_over_best_{tag}"] = worst("learned_ratio", rs)
+            meta[f"worst_analytic_over_best_{tag}"] = worst("analytic_ratio", rs)
     save_weights(params, meta, out)
-    log(f"[costmodel] geomean learned/best {meta['geomean_learned_over_best']:.4f}, "
-        f"analytic/best {meta['geomean_analytic_over_best']:.4f}; test rmse {test_rmse:.4f}")
+    log(f"[costmodel] test plans, geomean over best: learned {meta['geomean_learned_over_best_all']:.4f}, "
+        f"analytic {meta['geomean_analytic_over_best_all']:.4f}; test rmse {test_rmse:.4f}")
     return params, meta
 
 
 if __name__ == "__main__":
     import argparse
     ap = argparse.ArgumentParser(description="measure group times, train the cost network, evaluate")
-    ap.add_argument("out", nargs="?", default=WEIGHTS_PATH)
-    ap.add_argument("--fixed-train", type=int, default=24)
-    ap.add_argument("--fixed-test", type=int, default=8)
-    ap.add_argument("--random-train", type=int, default=0)
-    ap.add_argument("--random-test", type=int, default=0)
-    ap.add_argument("--steps", type=int, default=4000)
-    ap.add_argument("--reps", type=int, default=5)
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    m = sub.add_parser("measure", help="measure a range of a campaign split into a directory (resumable)")
+    m.add_argument("directory")
+    m.add_argument("split", choices=["train", "val", "test"])
+    m.add_argument("--first", type=int, default=0)
+    m.add_argument("--count", type=int, default=None)
+    m.add_argument("--reps", type=int, default=3)
+    m.add_argument("--max-seconds", type=float, default=None)
+    t = sub.add_parser("train", help="train and evaluate from a directory of tables")
+    t.add_argument("directory")
+    t.add_argument("out", nargs="?", default=WEIGHTS_PATH)
+    t.add_argument("--steps", type=int, default=6000)
+    t.add_argument("--batch", type=int, default=8192)
     a = ap.parse_args()
-    build(n_train=a.fixed_train, n_test=a.fixed_test, n_random_train=a.random_train, n_random_test=a.random_test,
-          steps=a.steps, reps=a.reps, out=a.out, log=lambda m: print(m, flush=True))
+    say = lambda msg: print(msg, flush=True)
+    if a.cmd == "measure":
+        complete = measure_cases(a.directory, a.split, a.first, a.count, a.reps, a.max_seconds, log=say)
+        say(f"[costmodel] {a.split} measurement {'complete' if complete else 'incomplete'}")
+    else:
+        train_from_tables(a.directory, a.steps, a.batch, 5, a.out, log=say)
