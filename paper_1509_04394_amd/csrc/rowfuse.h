@@ -122,14 +122,36 @@ struct RowCtx {
     uint8_t* prev;            // LDS previous-frame mask bits of this wavefront (DIFF)
 };
 
+// NB consecutive bytes at byte offset voff + soff of buffer r into raw[0..NB)
+// (one byte per word): the fewest dword / short / byte loads.  The bytes need
+// not be aligned.  soff is wavefront-uniform (a scalar register), voff the
+// lane's own offset, so the address needs no per-lane arithmetic.
+template <int NB>
+__device__ __forceinline__ void load_bytes(__amdgpu_buffer_rsrc_t r, int voff, int soff, uint32_t* raw)
+{
+    int i = 0;
+#pragma unroll
+    for (; i + 4 <= NB; i += 4) {
+        const uint32_t v = __builtin_amdgcn_raw_buffer_load_b32(r, voff + i, soff, 0);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) raw[i + q] = (v >> (8 * q)) & 0xffu;
+    }
+    if constexpr (NB % 4 >= 2) {
+        const uint32_t v = __builtin_amdgcn_raw_buffer_load_b16(r, voff + i, soff, 0);
+        raw[i] = v & 0xffu;
+        raw[i + 1] = (v >> 8) & 0xffu;
+    }
+    if constexpr (NB % 2 == 1) raw[NB - 1] = __builtin_amdgcn_raw_buffer_load_b8(r, voff + NB - 1, soff, 0);
+}
+
+// The K*C input bytes of this lane in input row `row` (every strip lies inside
+// the frame, so the loads are in range).
 template <int K, bool RGB>
 __device__ __forceinline__ void load_raw(const RowCtx& c, int row, uint32_t (&raw)[RowState<K, RGB>::NRAW])
 {
-    constexpr int C = RGB ? 3 : 1;
-    // wavefront-uniform row base (scalar registers) plus a 32-bit per-lane offset
-    const uint8_t* rowp = c.in_frame + (size_t)row * c.row_bytes;
-#pragma unroll
-    for (int i = 0; i < K * C; ++i) raw[i] = rowp[c.lane_in + i];
+    const __amdgpu_buffer_rsrc_t r =
+        __builtin_amdgcn_make_buffer_rsrc((void*)c.in_frame, (short)0, c.row_bytes * c.Hf, 0x00020000);
+    load_bytes<K * (RGB ? 3 : 1)>(r, c.lane_in, row * c.row_bytes, raw);
 }
 
 template <int K, bool RGB, bool DIFF, bool EL, bool ER, int U>
@@ -254,11 +276,11 @@ __device__ __forceinline__ void row_step(RowState<K, RGB>& st, const RowCtx& c, 
         }
         if (c.real) {
             const __amdgpu_buffer_rsrc_t r = out_rsrc(c.out_frame, (uint32_t)(c.W * c.Hf));
-            const int row_off = rn * c.W + c.lane_out;
+            const int soff = rn * c.W;  // uniform row offset
 #pragma unroll
             for (int k = 0; k < K; ++k)
                 __builtin_amdgcn_raw_buffer_store_b8((outbits >> k & 1u) ? (uint8_t)255 : (uint8_t)0, r,
-                                                     (c.valid >> k & 1u) ? row_off + k : DROP, 0, 0);
+                                                     (c.valid >> k & 1u) ? c.lane_out + k : DROP, soff, 0);
         }
     }
     // bottom replicate: after the last frame row, copy it into the next slot of

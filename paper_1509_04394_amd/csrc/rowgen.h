@@ -90,17 +90,20 @@ template <int CH, int A, int B, int K>
 __device__ __forceinline__ void gen_load(const GenCtx& c, int row, uint32_t* raw)
 {
     using I = GenInfo<CH, A, B>;
-    const size_t base = (size_t)c.t * c.plane + (size_t)row * c.W;
+    // buffers over frame t (of each plane), uniform row offset, lane offset
+    const size_t fbase = (size_t)c.t * c.plane;
     if constexpr (I::IN_U8) {
-        const uint8_t* rp = (const uint8_t*)c.in + base * I::IN_BYTES;
-#pragma unroll
-        for (int i = 0; i < K * I::IN_BYTES; ++i) raw[i] = rp[c.lane_in * I::IN_BYTES + i];
+        const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(
+            (void*)((const uint8_t*)c.in + fbase * I::IN_BYTES), (short)0, (int)(c.plane * I::IN_BYTES), 0x00020000);
+        load_bytes<K * I::IN_BYTES>(r, c.lane_in * I::IN_BYTES, row * c.W * I::IN_BYTES, raw);
     } else {
 #pragma unroll
         for (int ch = 0; ch < I::IN_PLANES; ++ch) {
-            const uint32_t* rp = (const uint32_t*)c.in + ch * c.vol + base;
+            const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(
+                (void*)((const float*)c.in + ch * c.vol + fbase), (short)0, (int)(c.plane * 4), 0x00020000);
 #pragma unroll
-            for (int k = 0; k < K; ++k) raw[ch * K + k] = rp[c.lane_in + k];
+            for (int k = 0; k < K; ++k)
+                raw[ch * K + k] = __builtin_amdgcn_raw_buffer_load_b32(r, 4 * (c.lane_in + k), 4 * row * c.W, 0);
         }
     }
 }
@@ -148,7 +151,7 @@ __device__ __forceinline__ void gen_store(const GenCtx& c, int row, const float 
 {
     using I = GenInfo<CH, A, B>;
     const size_t fbase = (size_t)c.t * c.plane;
-    const int off = row * c.W + c.lane_in;
+    const int soff = row * c.W;  // uniform row offset (elements)
     if constexpr (I::DIFF || I::OUT.out_dt == FZ_U8) {
         const __amdgpu_buffer_rsrc_t r = out_rsrc((uint8_t*)c.out + fbase, (uint32_t)c.plane);
 #pragma unroll
@@ -158,7 +161,7 @@ __device__ __forceinline__ void gen_store(const GenCtx& c, int row, const float 
                 b = (outbits >> k & 1u) ? (uint8_t)255 : (uint8_t)0;
             else
                 b = (uint8_t)(uint32_t)v[0][k];
-            __builtin_amdgcn_raw_buffer_store_b8(b, r, (c.valid >> k & 1u) ? off + k : DROP, 0, 0);
+            __builtin_amdgcn_raw_buffer_store_b8(b, r, (c.valid >> k & 1u) ? c.lane_in + k : DROP, soff, 0);
         }
     } else {
 #pragma unroll
@@ -167,7 +170,8 @@ __device__ __forceinline__ void gen_store(const GenCtx& c, int row, const float 
 #pragma unroll
             for (int k = 0; k < K; ++k)
                 __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v[ch][k]), r,
-                                                      (c.valid >> k & 1u) ? 4 * (off + k) : DROP, 0, 0);
+                                                      (c.valid >> k & 1u) ? 4 * (c.lane_in + k) : DROP, 4 * soff,
+                                                      0);
         }
     }
 }

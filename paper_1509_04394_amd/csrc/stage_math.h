@@ -17,7 +17,15 @@ namespace fz {
 // division.
 __device__ __forceinline__ uint32_t rgb2gray(uint32_t r, uint32_t g, uint32_t b)
 {
-    return (299u * r + 587u * g + 114u * b + 500u) / 1000u;
+    // x = 299R + 587G + 114B + 500 <= 255500 < 2^24, so 24-bit multiplies are
+    // exact (full rate, where 32-bit multiplies issue at a quarter of it).
+    const uint32_t x = __umul24(299u, r) + __umul24(587u, g) + __umul24(114u, b) + 500u;
+    // floor(x / 1000) is the high word of x * ceil(2^32 / 1000) = x * 0x418938
+    // for every x <= 255500 (checked exhaustively); both factors are below
+    // 2^24, so the 24-bit multiply-high gives it in one instruction.
+    uint32_t q;
+    asm("v_mul_hi_u32_u24 %0, 0x418938, %1" : "=v"(q) : "v"(x));
+    return q;
 }
 
 // Symmetric 5-tap weighted sum: w2*(x-2 + x+2) + w1*(x-1 + x+1) + w0*x0.
