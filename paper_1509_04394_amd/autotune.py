@@ -14,8 +14,8 @@ import numpy as np
 from . import fz
 
 TILES = [(64, 16), (32, 32), (64, 32)]
-BANDS = [32, 48, 67, 100, 150, 300]
-FRAME_RUNS = [4, 8, 16, 32]
+BANDS = [32, 44, 55, 67, 86, 100, 150]
+FRAME_RUNS = [8, 12, 16, 24]
 
 
 def candidates(info):

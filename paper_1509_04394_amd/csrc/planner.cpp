@@ -86,7 +86,8 @@ Segment price_group(const fz_plan& p, int a, int b, int req_w, int req_h, int re
         const bool diff = chain_op(ch, B) == FZ_OP_FRAMEDIFF;
         s.row_k = row_generic ? 2 : row_strips_best(p.W);
         s.nstrips = row_strips(p.W, s.row_k, row_generic ? s.halo : ROW_HX);
-        const RowShape rs = row_shape(p.H, p.T, s.nstrips, diff, req_h, req_tpb);
+        const int slots = row_generic ? ROW_SLOTS_GENERIC : (s.row_k == 2 ? ROW_SLOTS_K2 : ROW_SLOTS_K3);
+        const RowShape rs = row_shape(p.H, p.T, s.nstrips, diff, req_h, req_tpb, slots);
         s.tpb = rs.tt;
         s.nchunks = (p.T + s.tpb - 1) / s.tpb;
         s.tile_h = rs.band_h;

@@ -98,7 +98,8 @@ __device__ __forceinline__ void copy_row(float (&d)[K], const float (&s)[K])
 
 template <int K, bool RGB>
 struct RowState {
-    static constexpr int NRAW = RGB ? 3 * K : K;
+    static constexpr int NB = RGB ? 3 * K : K;                     // input bytes per lane and row
+    static constexpr int NRAW = NB / 4 + (NB % 4 >= 2) + (NB % 2);  // words as loaded (packed bytes)
     float h[5][K];     // Gaussian horizontal pass
     float g[3][K];     // Gaussian output
     float b[5][3][K];  // window-sum horizontal pass, 3 channels
@@ -144,14 +145,49 @@ __device__ __forceinline__ void load_bytes(__amdgpu_buffer_rsrc_t r, int voff, i
     if constexpr (NB % 2 == 1) raw[NB - 1] = __builtin_amdgcn_raw_buffer_load_b8(r, voff + NB - 1, soff, 0);
 }
 
-// The K*C input bytes of this lane in input row `row` (every strip lies inside
-// the frame, so the loads are in range).
+// NB consecutive bytes kept packed as loaded: dwords, then a short, then a
+// byte (zero-extended); byte_of<NB>(w, i) extracts byte i.  Keeping the bytes
+// packed holds a row of 6 RGB bytes in 2 registers instead of 6.
+template <int NB>
+__device__ __forceinline__ void load_words(__amdgpu_buffer_rsrc_t r, int voff, int soff, uint32_t* w)
+{
+    int i = 0, n = 0;
+#pragma unroll
+    for (; i + 4 <= NB; i += 4) w[n++] = __builtin_amdgcn_raw_buffer_load_b32(r, voff + i, soff, 0);
+    if constexpr (NB % 4 >= 2) {
+        w[n++] = __builtin_amdgcn_raw_buffer_load_b16(r, voff + i, soff, 0);
+        i += 2;
+    }
+    if constexpr (NB % 2 == 1) w[n] = __builtin_amdgcn_raw_buffer_load_b8(r, voff + NB - 1, soff, 0);
+}
+template <int NB, int I>
+__device__ __forceinline__ uint32_t byte_of(const uint32_t* w)
+{
+    constexpr int D = NB / 4;  // whole dwords
+    if constexpr (I < 4 * D) return (w[I / 4] >> (8 * (I % 4))) & 0xffu;
+    else if constexpr (NB % 4 >= 2 && I < 4 * D + 2) return (w[D] >> (8 * (I - 4 * D))) & 0xffu;
+    else return w[D + (NB % 4 >= 2 ? 1 : 0)];
+}
+
+// Gray value of each of the lane's K columns from its packed input bytes.
+template <int K, bool RGB, int... k>
+__device__ __forceinline__ void gray_row(const uint32_t* w, float (&gr)[K], std::integer_sequence<int, k...>)
+{
+    constexpr int NB = RowState<K, RGB>::NB;
+    if constexpr (RGB)
+        ((gr[k] = (float)rgb2gray(byte_of<NB, 3 * k>(w), byte_of<NB, 3 * k + 1>(w), byte_of<NB, 3 * k + 2>(w))), ...);
+    else
+        ((gr[k] = (float)byte_of<NB, k>(w)), ...);
+}
+
+// The K*C input bytes of this lane in input row `row`, packed (every strip
+// lies inside the frame, so the loads are in range).
 template <int K, bool RGB>
 __device__ __forceinline__ void load_raw(const RowCtx& c, int row, uint32_t (&raw)[RowState<K, RGB>::NRAW])
 {
     const __amdgpu_buffer_rsrc_t r =
         __builtin_amdgcn_make_buffer_rsrc((void*)c.in_frame, (short)0, c.row_bytes * c.Hf, 0x00020000);
-    load_bytes<K * (RGB ? 3 : 1)>(r, c.lane_in, row * c.row_bytes, raw);
+    load_words<RowState<K, RGB>::NB>(r, c.lane_in, row * c.row_bytes, raw);
 }
 
 template <int K, bool RGB, bool DIFF, bool EL, bool ER, int U>
@@ -168,13 +204,7 @@ __device__ __forceinline__ void row_step(RowState<K, RGB>& st, const RowCtx& c, 
     // Gaussian, horizontal pass, on the gray input row
     if ((unsigned)(j - c.ji) < (unsigned)c.ni) {
         float gr[K];
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            if constexpr (RGB)
-                gr[k] = (float)rgb2gray(st.raw[U3][3 * k], st.raw[U3][3 * k + 1], st.raw[U3][3 * k + 2]);
-            else
-                gr[k] = (float)st.raw[U3][k];
-        }
+        gray_row<K, RGB>(st.raw[U3], gr, std::make_integer_sequence<int, K>{});
         float e[K + 4];
         extend_row<K, 2, EL, ER>(gr, e);
 #pragma unroll

@@ -7,7 +7,13 @@ namespace fz {
 
 constexpr int ROW_HX = 6;     // horizontal and vertical halo of the chain: 2 + 1 + 2 + 1
 constexpr int ROW_WAVES = 4;  // independent wavefronts per workgroup
-constexpr int ROW_TARGET_ITEMS = 4096;  // enough wavefronts to fill 256 CUs several times
+// Wavefronts the 256 CUs hold at once: 4 SIMDs each, and waves per SIMD as
+// the kernel's registers allow (512 per lane, allocated in blocks of 8): the
+// Harris row kernel uses <= 96 with two columns per lane (5 waves) and <= 144
+// with three (3 waves); 4 is assumed for the generic row kernel.
+constexpr int ROW_SLOTS_K2 = 256 * 4 * 5;
+constexpr int ROW_SLOTS_K3 = 256 * 4 * 3;
+constexpr int ROW_SLOTS_GENERIC = 256 * 4 * 4;
 
 // Groups the row kernel implements: gray conversion or Gaussian first, suppression
 // or frame difference last, of the Harris chain.
@@ -39,13 +45,13 @@ inline int row_lds_bytes(int band_h) { return ROW_WAVES * band_h * 64; }
 
 // Rows per band and frames per work item.  A work item marches band_h + 2*HX
 // rows per frame over tt frames (plus the frame before them when the group
-// ends in the frame difference); items run in rounds of ROW_TARGET_ITEMS
-// wavefronts.  Pick the pair with the least (rounds x item length); explicit
-// requests (> 0) are kept.
+// ends in the frame difference); items run in rounds of `slots` wavefronts.
+// Pick the pair with the least (rounds x item length); explicit requests
+// (> 0) are kept.
 struct RowShape {
     int band_h, tt;
 };
-inline RowShape row_shape(int H, int T, int nstrips, bool diff, int req_h, int req_tt)
+inline RowShape row_shape(int H, int T, int nstrips, bool diff, int req_h, int req_tt, int slots)
 {
     RowShape best{H, 1};
     double best_cost = -1.0;
@@ -60,7 +66,7 @@ inline RowShape row_shape(int H, int T, int nstrips, bool diff, int req_h, int r
             if (diff && bh > 256) continue;
             if (bh < 16 && req_h <= 0 && nb > 1) break;
             const long long items = (long long)nstrips * ((H + bh - 1) / bh) * ((T + t - 1) / t);
-            const long long rounds = (items + ROW_TARGET_ITEMS - 1) / ROW_TARGET_ITEMS;
+            const long long rounds = (items + slots - 1) / slots;
             const double cost = (double)rounds * (bh + 2 * ROW_HX) * (t + (diff ? 1 : 0));
             if (best_cost < 0 || cost < best_cost) {
                 best_cost = cost;
