@@ -131,6 +131,7 @@ static fz_status enqueue_batch(const fz_plan& p, const fz_clip* clips, int n, vo
 fz_status run_batch(fz_plan& p, const fz_clip* clips, int n, void* ws, size_t ws_bytes, void* stream)
 {
     hipStream_t user = (hipStream_t)stream;
+    (void)hipGetLastError();  // drop an error latched by earlier, unrelated runtime calls
     std::vector<uint64_t> key = batch_key(clips, n, ws, ws_bytes);
     if (p.batch_exec && key == p.batch_key) {
         hipError_t e = hipGraphLaunch((hipGraphExec_t)p.batch_exec, user);

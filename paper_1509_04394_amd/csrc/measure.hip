@@ -92,6 +92,7 @@ fz_status plan_measure(fz_plan& p, const void* d_in, void* ws, size_t ws_bytes, 
     if (!ws || ws_bytes < need)
         return fail(FZ_E_WORKSPACE, "fz_plan_measure: workspace needs " + std::to_string(need) + " bytes");
     hipStream_t s = (hipStream_t)stream;
+    (void)hipGetLastError();  // drop an error latched by earlier, unrelated runtime calls
     const size_t slot = (need - 256) / 3;
     char* buf[3] = {(char*)ws, (char*)ws + slot, (char*)ws + 2 * slot};
     uint32_t* cnt = (uint32_t*)((char*)ws + 3 * slot);

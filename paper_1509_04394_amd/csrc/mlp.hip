@@ -243,6 +243,7 @@ fz_status fz_mlp_forward(const float* d_params, int32_t n_features, const float*
     if (!d_params || !d_x || !d_y) return fail(FZ_E_INVALID, "fz_mlp_forward: null pointer");
     if (n_features <= 0 || n_features > MLP_FMAX || n <= 0) return fail(FZ_E_INVALID, "fz_mlp_forward: bad size");
     const int nb = (n + MLP_TILE - 1) / MLP_TILE;
+    (void)hipGetLastError();  // drop an error latched by earlier, unrelated runtime calls
     hipLaunchKernelGGL(k_mlp_forward, dim3(nb), dim3(MLP_THREADS), 0, (hipStream_t)stream, d_params, n_features,
                        d_x, n, d_y, nullptr, nullptr);
     hipError_t e = hipGetLastError();
@@ -257,6 +258,7 @@ fz_status fz_mlp_loss_grad(const float* d_params, int32_t n_features, const floa
     if (!d_ws || ws_bytes < mlp_ws(n_features, n))
         return fail(FZ_E_WORKSPACE, "fz_mlp_loss_grad: workspace needs " + std::to_string(mlp_ws(n_features, n)));
     hipStream_t s = (hipStream_t)stream;
+    (void)hipGetLastError();  // drop an error latched by earlier, unrelated runtime calls
     const int nb = (n + MLP_TILE - 1) / MLP_TILE;
     const int P = mlp_params(n_features);
     char* w = (char*)d_ws;
@@ -281,6 +283,7 @@ fz_status fz_mlp_adam_step(float* d_params, const float* d_grad, float* d_m, flo
     if (!d_params || !d_grad || !d_m || !d_v) return fail(FZ_E_INVALID, "fz_mlp_adam_step: null pointer");
     if (n_params <= 0 || step < 1) return fail(FZ_E_INVALID, "fz_mlp_adam_step: bad size or step");
     const float c1 = 1.0f - powf(beta1, (float)step), c2 = 1.0f - powf(beta2, (float)step);
+    (void)hipGetLastError();  // drop an error latched by earlier, unrelated runtime calls
     hipLaunchKernelGGL(k_mlp_adam, dim3((n_params + 255) / 256), dim3(256), 0, (hipStream_t)stream, d_params, d_grad,
                        d_m, d_v, n_params, lr, beta1, beta2, eps, c1, c2);
     hipError_t e = hipGetLastError();

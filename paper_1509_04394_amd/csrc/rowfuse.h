@@ -180,14 +180,19 @@ __device__ __forceinline__ void gray_row(const uint32_t* w, float (&gr)[K], std:
         ((gr[k] = (float)byte_of<NB, k>(w)), ...);
 }
 
-// The K*C input bytes of this lane in input row `row`, packed (every strip
-// lies inside the frame, so the loads are in range).
+// The K*C input bytes of this lane in input row `row`, packed.  The row is
+// clamped into the frame (a wavefront-uniform scalar operation), so the load
+// can be issued on every row step, in range, whether or not the row is used:
+// an unconditional load lets the compiler count the loads still in flight
+// and wait only for the one a step needs, instead of for all of them at the
+// join after a conditional load.  Every strip lies inside the frame.
 template <int K, bool RGB>
 __device__ __forceinline__ void load_raw(const RowCtx& c, int row, uint32_t (&raw)[RowState<K, RGB>::NRAW])
 {
     const __amdgpu_buffer_rsrc_t r =
         __builtin_amdgcn_make_buffer_rsrc((void*)c.in_frame, (short)0, c.row_bytes * c.Hf, 0x00020000);
-    load_words<RowState<K, RGB>::NB>(r, c.lane_in, row * c.row_bytes, raw);
+    const int rc = row < 0 ? 0 : (row >= c.Hf ? c.Hf - 1 : row);
+    load_words<RowState<K, RGB>::NB>(r, c.lane_in, rc * c.row_bytes, raw);
 }
 
 template <int K, bool RGB, bool DIFF, bool EL, bool ER, int U>
@@ -199,7 +204,7 @@ __device__ __forceinline__ void row_step(RowState<K, RGB>& st, const RowCtx& c, 
     // prefetch the input row two iterations ahead
     {
         const int rp = row_in + 2;
-        if ((unsigned)(j - c.jp) < (unsigned)c.np_) load_raw<K, RGB>(c, rp, st.raw[(U + 2) % 3]);
+        load_raw<K, RGB>(c, rp, st.raw[(U + 2) % 3]);  // unused when rp is outside [lo_in, hi_in)
     }
     // Gaussian, horizontal pass, on the gray input row
     if ((unsigned)(j - c.ji) < (unsigned)c.ni) {
@@ -349,8 +354,8 @@ __device__ __forceinline__ void row_frames(RowCtx& c, const SegParams& p, int ts
         RowState<K, RGB> st;
         // first two input rows
         const int r0 = c.y0 - ROW_HX;
-        if (r0 >= c.lo_in && r0 < c.hi_in) load_raw<K, RGB>(c, r0, st.raw[0]);
-        if (r0 + 1 >= c.lo_in && r0 + 1 < c.hi_in) load_raw<K, RGB>(c, r0 + 1, st.raw[1]);
+        load_raw<K, RGB>(c, r0, st.raw[0]);
+        load_raw<K, RGB>(c, r0 + 1, st.raw[1]);
         for (int jb = 0; jb < n; jb += ROW_UNROLL)
             row_block<K, RGB, DIFF, EL, ER>(st, c, p, jb, n, std::make_integer_sequence<int, ROW_UNROLL>{});
     }

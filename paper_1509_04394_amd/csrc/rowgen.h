@@ -90,7 +90,10 @@ template <int CH, int A, int B, int K>
 __device__ __forceinline__ void gen_load(const GenCtx& c, int row, uint32_t* raw)
 {
     using I = GenInfo<CH, A, B>;
-    // buffers over frame t (of each plane), uniform row offset, lane offset
+    // buffers over frame t (of each plane), uniform row offset, lane offset;
+    // the row is clamped into the frame so the load can be issued on every
+    // step (see load_raw)
+    row = row < 0 ? 0 : (row >= c.Hf ? c.Hf - 1 : row);
     const size_t fbase = (size_t)c.t * c.plane;
     if constexpr (I::IN_U8) {
         const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(
@@ -356,7 +359,7 @@ __device__ __forceinline__ void gen_step(GenState<CH, A, B, K>& st, const GenCtx
     const int row_in = c.y0 - I::H + j;
     const int lo_in = max(0, c.y0 - I::H), hi_in = min(c.Hf, c.y1 + I::H);
     const int rp = row_in + 2;
-    if (rp >= lo_in && rp < hi_in) gen_load<CH, A, B, K>(c, rp, st.raw[(U + 2) % 3]);
+    gen_load<CH, A, B, K>(c, rp, st.raw[(U + 2) % 3]);  // unused when rp is outside [lo_in, hi_in)
     const bool have = row_in >= lo_in && row_in < hi_in;
     float v[3][K];
     if (have) gen_unpack<CH, A, B, K>(st.raw[U % 3], v, p);
@@ -381,8 +384,8 @@ __device__ __forceinline__ void gen_frames(GenCtx& c, const SegParams& p, int ts
         c.real = t >= t0;
         GenState<CH, A, B, K> st;
         const int r0 = c.y0 - I::H;
-        if (r0 >= lo_in && r0 < hi_in) gen_load<CH, A, B, K>(c, r0, st.raw[0]);
-        if (r0 + 1 >= lo_in && r0 + 1 < hi_in) gen_load<CH, A, B, K>(c, r0 + 1, st.raw[1]);
+        gen_load<CH, A, B, K>(c, r0, st.raw[0]);
+        gen_load<CH, A, B, K>(c, r0 + 1, st.raw[1]);
         for (int jb = 0; jb < n; jb += ROW_UNROLL)
             gen_block<CH, A, B, K, EDGE>(st, c, p, jb, n, std::make_integer_sequence<int, ROW_UNROLL>{});
     }

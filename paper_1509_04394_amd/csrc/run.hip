@@ -36,6 +36,7 @@ fz_status run_plan(const fz_plan& p, const void* d_in, void* d_out, fz_point* d_
                    uint32_t cap, void* d_ws, size_t ws_bytes, void* stream)
 {
     (void)ws_bytes;
+    (void)hipGetLastError();  // drop an error latched by earlier, unrelated runtime calls
     hipStream_t s = (hipStream_t)stream;
     const size_t slot = p.segs.size() > 1 ? align256(workspace_bytes(p) / (p.segs.size() > 2 ? 2 : 1)) : 0;
     if (d_count && p.has_nms) {

@@ -124,6 +124,22 @@ SIGNATURES = [
 ]
 
 
+def _torch_runtime_first():
+    """Initialise torch's GPU runtime before the library is loaded.
+
+    The library and PyTorch's ROCm build may each bring a HIP runtime into the
+    process; the device buffers and streams the binding passes come from
+    torch's.  Loading the library first and initialising torch afterwards has
+    left the library's runtime without a device, so torch goes first (a no-op
+    without a GPU or without torch)."""
+    try:
+        import torch
+    except ImportError:
+        return
+    if torch.cuda.is_available():
+        torch.cuda.init()
+
+
 def lib():
     """The loaded C library; raises if it has not been built."""
     global _lib
@@ -131,6 +147,7 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() or "
                               f"python paper_1509_04394_amd/build.py")
+        _torch_runtime_first()
         L = ctypes.CDLL(LIB_PATH)
         for name, res, args in SIGNATURES:
             f = getattr(L, name)
