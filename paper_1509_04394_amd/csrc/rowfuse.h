@@ -96,16 +96,28 @@ __device__ __forceinline__ void copy_row(float (&d)[K], const float (&s)[K])
     for (int k = 0; k < K; ++k) d[k] = s[k];
 }
 
+// NB consecutive input bytes kept as loaded: whole dwords, then a short,
+// then a byte.  The short and the byte keep their 16- and 8-bit types so that
+// their zero extension happens where they are used, not right after the
+// load (an operation on a loaded register makes the wavefront wait for the
+// load).
+template <int NB>
+struct RawRow {
+    static constexpr int ND = NB / 4;
+    uint32_t d[ND > 0 ? ND : 1];
+    uint16_t h;  // bytes 4*ND, 4*ND+1 when NB % 4 >= 2
+    uint8_t y;   // the last byte when NB is odd
+};
+
 template <int K, bool RGB>
 struct RowState {
-    static constexpr int NB = RGB ? 3 * K : K;                     // input bytes per lane and row
-    static constexpr int NRAW = NB / 4 + (NB % 4 >= 2) + (NB % 2);  // words as loaded (packed bytes)
+    static constexpr int NB = RGB ? 3 * K : K;  // input bytes per lane and row
     float h[5][K];     // Gaussian horizontal pass
     float g[3][K];     // Gaussian output
     float b[5][3][K];  // window-sum horizontal pass, 3 channels
     float rt[3][K];    // thresholded response
     float m[3][K];     // 3-wide horizontal maximum of rt
-    uint32_t raw[3][NRAW];
+    RawRow<NB> raw[3];  // input rows, two loaded ahead
 };
 
 struct RowCtx {
@@ -123,55 +135,44 @@ struct RowCtx {
     uint8_t* prev;            // LDS previous-frame mask bits of this wavefront (DIFF)
 };
 
-// NB consecutive bytes at byte offset voff + soff of buffer r into raw[0..NB)
-// (one byte per word): the fewest dword / short / byte loads.  The bytes need
-// not be aligned.  soff is wavefront-uniform (a scalar register), voff the
-// lane's own offset, so the address needs no per-lane arithmetic.
+// NB consecutive bytes at byte offset voff + soff of buffer r into a RawRow:
+// the fewest dword / short / byte loads; the bytes need not be aligned.  soff
+// is wavefront-uniform (a scalar register), voff the lane's own offset, so
+// the address needs no per-lane arithmetic.  byte_of<NB, I>(w) extracts byte
+// I; keeping the bytes packed holds a row of 6 RGB bytes in 2 registers
+// instead of 6.
 template <int NB>
-__device__ __forceinline__ void load_bytes(__amdgpu_buffer_rsrc_t r, int voff, int soff, uint32_t* raw)
+__device__ __forceinline__ void load_words(__amdgpu_buffer_rsrc_t r, int voff, int soff, RawRow<NB>& w)
 {
-    int i = 0;
+    constexpr int D = NB / 4;
 #pragma unroll
-    for (; i + 4 <= NB; i += 4) {
-        const uint32_t v = __builtin_amdgcn_raw_buffer_load_b32(r, voff + i, soff, 0);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) raw[i + q] = (v >> (8 * q)) & 0xffu;
-    }
-    if constexpr (NB % 4 >= 2) {
-        const uint32_t v = __builtin_amdgcn_raw_buffer_load_b16(r, voff + i, soff, 0);
-        raw[i] = v & 0xffu;
-        raw[i + 1] = (v >> 8) & 0xffu;
-    }
-    if constexpr (NB % 2 == 1) raw[NB - 1] = __builtin_amdgcn_raw_buffer_load_b8(r, voff + NB - 1, soff, 0);
-}
-
-// NB consecutive bytes kept packed as loaded: dwords, then a short, then a
-// byte (zero-extended); byte_of<NB>(w, i) extracts byte i.  Keeping the bytes
-// packed holds a row of 6 RGB bytes in 2 registers instead of 6.
-template <int NB>
-__device__ __forceinline__ void load_words(__amdgpu_buffer_rsrc_t r, int voff, int soff, uint32_t* w)
-{
-    int i = 0, n = 0;
-#pragma unroll
-    for (; i + 4 <= NB; i += 4) w[n++] = __builtin_amdgcn_raw_buffer_load_b32(r, voff + i, soff, 0);
-    if constexpr (NB % 4 >= 2) {
-        w[n++] = __builtin_amdgcn_raw_buffer_load_b16(r, voff + i, soff, 0);
-        i += 2;
-    }
-    if constexpr (NB % 2 == 1) w[n] = __builtin_amdgcn_raw_buffer_load_b8(r, voff + NB - 1, soff, 0);
+    for (int i = 0; i < D; ++i) w.d[i] = __builtin_amdgcn_raw_buffer_load_b32(r, voff + 4 * i, soff, 0);
+    if constexpr (NB % 4 >= 2) w.h = __builtin_amdgcn_raw_buffer_load_b16(r, voff + 4 * D, soff, 0);
+    if constexpr (NB % 2 == 1) w.y = __builtin_amdgcn_raw_buffer_load_b8(r, voff + NB - 1, soff, 0);
 }
 template <int NB, int I>
-__device__ __forceinline__ uint32_t byte_of(const uint32_t* w)
+__device__ __forceinline__ uint32_t byte_of(const RawRow<NB>& w)
 {
     constexpr int D = NB / 4;  // whole dwords
-    if constexpr (I < 4 * D) return (w[I / 4] >> (8 * (I % 4))) & 0xffu;
-    else if constexpr (NB % 4 >= 2 && I < 4 * D + 2) return (w[D] >> (8 * (I - 4 * D))) & 0xffu;
-    else return w[D + (NB % 4 >= 2 ? 1 : 0)];
+    if constexpr (I < 4 * D) return (w.d[I / 4] >> (8 * (I % 4))) & 0xffu;
+    else if constexpr (NB % 4 >= 2 && I < 4 * D + 2) return ((uint32_t)w.h >> (8 * (I - 4 * D))) & 0xffu;
+    else return (uint32_t)w.y;
+}
+
+// byte_of with the index as an argument (constant after unrolling).
+template <int NB>
+__device__ __forceinline__ uint32_t byte_at(const RawRow<NB>& w, int i)
+{
+    constexpr int D = NB / 4;
+    if (i < 4 * D) return (w.d[i / 4] >> (8 * (i % 4))) & 0xffu;
+    if (NB % 4 >= 2 && i < 4 * D + 2) return ((uint32_t)w.h >> (8 * (i - 4 * D))) & 0xffu;
+    return (uint32_t)w.y;
 }
 
 // Gray value of each of the lane's K columns from its packed input bytes.
 template <int K, bool RGB, int... k>
-__device__ __forceinline__ void gray_row(const uint32_t* w, float (&gr)[K], std::integer_sequence<int, k...>)
+__device__ __forceinline__ void gray_row(const RawRow<RowState<K, RGB>::NB>& w, float (&gr)[K],
+                                         std::integer_sequence<int, k...>)
 {
     constexpr int NB = RowState<K, RGB>::NB;
     if constexpr (RGB)
@@ -187,7 +188,7 @@ __device__ __forceinline__ void gray_row(const uint32_t* w, float (&gr)[K], std:
 // and wait only for the one a step needs, instead of for all of them at the
 // join after a conditional load.  Every strip lies inside the frame.
 template <int K, bool RGB>
-__device__ __forceinline__ void load_raw(const RowCtx& c, int row, uint32_t (&raw)[RowState<K, RGB>::NRAW])
+__device__ __forceinline__ void load_raw(const RowCtx& c, int row, RawRow<RowState<K, RGB>::NB>& raw)
 {
     const __amdgpu_buffer_rsrc_t r =
         __builtin_amdgcn_make_buffer_rsrc((void*)c.in_frame, (short)0, c.row_bytes * c.Hf, 0x00020000);

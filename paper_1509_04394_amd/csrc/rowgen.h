@@ -37,7 +37,6 @@ struct GenInfo {
     static constexpr bool IN_U8 = IN.in_dt == FZ_U8;
     static constexpr int IN_PLANES = IN_U8 ? 1 : IN.in_ch;         // f32 planes
     static constexpr int IN_BYTES = IN_RGB ? 3 : 1;                // bytes per pixel of a u8 input
-    static constexpr int NRAW_PER_K = IN_U8 ? IN_BYTES : IN_PLANES;
     static constexpr int W0 = next_window(CH, A, BL);
     static constexpr int LASTW = [] {
         int w = -1;
@@ -66,7 +65,11 @@ struct GenState {
     float bh[I::has(FZ_OP_BOXSUM5) ? 5 : 1][3][K];
     float nr[I::HAS_NMS ? 3 : 1][K];
     float nm[I::HAS_NMS ? 3 : 1][K];
-    uint32_t raw[3][K * I::NRAW_PER_K];
+    // input rows, two loaded ahead: u8 bytes as loaded, or f32 words
+    struct Raw {
+        RawRow<I::IN_U8 ? K * I::IN_BYTES : 1> b;
+        uint32_t f[I::IN_U8 ? 1 : K * I::IN_PLANES];
+    } raw[3];
 };
 
 struct GenCtx {
@@ -86,8 +89,8 @@ __device__ __forceinline__ void gen_extend(const float (&v)[K], float (&e)[K + 2
     extend_row<K, R, EDGE, EDGE>(v, e);
 }
 
-template <int CH, int A, int B, int K>
-__device__ __forceinline__ void gen_load(const GenCtx& c, int row, uint32_t* raw)
+template <int CH, int A, int B, int K, class Raw>
+__device__ __forceinline__ void gen_load(const GenCtx& c, int row, Raw& raw)
 {
     using I = GenInfo<CH, A, B>;
     // buffers over frame t (of each plane), uniform row offset, lane offset;
@@ -98,7 +101,7 @@ __device__ __forceinline__ void gen_load(const GenCtx& c, int row, uint32_t* raw
     if constexpr (I::IN_U8) {
         const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(
             (void*)((const uint8_t*)c.in + fbase * I::IN_BYTES), (short)0, (int)(c.plane * I::IN_BYTES), 0x00020000);
-        load_bytes<K * I::IN_BYTES>(r, c.lane_in * I::IN_BYTES, row * c.W * I::IN_BYTES, raw);
+        load_words<K * I::IN_BYTES>(r, c.lane_in * I::IN_BYTES, row * c.W * I::IN_BYTES, raw.b);
     } else {
 #pragma unroll
         for (int ch = 0; ch < I::IN_PLANES; ++ch) {
@@ -106,28 +109,29 @@ __device__ __forceinline__ void gen_load(const GenCtx& c, int row, uint32_t* raw
                 (void*)((const float*)c.in + ch * c.vol + fbase), (short)0, (int)(c.plane * 4), 0x00020000);
 #pragma unroll
             for (int k = 0; k < K; ++k)
-                raw[ch * K + k] = __builtin_amdgcn_raw_buffer_load_b32(r, 4 * (c.lane_in + k), 4 * row * c.W, 0);
+                raw.f[ch * K + k] = __builtin_amdgcn_raw_buffer_load_b32(r, 4 * (c.lane_in + k), 4 * row * c.W, 0);
         }
     }
 }
 
 // Input row (after the group's leading point stages) as v[ch][k].
-template <int CH, int A, int B, int K>
-__device__ __forceinline__ void gen_unpack(const uint32_t* raw, float (&v)[3][K], const SegParams& p)
+template <int CH, int A, int B, int K, class Raw>
+__device__ __forceinline__ void gen_unpack(const Raw& raw, float (&v)[3][K], const SegParams& p)
 {
     using I = GenInfo<CH, A, B>;
+    constexpr int NB = K * I::IN_BYTES;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         float px[3];
         if constexpr (I::IN_RGB) {
-            px[0] = (float)raw[3 * k];
-            px[1] = (float)raw[3 * k + 1];
-            px[2] = (float)raw[3 * k + 2];
+            px[0] = (float)byte_at<NB>(raw.b, 3 * k);
+            px[1] = (float)byte_at<NB>(raw.b, 3 * k + 1);
+            px[2] = (float)byte_at<NB>(raw.b, 3 * k + 2);
         } else if constexpr (I::IN_U8) {
-            px[0] = (float)raw[k];
+            px[0] = (float)byte_at<NB>(raw.b, k);
         } else {
 #pragma unroll
-            for (int ch = 0; ch < I::IN_PLANES; ++ch) px[ch] = __uint_as_float(raw[ch * K + k]);
+            for (int ch = 0; ch < I::IN_PLANES; ++ch) px[ch] = __uint_as_float(raw.f[ch * K + k]);
         }
         point_run<CH, A, pw_end(CH, A, B)>(px, p);
 #pragma unroll
