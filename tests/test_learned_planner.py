@@ -67,3 +67,27 @@ def test_learned_requires_weights():
     with pytest.raises(fz.FzError) as e:
         fz.fz_plan_chain(stages, o)
     assert e.value.code == fz.FZ_E_INVALID
+
+
+def test_committed_weights_plan_random_chains_optimally():
+    """The trained weights shipped with the package load, match this build's
+    feature set, and give finite prices from which the DP picks the exhaustive
+    optimum (on random generic chains of the learned-cost workload)."""
+    import os
+    from oracle import partition as P
+    from paper_1509_04394_amd import costmodel, synth
+    if not os.path.exists(costmodel.WEIGHTS_PATH):
+        pytest.skip("no trained weights in the package")
+    params, meta = costmodel.load_weights()
+    assert len(params) == fz.fz_mlp_param_count(F)
+    assert np.all(np.isfinite(params))
+    assert meta["train_chains"] >= 1000 and meta["test_chains"] >= 100
+    for seed in (9600, 9601, 9602):
+        spec = synth.random_chain(seed)[:10]
+        plan = fz.Plan(spec, 640, 480, 64, cost_weights=params)
+        n = len(spec)
+        c = [[plan.group_cost(a, b) if b >= a else None for b in range(n)] for a in range(n)]
+        assert all(math.isfinite(c[a][b]) and c[a][b] > 0 for a in range(n) for b in range(a, n))
+        want, groups = P.best(c, n)
+        assert plan.cost == pytest.approx(want, rel=1e-12)
+        assert plan.segments == [b for (_, b) in groups]
