@@ -192,6 +192,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="rgb800", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--engine", default="auto", choices=["auto", "tile", "row"],
+                    help="kernel family for the fused plan's groups (auto: the planner's choice)")
+    ap.add_argument("--autotune", action="store_true",
+                    help="measure every band / tile configuration of each fused group first (untimed) and "
+                         "keep the fastest")
     ap.add_argument("--no-unfused", action="store_true", help="skip timing the unfused sequence")
     ap.add_argument("--fused-only", action="store_true", help="time only the fused plan (for profiling)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -234,7 +239,12 @@ def main():
     del vol
     stream = torch.cuda.current_stream(dev)
 
-    fused = fz.Plan(ops, W, H, T)
+    fused = fz.Plan(ops, W, H, T, engine=args.engine)
+    tuned = None
+    if args.autotune:
+        from paper_1509_04394_amd import autotune
+        tuned = autotune.autotune(fused, x, reps=3)
+        log("autotuned", tuned)
     info = fused.segment_info()
     fb = fused.alloc(dev)
     log("fused plan groups", fused.segments, "tiles", [(s.tile_w, s.tile_h, s.frames_per_block) for s in info])
@@ -246,7 +256,7 @@ def main():
     if not (args.no_unfused or args.fused_only):
         del fb
         torch.cuda.empty_cache()
-        uplan = fz.Plan(ops, W, H, T, partition="unfused")
+        uplan = fz.Plan(ops, W, H, T, partition="unfused", engine=args.engine)
         ub = uplan.alloc(dev)
         u_mean, u_med, _ = time_plan(uplan, x, ub, max(3, args.steps // 2), 1, stream)
         log(f"unfused: {u_mean:.3f} ms/step mean, {u_med:.3f} median")
@@ -278,6 +288,9 @@ def main():
            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
            "config": {"workload": wl["desc"], "partition": fused.segments,
                       "tile": [dominant.tile_w, dominant.tile_h, dominant.frames_per_block],
+                      "engine": {fz.FZ_ENGINE_ROW: "row", fz.FZ_ENGINE_TILE: "tile",
+                                 fz.FZ_ENGINE_STREAM: "stream"}[dominant.engine],
+                      "sizing": "autotuned" if args.autotune else "planner",
                       "points_per_step": nfused},
            "roofline": roof}
     if unf is not None:
