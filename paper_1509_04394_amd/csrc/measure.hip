@@ -134,8 +134,9 @@ fz_status plan_measure(fz_plan& p, const void* d_in, void* ws, size_t ws_bytes, 
             }
         }
         if (a + 1 < n) {  // stage a alone gives the next stage's real input
-            Segment g1 = best[(size_t)a * n + a];
-            if (!(g1.cost < inf)) return fail(FZ_E_LDS, "fz_plan_measure: stage " + std::to_string(a) + " cannot run");
+            if (!(cost[(size_t)a * n + a] < inf))  // (best[] holds a timed configuration only where cost is finite)
+                return fail(FZ_E_LDS, "fz_plan_measure: stage " + std::to_string(a) + " cannot run");
+            const Segment g1 = best[(size_t)a * n + a];
             fz_plan sub;
             single_group(sub, p, g1);
             fz_status st = run_plan(sub, cur, buf[next_buf], nullptr, cnt, 0u, nullptr, 0, s);

@@ -57,6 +57,8 @@ struct GenInfo {
     static constexpr int OUT_CH = channels_after_step(CH, LASTW, BL);
 };
 
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+
 template <int CH, int A, int B, int K>
 struct GenState {
     using I = GenInfo<CH, A, B>;
@@ -107,9 +109,9 @@ __device__ __forceinline__ void gen_load(const GenCtx& c, int row, Raw& raw)
         for (int ch = 0; ch < I::IN_PLANES; ++ch) {
             const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(
                 (void*)((const float*)c.in + ch * c.vol + fbase), (short)0, (int)(c.plane * 4), 0x00020000);
-#pragma unroll
-            for (int k = 0; k < K; ++k)
-                raw.f[ch * K + k] = __builtin_amdgcn_raw_buffer_load_b32(r, 4 * (c.lane_in + k), 4 * row * c.W, 0);
+            const u32x2 w = __builtin_amdgcn_raw_buffer_load_b64(r, 4 * c.lane_in, 4 * row * c.W, 0);  // K == 2
+            raw.f[ch * K] = w.x;
+            raw.f[ch * K + 1] = w.y;
         }
     }
 }
@@ -159,26 +161,37 @@ __device__ __forceinline__ void gen_store(const GenCtx& c, int row, const float 
     using I = GenInfo<CH, A, B>;
     const size_t fbase = (size_t)c.t * c.plane;
     const int soff = row * c.W;  // uniform row offset (elements)
+    // With two columns per lane, a lane that owns both writes them with one
+    // access (a contiguous segment per wavefront instead of two interleaved
+    // half-filled ones); the few lanes at a strip boundary that own one
+    // column write it alone.  Dropped (out-of-range) offsets do the masking.
+    static_assert(K == 2, "the generic row kernel runs two columns per lane");
+    const bool both = c.valid == 3u;
+    const int lo = (!both && (c.valid & 1u)) ? c.lane_in : DROP;
+    const int hi = (!both && (c.valid & 2u)) ? c.lane_in + 1 : DROP;
     if constexpr (I::DIFF || I::OUT.out_dt == FZ_U8) {
         const __amdgpu_buffer_rsrc_t r = out_rsrc((uint8_t*)c.out + fbase, (uint32_t)c.plane);
+        uint32_t b[K];
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-            uint8_t b;
             if constexpr (I::DIFF || I::OUT.op == FZ_OP_NMS3)
-                b = (outbits >> k & 1u) ? (uint8_t)255 : (uint8_t)0;
+                b[k] = (outbits >> k & 1u) ? 255u : 0u;
             else
-                b = (uint8_t)(uint32_t)v[0][k];
-            __builtin_amdgcn_raw_buffer_store_b8(b, r, (c.valid >> k & 1u) ? c.lane_in + k : DROP, soff, 0);
+                b[k] = (uint32_t)v[0][k];
         }
+        __builtin_amdgcn_raw_buffer_store_b16((uint16_t)(b[0] | b[1] << 8), r, both ? c.lane_in : DROP, soff, 0);
+        __builtin_amdgcn_raw_buffer_store_b8((uint8_t)b[0], r, lo, soff, 0);
+        __builtin_amdgcn_raw_buffer_store_b8((uint8_t)b[1], r, hi, soff, 0);
     } else {
 #pragma unroll
         for (int ch = 0; ch < I::OUT_CH; ++ch) {
             const __amdgpu_buffer_rsrc_t r = out_rsrc((float*)c.out + ch * c.vol + fbase, (uint32_t)(c.plane * 4));
-#pragma unroll
-            for (int k = 0; k < K; ++k)
-                __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v[ch][k]), r,
-                                                      (c.valid >> k & 1u) ? 4 * (c.lane_in + k) : DROP, 4 * soff,
-                                                      0);
+            u32x2 w;
+            w.x = __float_as_uint(v[ch][0]);
+            w.y = __float_as_uint(v[ch][1]);
+            __builtin_amdgcn_raw_buffer_store_b64(w, r, both ? 4 * c.lane_in : DROP, 4 * soff, 0);
+            __builtin_amdgcn_raw_buffer_store_b32(w.x, r, lo == DROP ? DROP : 4 * lo, 4 * soff, 0);
+            __builtin_amdgcn_raw_buffer_store_b32(w.y, r, hi == DROP ? DROP : 4 * hi, 4 * soff, 0);
         }
     }
 }

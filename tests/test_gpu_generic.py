@@ -7,7 +7,8 @@ partition and every tile shape must give the same bits (each stage's result
 is rounded to FP32 once, in a fixed order, whichever kernel holds it).  Sizes
 span several tiles with ragged right and bottom tails; the edge cases are
 frames smaller than the window, one-pixel frames, point-only chains, a group
-whose LDS box exceeds 64 KB, and weights changed after planning.
+whose LDS box exceeds 64 KB, weights changed after planning, and a batch
+of generic clips (graph replay included).
 """
 import itertools
 
@@ -174,3 +175,27 @@ def test_random_chain_full_size_config(dev, oracle_lib):
     out, plan = run_gpu(spec, vol, dev)
     ratio = parity.assert_within_bound(out, ref, bound, "full size")
     say("segments", plan.segments, "worst err/bound", ratio)
+
+
+def test_batch_of_generic_clips_equals_single_runs(dev):
+    """fz_run_batch on a generic plan (clips run one after another inside the
+    captured graph): every clip equals a single run bit for bit, on the first
+    launch and on a graph replay."""
+    spec = WELL[:4] + [("box", 2, 1)]
+    sizes = [(150, 70, 3), (64, 48, 5), (203, 77, 2)]
+    xs, outs, refs = [], [], []
+    for i, (W, H, T) in enumerate(sizes):
+        x = torch.from_numpy(synth.video(W, H, T, seed=90 + i)).to(dev)
+        ref, _ = run_gpu(spec, synth.video(W, H, T, seed=90 + i), dev)
+        xs.append(x)
+        outs.append(torch.full((1, T, H, W), float("nan"), dtype=torch.float32, device=dev))
+        refs.append(ref)
+    plan = fz.Plan(spec, 800, 600, 100)
+    clips = [fz.make_clip(x, o) for x, o in zip(xs, outs)]
+    for rep in range(2):
+        for o in outs:
+            o.fill_(float("nan"))
+        ws = fz.run_batch(plan, clips) if rep == 0 else fz.run_batch(plan, clips, workspace=ws)
+        torch.cuda.synchronize()
+        for i, (o, ref) in enumerate(zip(outs, refs)):
+            assert np.array_equal(o.cpu().numpy()[0].view(np.uint32), ref.view(np.uint32)), f"clip {i}, run {rep}"
