@@ -431,15 +431,18 @@ __device__ __forceinline__ void row_item(const SegParams& p, const RowItem& it, 
         row_frames<K, RGB, DIFF, false, false>(c, p, ts, t0, t1);
 }
 
-// Decompose a clip-local item index, strip-major: neighbouring wavefronts run
-// the same strip (same code variant, shared halo rows in L2).
+// Decompose a clip-local item index.  Strips vary fastest, then bands, then
+// frame runs: the wavefronts in flight cover whole frames, neighbouring
+// wavefronts reading neighbouring segments of the same rows.  (With strips
+// varying slowest, the wavefronts in flight covered one 128-column strip of
+// hundreds of frames, and the memory-bound kernels ran at a third of the
+// bandwidth.)
 __device__ __forceinline__ RowItem row_decompose(int item, int nstrips, int nbands, int nchunks, int band_h, int tt,
                                                  int strip_step)
 {
     RowItem it;
-    const int per_strip = nbands * nchunks;
-    it.strip = item / per_strip;
-    const int rest = item - it.strip * per_strip;
+    it.strip = item % nstrips;
+    const int rest = item / nstrips;
     it.band = rest % nbands;
     it.chunk = rest / nbands;
     it.nstrips = nstrips;
