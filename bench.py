@@ -108,7 +108,7 @@ METRIC = "Mpixel/s fused vs unfused and HBM GB/s (% of peak), 800×600×1000 cha
 # passes, scaled by the plain-copy calibration (profiles/rowfuse_rgb800_counters.md).
 # Valid only for the kernel sources they were taken with: the key is a hash of them.
 COUNTER_TRAFFIC = {
-    ("rgb800", "f7276d14f737db46"): {"fetch_bytes": 2.767e9, "write_bytes": 0.598e9,
+    ("rgb800", "327b03c471f701ee"): {"fetch_bytes": 2.490e9, "write_bytes": 0.592e9,
                                      "source": "profiles/rowfuse_rgb800_counters.md"},
 }
 KERNEL_SOURCES = ["rowfuse.h", "rowgeom.h", "stage_math.h"]

@@ -99,13 +99,15 @@ __global__ __launch_bounds__(BLOCK_THREADS) void k_gtile(const GParams p)
             if (gx < 0 || gx >= p.W || gy < 0 || gy >= p.H) continue;
             float acc = 0.0f;
             for (int v = -s.ry; v <= s.ry; ++v) {
-                const float* row = src + (clampi(gy + v, 0, p.H - 1) - oy) * RW - ox;
+                // box index of the clamped cell (x, y) = (y - oy) * RW + (x - ox)
+                const int row = (clampi(gy + v, 0, p.H - 1) - oy) * RW - ox;
                 if (s.kind == G_STENCIL) {
-                    const float* w = p.w + s.woff + (v + s.ry) * kw + s.rx;
-                    for (int u = -s.rx; u <= s.rx; ++u) acc = fmaf(w[u], row[clampi(gx + u, 0, p.W - 1)], acc);
+                    const int w0 = s.woff + (v + s.ry) * kw + s.rx;
+                    for (int u = -s.rx; u <= s.rx; ++u)
+                        acc = fmaf(p.w[w0 + u], src[row + clampi(gx + u, 0, p.W - 1)], acc);
                 } else {
                     float h = 0.0f;
-                    for (int u = -s.rx; u <= s.rx; ++u) h = h + row[clampi(gx + u, 0, p.W - 1)];
+                    for (int u = -s.rx; u <= s.rx; ++u) h = h + src[row + clampi(gx + u, 0, p.W - 1)];
                     acc = acc + h;
                 }
             }
