@@ -160,6 +160,51 @@ def time_plan(plan, x, bufs, steps, warmup, stream):
     return float(np.mean(times)), float(np.median(times)), times
 
 
+def copy_ceiling_gbs(dev, nbytes=1 << 30, reps=5):
+    """Same-run device-to-device copy rate: (bytes read + bytes written) / time, GB/s."""
+    import torch
+    a = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return 2 * nbytes / (ms * 1e-3) / 1e9
+
+
+def pcie_inclusive(plan, x, bufs, stream, reps=3):
+    """End-to-end time of one pass including the host-to-device copy of the
+    input from pinned host memory (ms), and the copy alone (ms)."""
+    import torch
+    host = torch.empty(x.shape, dtype=x.dtype, pin_memory=True)
+    host.copy_(x)
+    out, pts, cnt, ws = bufs
+    torch.cuda.synchronize()
+    tot, cp = [], []
+    for _ in range(reps):
+        a = torch.cuda.Event(enable_timing=True)
+        m = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        x.copy_(host, non_blocking=True)
+        m.record(stream)
+        plan.run(x, out, pts, cnt, ws, stream=stream.cuda_stream)
+        b.record(stream)
+        torch.cuda.synchronize()
+        tot.append(a.elapsed_time(b))
+        cp.append(a.elapsed_time(m))
+    del host
+    return float(np.median(tot)), float(np.median(cp))
+
+
 def cpu_baseline(wl, ops, budget_s=15.0):
     """The oracle (FP64, unfused) on a bounded sample of the same workload."""
     import oracle
@@ -251,6 +296,14 @@ def main():
     f_mean, f_med, _ = time_plan(fused, x, fb, args.steps, args.warmup, stream)
     nfused = int(fb[2].item()) if fb[2] is not None else 0
     log(f"fused: {f_mean:.3f} ms/step mean, {f_med:.3f} median, {nfused} points")
+    pcie = None
+    if not args.fused_only:
+        e2e, h2d = pcie_inclusive(fused, x, fb, stream)
+        pcie = {"ms_per_step": round(e2e, 4), "mpx_s": round(npx / (e2e * 1e-3) / 1e6, 1),
+                "h2d_ms": round(h2d, 4), "h2d_GBs": round(x.numel() * x.element_size() / (h2d * 1e-3) / 1e9, 1),
+                "note": "input copied from pinned host memory inside the timed pass; not the headline value"}
+        log(f"with the host-to-device copy: {e2e:.3f} ms/step ({h2d:.3f} ms copy)")
+    copy_gbs = None if args.fused_only else copy_ceiling_gbs(dev)
 
     unf = None
     if not (args.no_unfused or args.fused_only):
@@ -293,6 +346,14 @@ def main():
                       "sizing": "autotuned" if args.autotune else "planner",
                       "points_per_step": nfused},
            "roofline": roof}
+    if copy_gbs is not None:
+        # the same bytes against a plain device copy measured in this run
+        rec["copy_ceiling_GBs"] = round(copy_gbs, 1)
+        roof["hbm_frac_of_copy"] = round(achieved_gbs / copy_gbs, 4)
+        if unf is not None:
+            unf["hbm_frac_of_copy"] = unf["algorithmic_GBs"] / copy_gbs
+    if pcie is not None:
+        rec["pcie_inclusive"] = pcie
     if unf is not None:
         rec["unfused"] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in unf.items()}
         rec["speedup_vs_unfused"] = round(u_mean / f_mean, 3)
