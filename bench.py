@@ -248,8 +248,8 @@ def main():
                     help="only run 5 plain device copies of MIB MiB (scale for memory counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py: this build runs on one GPU only; multi-GPU runs are not supported "
-              "(the temporal sharding that would split the video is described in DESIGN.md)", file=sys.stderr)
+        print("bench.py: runs on one GPU only; multi-GPU runs are not supported (the video would be "
+              "split along time, each GPU reading one frame before its range)", file=sys.stderr)
         sys.exit(2)
 
     import torch
