@@ -31,13 +31,14 @@ inline int row_strips(int W, int K, int halo = ROW_HX)
 // (one column per lane pair, K = 2).
 inline bool rowgen_group(int ch, int A, int B) { return group_has_window(ch, A, B); }
 
-// Columns per lane (2 or 3) that compute the fewest columns in total; 0 if the
-// frame is narrower than 128 columns.
+// Columns per lane (2 or 3): the choice that computes the fewest columns per
+// wavefront the SIMDs can hold (two columns per lane keep 5 waves per SIMD,
+// three keep 3); 0 if the frame is narrower than 128 columns.
 inline int row_strips_best(int W)
 {
     const int n2 = row_strips(W, 2), n3 = row_strips(W, 3);
     if (n2 == 0) return 0;
-    if (n3 > 0 && n3 * 192 < n2 * 128) return 3;
+    if (n3 > 0 && n3 * 192 * 5 < n2 * 128 * 3) return 3;
     return 2;
 }
 
