@@ -106,12 +106,13 @@ METRIC = "Mpixel/s fused vs unfused and HBM GB/s (% of peak), 800×600×1000 cha
 
 # HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE
 # passes, scaled by the plain-copy calibration (profiles/rowfuse_rgb800_counters.md).
-# Valid only for the kernel sources they were taken with: the key is a hash of them.
+# Valid only for the kernel sources and the launch geometry (columns per strip,
+# band rows, frames per work item) they were taken with: the key holds both.
 COUNTER_TRAFFIC = {
-    ("rgb800", "327b03c471f701ee"): {"fetch_bytes": 2.490e9, "write_bytes": 0.592e9,
-                                     "source": "profiles/rowfuse_rgb800_counters.md"},
+    ("rgb800", "7d4aa991cae9e8d8", (128, 55, 16)): {"fetch_bytes": 2.490e9, "write_bytes": 0.592e9,
+                                                    "source": "profiles/rowfuse_rgb800_counters.md"},
 }
-KERNEL_SOURCES = ["rowfuse.h", "rowgeom.h", "stage_math.h"]
+KERNEL_SOURCES = ["rowfuse.h", "stage_math.h"]
 
 
 def kernel_source_hash():
@@ -327,7 +328,8 @@ def main():
     achieved_gops = npx * opx / (f_mean * 1e-3) / 1e9
     achieved_gbs = alg_bytes / (f_mean * 1e-3) / 1e9
     traffic = None
-    ct = COUNTER_TRAFFIC.get((args.workload, kernel_source_hash()))
+    ct = COUNTER_TRAFFIC.get((args.workload, kernel_source_hash(),
+                              (dominant.tile_w, dominant.tile_h, dominant.frames_per_block)))
     if ct is not None and dominant.engine == fz.FZ_ENGINE_ROW:
         # measured HBM bytes per launch over this run's launch time, GB/s
         traffic = round((ct["fetch_bytes"] + ct["write_bytes"]) / (f_mean * 1e-3) / 1e9, 1)
