@@ -51,6 +51,87 @@ __device__ __forceinline__ int xcd_contiguous(int b, int nb)
 
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
+// Quotient and remainder of e by a wavefront-uniform divisor d > 0 without an
+// integer divide (which the hardware lacks): a single-precision estimate,
+// then one correction step.  Exact for 0 <= e < 2^20 (a box has at most
+// 40960 cells), where the estimate is off by at most one.
+struct UDiv {
+    int d;
+    float inv;
+    __device__ __forceinline__ explicit UDiv(int dd) : d(dd), inv(1.0f / (float)dd) {}
+    __device__ __forceinline__ int quot(int e, int& rem) const
+    {
+        int q = (int)((float)e * inv);
+        int r = e - q * d;
+        if (r < 0) {
+            --q;
+            r += d;
+        } else if (r >= d) {
+            ++q;
+            r -= d;
+        }
+        rem = r;
+        return q;
+    }
+};
+
+// Four neighbouring cells of one row of a window stage whose whole input box
+// lies inside the frame (no clamping): each input row is read once into
+// registers, 4 + 2RX values, and every cell sums in the same order as the
+// general path (rows top to bottom, each row left to right), so the bits are
+// the same.  `base` is the box index of the first cell.
+template <bool STENCIL, int RX, int RY>
+__device__ __forceinline__ void window4(const float* src, int RW, int base, const float* w, float (&acc)[4])
+{
+#pragma unroll
+    for (int k = 0; k < 4; ++k) acc[k] = 0.0f;
+#pragma unroll
+    for (int v = -RY; v <= RY; ++v) {
+        float x[4 + 2 * RX];
+        const int r0 = base + v * RW - RX;
+#pragma unroll
+        for (int q = 0; q < 4 + 2 * RX; ++q) x[q] = src[r0 + q];
+        if constexpr (STENCIL) {
+#pragma unroll
+            for (int u = -RX; u <= RX; ++u) {
+                const float wv = w[(v + RY) * (2 * RX + 1) + (u + RX)];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) acc[k] = fmaf(wv, x[k + u + RX], acc[k]);
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                float h = 0.0f;
+#pragma unroll
+                for (int u = -RX; u <= RX; ++u) h = h + x[k + u + RX];
+                acc[k] = acc[k] + h;
+            }
+        }
+    }
+}
+template <bool STENCIL, int RX>
+__device__ __forceinline__ void window4_ry(int ry, const float* src, int RW, int base, const float* w,
+                                           float (&acc)[4])
+{
+    switch (ry) {
+    case 0: window4<STENCIL, RX, 0>(src, RW, base, w, acc); break;
+    case 1: window4<STENCIL, RX, 1>(src, RW, base, w, acc); break;
+    case 2: window4<STENCIL, RX, 2>(src, RW, base, w, acc); break;
+    default: window4<STENCIL, RX, 3>(src, RW, base, w, acc); break;
+    }
+}
+template <bool STENCIL>
+__device__ __forceinline__ void window4_r(int rx, int ry, const float* src, int RW, int base, const float* w,
+                                          float (&acc)[4])
+{
+    switch (rx) {
+    case 0: window4_ry<STENCIL, 0>(ry, src, RW, base, w, acc); break;
+    case 1: window4_ry<STENCIL, 1>(ry, src, RW, base, w, acc); break;
+    case 2: window4_ry<STENCIL, 2>(ry, src, RW, base, w, acc); break;
+    default: window4_ry<STENCIL, 3>(ry, src, RW, base, w, acc); break;
+    }
+}
+
 template <int TW, int TH>
 __global__ __launch_bounds__(BLOCK_THREADS) void k_gtile(const GParams p)
 {
@@ -66,13 +147,17 @@ __global__ __launch_bounds__(BLOCK_THREADS) void k_gtile(const GParams p)
     const int t = b / p.tiles_y;
     const int ox = tx * TW - p.hx, oy = ty * TH - p.hy;  // frame position of the box's first cell
     const size_t fbase = (size_t)t * p.W * p.H;
+    // the whole input box inside the frame: no read needs clamping
+    const bool interior = ox >= 0 && oy >= 0 && ox + RW <= p.W && oy + RH <= p.H;
 
     int lead = 0;
     while (lead < p.n && p.st[lead].kind == G_POINT) ++lead;
 
     // the input box; cells outside the frame are never read (reads clamp)
+    const UDiv by_rw(RW);
     for (int e = threadIdx.x; e < RW * RH; e += BLOCK_THREADS) {
-        const int ly = e / RW, lx = e - ly * RW;
+        int lx;
+        const int ly = by_rw.quot(e, lx);
         const int gx = ox + lx, gy = oy + ly;
         if (gx < 0 || gx >= p.W || gy < 0 || gy >= p.H) continue;
         const size_t gi = fbase + (size_t)gy * p.W + gx;
@@ -92,30 +177,61 @@ __global__ __launch_bounds__(BLOCK_THREADS) void k_gtile(const GParams p)
         const int OW = TW + 2 * ohx, OH = TH + 2 * ohy;   // cells this stage computes
         const int bx = p.hx - ohx, by = p.hy - ohy;       // their first cell in box coordinates
         const int kw = 2 * s.rx + 1;
-        for (int e = threadIdx.x; e < OW * OH; e += BLOCK_THREADS) {
-            const int cy = e / OW, cx = e - cy * OW;
-            const int lx = bx + cx, ly = by + cy;
-            const int gx = ox + lx, gy = oy + ly;
-            if (gx < 0 || gx >= p.W || gy < 0 || gy >= p.H) continue;
-            float acc = 0.0f;
-            for (int v = -s.ry; v <= s.ry; ++v) {
-                // box index of the clamped cell (x, y) = (y - oy) * RW + (x - ox)
-                const int row = (clampi(gy + v, 0, p.H - 1) - oy) * RW - ox;
-                if (s.kind == G_STENCIL) {
-                    const int w0 = s.woff + (v + s.ry) * kw + s.rx;
-                    for (int u = -s.rx; u <= s.rx; ++u)
-                        acc = fmaf(p.w[w0 + u], src[row + clampi(gx + u, 0, p.W - 1)], acc);
-                } else {
-                    float h = 0.0f;
-                    for (int u = -s.rx; u <= s.rx; ++u) h = h + src[row + clampi(gx + u, 0, p.W - 1)];
-                    acc = acc + h;
+        if (interior) {
+            // four neighbouring cells per thread; the last group of a row may
+            // read up to two cells past it (into the next row or the padding)
+            const int NQ = (OW + 3) >> 2;
+            const float* w = p.w + s.woff;
+            const UDiv by_nq(NQ);
+            for (int e = threadIdx.x; e < NQ * OH; e += BLOCK_THREADS) {
+                int qx;
+                const int cy = by_nq.quot(e, qx), cx = qx << 2;
+                const int lx = bx + cx, ly = by + cy;
+                float acc[4];
+                if (s.kind == G_STENCIL)
+                    window4_r<true>(s.rx, s.ry, src, RW, ly * RW + lx, w, acc);
+                else
+                    window4_r<false>(s.rx, s.ry, src, RW, ly * RW + lx, w, acc);
+                const int nk = min(4, OW - cx);
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    if (k >= nk) break;
+                    float v = acc[k];
+                    for (int q = i + 1; q < j; ++q) v = gpoint(p.st[q], v);
+                    if (last)
+                        p.out[fbase + (size_t)(oy + ly) * p.W + (ox + lx + k)] = v;
+                    else
+                        dst[ly * RW + lx + k] = v;
                 }
             }
-            for (int q = i + 1; q < j; ++q) acc = gpoint(p.st[q], acc);
-            if (last)
-                p.out[fbase + (size_t)gy * p.W + gx] = acc;
-            else
-                dst[ly * RW + lx] = acc;
+        } else {
+            const UDiv by_ow(OW);
+            for (int e = threadIdx.x; e < OW * OH; e += BLOCK_THREADS) {
+                int cx;
+                const int cy = by_ow.quot(e, cx);
+                const int lx = bx + cx, ly = by + cy;
+                const int gx = ox + lx, gy = oy + ly;
+                if (gx < 0 || gx >= p.W || gy < 0 || gy >= p.H) continue;
+                float acc = 0.0f;
+                for (int v = -s.ry; v <= s.ry; ++v) {
+                    // box index of the clamped cell (x, y) = (y - oy) * RW + (x - ox)
+                    const int row = (clampi(gy + v, 0, p.H - 1) - oy) * RW - ox;
+                    if (s.kind == G_STENCIL) {
+                        const int w0 = s.woff + (v + s.ry) * kw + s.rx;
+                        for (int u = -s.rx; u <= s.rx; ++u)
+                            acc = fmaf(p.w[w0 + u], src[row + clampi(gx + u, 0, p.W - 1)], acc);
+                    } else {
+                        float h = 0.0f;
+                        for (int u = -s.rx; u <= s.rx; ++u) h = h + src[row + clampi(gx + u, 0, p.W - 1)];
+                        acc = acc + h;
+                    }
+                }
+                for (int q = i + 1; q < j; ++q) acc = gpoint(p.st[q], acc);
+                if (last)
+                    p.out[fbase + (size_t)gy * p.W + gx] = acc;
+                else
+                    dst[ly * RW + lx] = acc;
+            }
         }
         if (last) break;
         __syncthreads();
