@@ -72,7 +72,8 @@ Segment price_group(const fz_plan& p, int a, int b, int req_w, int req_h, int re
     if (s.tpb > p.T) s.tpb = p.T;
     // row-marching: the Harris-chain kernel for its groups, the generic kernel
     // (two columns per lane) for every other group with a window stage
-    const bool row_special = row_group(ch, A, B) && row_strips_best(p.W) > 0;
+    const bool rgb_in = chain_op(ch, A) == FZ_OP_RGB2GRAY;
+    const bool row_special = row_group(ch, A, B) && row_strips_best(p.W, rgb_in) > 0;
     const bool row_generic = !row_special && rowgen_group(ch, A, B) && row_strips(p.W, 2, s.halo) > 0;
     const bool row_ok = !s.streaming && (row_special || row_generic) && p.H >= 8 && req_engine != FZ_ENGINE_TILE &&
                         req_w == 0;
@@ -84,9 +85,9 @@ Segment price_group(const fz_plan& p, int a, int b, int req_w, int req_h, int re
         s.engine = FZ_ENGINE_ROW;
         s.row_gen = row_generic ? 1 : 0;
         const bool diff = chain_op(ch, B) == FZ_OP_FRAMEDIFF;
-        s.row_k = row_generic ? 2 : row_strips_best(p.W);
+        s.row_k = row_generic ? 2 : row_strips_best(p.W, rgb_in);
         s.nstrips = row_strips(p.W, s.row_k, row_generic ? s.halo : ROW_HX);
-        const int slots = row_generic ? ROW_SLOTS_GENERIC : (s.row_k == 2 ? ROW_SLOTS_K2 : ROW_SLOTS_K3);
+        const int slots = row_generic ? ROW_SLOTS_GENERIC : row_slots(s.row_k, rgb_in);
         const RowShape rs = row_shape(p.H, p.T, s.nstrips, diff, req_h, req_tpb, slots);
         s.tpb = rs.tt;
         s.nchunks = (p.T + s.tpb - 1) / s.tpb;

@@ -7,7 +7,9 @@
 //   * a wavefront owns a strip of 64*K columns (K adjacent columns per lane)
 //     of a band of rows of one frame and marches down the rows; every window
 //     stage keeps the few rows it still needs in registers (rings of 2r+1
-//     rows), so nothing is staged in LDS and no barrier is needed;
+//     rows; the 5x5 window sums keep sums of row pairs instead, and share
+//     the pair sums of neighbouring columns across lanes), so nothing is
+//     staged in LDS and no barrier is needed;
 //   * horizontal neighbours come from the adjacent lanes through DPP wave
 //     shifts; a lane at the strip's edge receives its own edge value, which is
 //     exactly the replicate border when the strip touches the frame edge (and a
@@ -79,6 +81,32 @@ __device__ __forceinline__ void extend_row(const float (&v)[K], float (&e)[K + 2
     }
 }
 
+// Horizontal pass of the 5-wide window sum of a row held K per lane:
+// s[k] = sum5(e[k], ..., e[k+4]) over the extended row e = extend_row<K, 2>(v),
+// computed from pair sums p[j] = e[j] + e[j+1].  Window k needs p[k], p[k+2]
+// and e[k+4]; each pair of adjacent columns is added once, by the lane that
+// holds its right column, and a lane reads its neighbours' pairs through DPP
+// shifts: p[0] is the left lane's p[K] and p[K+1] the right lane's p[1].  At
+// a frame edge the shifted pair of the edge lane is the sum of its own edge
+// column with itself, which is what the replicate border gives.  Same bits as
+// sum5 on extend_row's output.
+template <int K, bool EL, bool ER>
+__device__ __forceinline__ void box5_row(const float (&v)[K], float (&s)[K])
+{
+    static_assert(K >= 2, "two or more columns per lane");
+    float p[K + 2];
+    p[1] = dpp_from_left<EL>(v[K - 1], v[0]) + v[0];  // straddles the left lane boundary
+#pragma unroll
+    for (int j = 2; j <= K; ++j) p[j] = v[j - 2] + v[j - 1];
+    p[0] = dpp_from_left<EL>(p[K], p[1]);  // at the left frame edge p[1] = v[0] + v[0]
+    p[K + 1] = dpp_from_right<ER>(p[1], ER ? v[K - 1] + v[K - 1] : 0.0f);
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const float e4 = k + 2 < K ? v[k + 2] : dpp_from_right<ER>(v[k + 2 - K], v[K - 1]);
+        s[k] = (p[k] + p[k + 2]) + e4;
+    }
+}
+
 // Raw buffer over `bytes` bytes at `base`: a store whose offset is at or past
 // `bytes` is dropped by the hardware, which lets every lane issue its store
 // with no divergent branch (columns outside the strip's output range get an
@@ -114,7 +142,8 @@ struct RowState {
     static constexpr int NB = RGB ? 3 * K : K;  // input bytes per lane and row
     float h[5][K];     // Gaussian horizontal pass
     float g[3][K];     // Gaussian output
-    float b[5][3][K];  // window-sum horizontal pass, 3 channels
+    float bp[3][K];    // window-sum horizontal pass of the previous row, 3 channels
+    float q[3][3][K];  // pairs of consecutive horizontal-pass rows, q_r = b_r + b_(r+1)
     float rt[3][K];    // thresholded response
     float m[3][K];     // 3-wide horizontal maximum of rt
     RawRow<NB> raw[3];  // input rows, two loaded ahead
@@ -131,7 +160,7 @@ struct RowCtx {
     int lo_in, hi_in, lo_g, hi_g, lo_s, hi_s, lo_b, hi_b;
     // iteration j computes a stage's row iff (unsigned)(j - j*) < n*: the rows
     // [lo, hi) of each stage mapped to iterations (row = y0 - 6 + j - lag)
-    int jp, np_, ji, ni, jg, ng, js, ns, jb, nb, jn, nn;
+    int jp, np_, ji, ni, jg, ng, js, ns, jq, nq, jb, nb, jn, nn;
     uint8_t* prev;            // LDS previous-frame mask bits of this wavefront (DIFF)
 };
 
@@ -231,6 +260,7 @@ __device__ __forceinline__ void row_step(RowState<K, RGB>& st, const RowCtx& c, 
     }
     // Sobel, products and the horizontal pass of the window sums: row row_in - 3
     const int rs = row_in - 3;
+    float bn[3][K];  // horizontal pass of row rs
     if ((unsigned)(j - c.js) < (unsigned)c.ns) {
         float sv[K], ev[K];
 #pragma unroll
@@ -250,30 +280,30 @@ __device__ __forceinline__ void row_step(RowState<K, RGB>& st, const RowCtx& c, 
             products(ix, iy, pr[0][k], pr[1][k], pr[2][k]);
         }
 #pragma unroll
-        for (int ch = 0; ch < 3; ++ch) {
-            float e[K + 4];
-            extend_row<K, 2, EL, ER>(pr[ch], e);
+        for (int ch = 0; ch < 3; ++ch) box5_row<K, EL, ER>(pr[ch], bn[ch]);
+        if (rs == 0) {  // the row above the frame's first row is that row
 #pragma unroll
-            for (int k = 0; k < K; ++k) st.b[U5][ch][k] = sum5(e[k], e[k + 1], e[k + 2], e[k + 3], e[k + 4]);
+            for (int ch = 0; ch < 3; ++ch) copy_row<K>(st.bp[ch], bn[ch]);
         }
-        if (rs == 0) {
+    } else {
+        // below the frame's last row: the replicate border (elsewhere unused)
 #pragma unroll
-            for (int ch = 0; ch < 3; ++ch) {
-                copy_row<K>(st.b[(U + 4) % 5][ch], st.b[U5][ch]);
-                copy_row<K>(st.b[(U + 3) % 5][ch], st.b[U5][ch]);
-            }
-        }
+        for (int ch = 0; ch < 3; ++ch) copy_row<K>(bn[ch], st.bp[ch]);
     }
     // Window sums (vertical), Harris, threshold, 3-wide maximum: row row_in - 5
     const int rb = row_in - 5;
     if ((unsigned)(j - c.jb) < (unsigned)c.nb) {
+        // sum5 over rows rb-2 .. rb+2: (q_(rb-2) + q_rb) + b_(rb+2), the same
+        // operations in the same order, with each row pair added once
+        // (the pair of the two newest rows replaces q_(rb-2) right after its read)
         float s[3][K];
 #pragma unroll
         for (int ch = 0; ch < 3; ++ch)
 #pragma unroll
-            for (int k = 0; k < K; ++k)
-                s[ch][k] = sum5(st.b[(U + 1) % 5][ch][k], st.b[(U + 2) % 5][ch][k], st.b[(U + 3) % 5][ch][k],
-                                st.b[(U + 4) % 5][ch][k], st.b[U5][ch][k]);
+            for (int k = 0; k < K; ++k) {
+                s[ch][k] = (st.q[U3][ch][k] + st.q[(U + 2) % 3][ch][k]) + bn[ch][k];
+                st.q[U3][ch][k] = st.bp[ch][k] + bn[ch][k];
+            }
 #pragma unroll
         for (int k = 0; k < K; ++k) st.rt[U3][k] = threshold(harris(s[0][k], s[1][k], s[2][k], p.k), p.thr);
         float e[K + 2];
@@ -285,6 +315,21 @@ __device__ __forceinline__ void row_step(RowState<K, RGB>& st, const RowCtx& c, 
             copy_row<K>(st.m[(U + 2) % 3], st.m[U3]);
         }
     }
+    // Row pair q_(rs-1) = b_(rs-1) + b_rs on the iterations whose window sums
+    // did not already form it (the first ones of the band); at the frame's
+    // first row the two pairs above it are both twice row 0 (replicate border)
+    if ((unsigned)(j - c.jq) < (unsigned)c.nq) {
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch)
+#pragma unroll
+            for (int k = 0; k < K; ++k) st.q[U3][ch][k] = st.bp[ch][k] + bn[ch][k];
+        if (rs == 0) {
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch) copy_row<K>(st.q[(U + 2) % 3][ch], st.q[U3][ch]);
+        }
+    }
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) copy_row<K>(st.bp[ch], bn[ch]);
     // Suppression, feature points, output: row row_in - 6
     const int rn = row_in - 6;
     if ((unsigned)(j - c.jn) < (unsigned)c.nn) {
@@ -319,14 +364,11 @@ __device__ __forceinline__ void row_step(RowState<K, RGB>& st, const RowCtx& c, 
                                                      (c.valid >> k & 1u) ? c.lane_out + k : DROP, soff, 0);
         }
     }
-    // bottom replicate: after the last frame row, copy it into the next slot of
-    // each ring, once per iteration, for as many rows as the consumer reads
+    // bottom replicate of the Gaussian and response rings: after the last
+    // frame row, copy it into the next slot, once per iteration, for as many
+    // rows as the consumer reads
     if (row_in >= c.Hf - 1 && row_in <= c.Hf) copy_row<K>(st.h[(U + 1) % 5], st.h[U5]);
     if (rg == c.Hf - 1) copy_row<K>(st.g[(U + 1) % 3], st.g[U3]);
-    if (rs >= c.Hf - 1 && rs <= c.Hf) {
-#pragma unroll
-        for (int ch = 0; ch < 3; ++ch) copy_row<K>(st.b[(U + 1) % 5][ch], st.b[U5][ch]);
-    }
     if (rb == c.Hf - 1) {
         copy_row<K>(st.rt[(U + 1) % 3], st.rt[U3]);
         copy_row<K>(st.m[(U + 1) % 3], st.m[U3]);
@@ -413,6 +455,13 @@ __device__ __forceinline__ void row_item(const SegParams& p, const RowItem& it, 
     c.ns = c.hi_s - c.lo_s;
     c.jb = c.lo_b + base + 5;
     c.nb = c.hi_b - c.lo_b;
+    // row pairs q_(s-1): the window sums of rows [lo_b, hi_b) read q_(lo_b-2) ..
+    // q_(hi_b-1), formed on the iterations s = max(lo_b - 1, lo_s) .. hi_b; from
+    // s = lo_b + 2 on, the window-sum step forms them, so the pair step runs on
+    // the iterations before it
+    const int lo_q = max(c.lo_b - 1, c.lo_s);
+    c.jq = lo_q + base + 3;
+    c.nq = c.lo_b + 2 - lo_q;
     c.jn = c.y0 + base + 6;
     c.nn = c.y1 - c.y0;
     c.prev = prev_lds;

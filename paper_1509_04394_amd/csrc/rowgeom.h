@@ -1,18 +1,22 @@
 // Geometry of the row-marching kernel, shared by the planner and the launcher.
 #pragma once
 
+#include <algorithm>
+
 #include "fz_ops.h"
 
 namespace fz {
 
 constexpr int ROW_HX = 6;     // horizontal and vertical halo of the chain: 2 + 1 + 2 + 1
 constexpr int ROW_WAVES = 4;  // independent wavefronts per workgroup
-// Wavefronts the 256 CUs hold at once: 4 SIMDs each, and waves per SIMD as
-// the kernel's registers allow (512 per lane, allocated in blocks of 8): the
-// Harris row kernel uses <= 96 with two columns per lane (5 waves) and <= 144
-// with three (3 waves); 4 is assumed for the generic row kernel.
-constexpr int ROW_SLOTS_K2 = 256 * 4 * 5;
-constexpr int ROW_SLOTS_K3 = 256 * 4 * 3;
+// Wavefronts per SIMD of the Harris row kernel, as its registers allow (512
+// per lane, allocated in blocks of 8): two columns per lane take <= 85
+// registers with RGB input (5 waves) and <= 80 with gray input (6 waves),
+// three columns <= 128 (4 waves).
+inline int row_waves(int K, bool rgb) { return K == 3 ? 4 : (rgb ? 5 : 6); }
+// Wavefronts the 256 CUs (4 SIMDs each) hold at once; 4 per SIMD is assumed
+// for the generic row kernel.
+inline int row_slots(int K, bool rgb) { return 256 * 4 * row_waves(K, rgb); }
 constexpr int ROW_SLOTS_GENERIC = 256 * 4 * 4;
 
 // Groups the row kernel implements: gray conversion or Gaussian first, suppression
@@ -32,13 +36,12 @@ inline int row_strips(int W, int K, int halo = ROW_HX)
 inline bool rowgen_group(int ch, int A, int B) { return group_has_window(ch, A, B); }
 
 // Columns per lane (2 or 3): the choice that computes the fewest columns per
-// wavefront the SIMDs can hold (two columns per lane keep 5 waves per SIMD,
-// three keep 3); 0 if the frame is narrower than 128 columns.
-inline int row_strips_best(int W)
+// wavefront the SIMDs can hold; 0 if the frame is narrower than 128 columns.
+inline int row_strips_best(int W, bool rgb)
 {
     const int n2 = row_strips(W, 2), n3 = row_strips(W, 3);
     if (n2 == 0) return 0;
-    if (n3 > 0 && n3 * 192 * 5 < n2 * 128 * 3) return 3;
+    if (n3 > 0 && n3 * 192 * row_waves(2, rgb) < n2 * 128 * row_waves(3, rgb)) return 3;
     return 2;
 }
 
@@ -46,9 +49,11 @@ inline int row_lds_bytes(int band_h) { return ROW_WAVES * band_h * 64; }
 
 // Rows per band and frames per work item.  A work item marches band_h + 2*HX
 // rows per frame over tt frames (plus the frame before them when the group
-// ends in the frame difference); items run in rounds of `slots` wavefronts.
-// Pick the pair with the least (rounds x item length); explicit requests
-// (> 0) are kept.
+// ends in the frame difference); items run in rounds of `slots` wavefronts,
+// fewer when the frame difference's LDS rows (one workgroup of ROW_WAVES
+// wavefronts per SIMD slot) do not fit 160 KB per CU that many times.  Pick
+// the pair with the least (rounds x item length); explicit requests (> 0)
+// are kept.
 struct RowShape {
     int band_h, tt;
 };
@@ -67,7 +72,9 @@ inline RowShape row_shape(int H, int T, int nstrips, bool diff, int req_h, int r
             if (diff && bh > 256) continue;
             if (bh < 16 && req_h <= 0 && nb > 1) break;
             const long long items = (long long)nstrips * ((H + bh - 1) / bh) * ((T + t - 1) / t);
-            const long long rounds = (items + slots - 1) / slots;
+            long long fit = slots;
+            if (diff) fit = std::min(fit, (long long)256 * ROW_WAVES * (163840 / row_lds_bytes(bh)));
+            const long long rounds = (items + fit - 1) / fit;
             const double cost = (double)rounds * (bh + 2 * ROW_HX) * (t + (diff ? 1 : 0));
             if (best_cost < 0 || cost < best_cost) {
                 best_cost = cost;

@@ -69,10 +69,12 @@ __device__ __forceinline__ void products(float ix, float iy, float& pxx, float& 
     pyy = iy * iy;
 }
 
-// Five-term sum, left to right.
+// Five-term sum: the two leading pairs, then the fifth term.  Neighbouring
+// windows of a row then share their pair sums (the row kernel adds each pair
+// of adjacent columns once).
 __device__ __forceinline__ float sum5(float a, float b, float c, float d, float e)
 {
-    return (((a + b) + c) + d) + e;
+    return ((a + b) + (c + d)) + e;
 }
 
 __device__ __forceinline__ float harris(float sxx, float sxy, float syy, float k)
