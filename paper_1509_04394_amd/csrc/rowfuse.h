@@ -256,7 +256,7 @@ __device__ __forceinline__ void row_step(RowState<K, RGB>& st, const RowCtx& c, 
         for (int k = 0; k < K; ++k)
             st.g[U3][k] = gauss5_taps(p.gw, st.h[(U + 1) % 5][k], st.h[(U + 2) % 5][k], st.h[(U + 3) % 5][k],
                                       st.h[(U + 4) % 5][k], st.h[U5][k]);
-        if (rg == 0) copy_row<K>(st.g[(U + 2) % 3], st.g[U3]);
+        if (__builtin_expect(rg == 0, 0)) copy_row<K>(st.g[(U + 2) % 3], st.g[U3]);
     }
     // Sobel, products and the horizontal pass of the window sums: row row_in - 3
     const int rs = row_in - 3;
@@ -366,9 +366,9 @@ __device__ __forceinline__ void row_step(RowState<K, RGB>& st, const RowCtx& c, 
     }
     // bottom replicate of the Gaussian and response rings: after the last
     // frame row, copy it into the next slot, once per iteration, for as many
-    // rows as the consumer reads
-    if (row_in >= c.Hf - 1 && row_in <= c.Hf) copy_row<K>(st.h[(U + 1) % 5], st.h[U5]);
-    if (rg == c.Hf - 1) copy_row<K>(st.g[(U + 1) % 3], st.g[U3]);
+    // rows as the consumer reads (rare: branches, not selects on every row)
+    if (__builtin_expect(row_in >= c.Hf - 1 && row_in <= c.Hf, 0)) copy_row<K>(st.h[(U + 1) % 5], st.h[U5]);
+    if (__builtin_expect(rg == c.Hf - 1, 0)) copy_row<K>(st.g[(U + 1) % 3], st.g[U3]);
     if (rb == c.Hf - 1) {
         copy_row<K>(st.rt[(U + 1) % 3], st.rt[U3]);
         copy_row<K>(st.m[(U + 1) % 3], st.m[U3]);
