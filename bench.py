@@ -109,7 +109,7 @@ METRIC = "Mpixel/s fused vs unfused and HBM GB/s (% of peak), 800×600×1000 cha
 # Valid only for the kernel sources and the launch geometry (columns per strip,
 # band rows, frames per work item) they were taken with: the key holds both.
 COUNTER_TRAFFIC = {
-    ("rgb800", "3a5655a7a2da9af1", (128, 55, 16)): {"fetch_bytes": 2.486e9, "write_bytes": 0.591e9,
+    ("rgb800", "ed9bc057f0e37bfd", (128, 55, 16)): {"fetch_bytes": 2.488e9, "write_bytes": 0.590e9,
                                                     "source": "profiles/rowfuse_rgb800_counters.md"},
 }
 KERNEL_SOURCES = ["rowfuse.h", "stage_math.h"]
