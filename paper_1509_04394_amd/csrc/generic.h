@@ -42,8 +42,8 @@ struct GParams {
 // LDS of the generic tile kernel: the input box (TW + 2hx) x (TH + 2hy) as
 // f32, doubled when a window step has to hand its output to a later window
 // step (the last window step writes global memory directly), plus GEN_PAD
-// floats: a thread computes four neighbouring cells of a row and reads the
-// row two cells past the last one it needs.
+// floats: a thread computes five neighbouring cells of a row and may read the
+// row up to four cells past the last one it needs.
 constexpr int GEN_PAD = 4;
 FZ_HD constexpr int generic_lds_bytes(int tw, int th, int hx, int hy, int nwin)
 {

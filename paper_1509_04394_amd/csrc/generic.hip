@@ -75,32 +75,36 @@ struct UDiv {
     }
 };
 
-// Four neighbouring cells of one row of a window stage whose whole input box
+// GQ neighbouring cells of one row of a window stage whose whole input box
 // lies inside the frame (no clamping): each input row is read once into
-// registers, 4 + 2RX values, and every cell sums in the same order as the
+// registers, GQ + 2RX values, and every cell sums in the same order as the
 // general path (rows top to bottom, each row left to right), so the bits are
-// the same.  `base` is the box index of the first cell.
+// the same.  `base` is the box index of the first cell.  GQ is odd: the
+// groups' first cells then lie GQ words apart from lane to lane, a stride
+// coprime with the LDS bank count, so the lanes of a read or write fall on
+// distinct banks (with four cells per thread, four lanes share each bank).
+constexpr int GQ = 5;
 template <bool STENCIL, int RX, int RY>
-__device__ __forceinline__ void window4(const float* src, int RW, int base, const float* w, float (&acc)[4])
+__device__ __forceinline__ void windowq(const float* src, int RW, int base, const float* w, float (&acc)[GQ])
 {
 #pragma unroll
-    for (int k = 0; k < 4; ++k) acc[k] = 0.0f;
+    for (int k = 0; k < GQ; ++k) acc[k] = 0.0f;
 #pragma unroll
     for (int v = -RY; v <= RY; ++v) {
-        float x[4 + 2 * RX];
+        float x[GQ + 2 * RX];
         const int r0 = base + v * RW - RX;
 #pragma unroll
-        for (int q = 0; q < 4 + 2 * RX; ++q) x[q] = src[r0 + q];
+        for (int q = 0; q < GQ + 2 * RX; ++q) x[q] = src[r0 + q];
         if constexpr (STENCIL) {
 #pragma unroll
             for (int u = -RX; u <= RX; ++u) {
                 const float wv = w[(v + RY) * (2 * RX + 1) + (u + RX)];
 #pragma unroll
-                for (int k = 0; k < 4; ++k) acc[k] = fmaf(wv, x[k + u + RX], acc[k]);
+                for (int k = 0; k < GQ; ++k) acc[k] = fmaf(wv, x[k + u + RX], acc[k]);
             }
         } else {
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
+            for (int k = 0; k < GQ; ++k) {
                 float h = 0.0f;
 #pragma unroll
                 for (int u = -RX; u <= RX; ++u) h = h + x[k + u + RX];
@@ -110,25 +114,25 @@ __device__ __forceinline__ void window4(const float* src, int RW, int base, cons
     }
 }
 template <bool STENCIL, int RX>
-__device__ __forceinline__ void window4_ry(int ry, const float* src, int RW, int base, const float* w,
-                                           float (&acc)[4])
+__device__ __forceinline__ void windowq_ry(int ry, const float* src, int RW, int base, const float* w,
+                                           float (&acc)[GQ])
 {
     switch (ry) {
-    case 0: window4<STENCIL, RX, 0>(src, RW, base, w, acc); break;
-    case 1: window4<STENCIL, RX, 1>(src, RW, base, w, acc); break;
-    case 2: window4<STENCIL, RX, 2>(src, RW, base, w, acc); break;
-    default: window4<STENCIL, RX, 3>(src, RW, base, w, acc); break;
+    case 0: windowq<STENCIL, RX, 0>(src, RW, base, w, acc); break;
+    case 1: windowq<STENCIL, RX, 1>(src, RW, base, w, acc); break;
+    case 2: windowq<STENCIL, RX, 2>(src, RW, base, w, acc); break;
+    default: windowq<STENCIL, RX, 3>(src, RW, base, w, acc); break;
     }
 }
 template <bool STENCIL>
-__device__ __forceinline__ void window4_r(int rx, int ry, const float* src, int RW, int base, const float* w,
-                                          float (&acc)[4])
+__device__ __forceinline__ void windowq_r(int rx, int ry, const float* src, int RW, int base, const float* w,
+                                          float (&acc)[GQ])
 {
     switch (rx) {
-    case 0: window4_ry<STENCIL, 0>(ry, src, RW, base, w, acc); break;
-    case 1: window4_ry<STENCIL, 1>(ry, src, RW, base, w, acc); break;
-    case 2: window4_ry<STENCIL, 2>(ry, src, RW, base, w, acc); break;
-    default: window4_ry<STENCIL, 3>(ry, src, RW, base, w, acc); break;
+    case 0: windowq_ry<STENCIL, 0>(ry, src, RW, base, w, acc); break;
+    case 1: windowq_ry<STENCIL, 1>(ry, src, RW, base, w, acc); break;
+    case 2: windowq_ry<STENCIL, 2>(ry, src, RW, base, w, acc); break;
+    default: windowq_ry<STENCIL, 3>(ry, src, RW, base, w, acc); break;
     }
 }
 
@@ -178,23 +182,23 @@ __global__ __launch_bounds__(BLOCK_THREADS) void k_gtile(const GParams p)
         const int bx = p.hx - ohx, by = p.hy - ohy;       // their first cell in box coordinates
         const int kw = 2 * s.rx + 1;
         if (interior) {
-            // four neighbouring cells per thread; the last group of a row may
-            // read up to two cells past it (into the next row or the padding)
-            const int NQ = (OW + 3) >> 2;
+            // GQ neighbouring cells per thread; the last group of a row may
+            // read up to GQ - 1 cells past it (into the next row or the padding)
+            const int NQ = (OW + GQ - 1) / GQ;
             const float* w = p.w + s.woff;
             const UDiv by_nq(NQ);
             for (int e = threadIdx.x; e < NQ * OH; e += BLOCK_THREADS) {
                 int qx;
-                const int cy = by_nq.quot(e, qx), cx = qx << 2;
+                const int cy = by_nq.quot(e, qx), cx = qx * GQ;
                 const int lx = bx + cx, ly = by + cy;
-                float acc[4];
+                float acc[GQ];
                 if (s.kind == G_STENCIL)
-                    window4_r<true>(s.rx, s.ry, src, RW, ly * RW + lx, w, acc);
+                    windowq_r<true>(s.rx, s.ry, src, RW, ly * RW + lx, w, acc);
                 else
-                    window4_r<false>(s.rx, s.ry, src, RW, ly * RW + lx, w, acc);
-                const int nk = min(4, OW - cx);
+                    windowq_r<false>(s.rx, s.ry, src, RW, ly * RW + lx, w, acc);
+                const int nk = min(GQ, OW - cx);
 #pragma unroll
-                for (int k = 0; k < 4; ++k) {
+                for (int k = 0; k < GQ; ++k) {
                     if (k >= nk) break;
                     float v = acc[k];
                     for (int q = i + 1; q < j; ++q) v = gpoint(p.st[q], v);
