@@ -20,3 +20,20 @@ def test_help_lists_the_contract_flags():
     assert p.returncode == 0
     for flag in ("--gpus", "--steps", "--warmup", "--workload"):
         assert flag in p.stdout
+
+
+def test_algorithmic_op_counts():
+    """The VALU roof's numerator: 63 ops per pixel for the RGB chain (separable
+    passes, intermediates formed once, shared pair sums in the window sums),
+    and the generic workload's per-stage counts (taps, window elements, one per
+    point op)."""
+    sys.path.insert(0, ROOT)
+    import bench
+    from paper_1509_04394_amd import fz
+    assert bench.ops_per_px(fz.RGB_HARRIS_CHAIN) == 63
+    assert bench.ops_per_px(fz.HARRIS_CHAIN) == 54
+    assert bench.ops_per_px(fz.GRAD_CHAIN) == 20
+    spec = bench.chain_ops("generic3")
+    assert bench.ops_per_px(spec) == 9 + 1 + 9
+    plan = fz.Plan(spec, 800, 600, 64)  # the three stages fuse into one group
+    assert plan.segments == [2]
