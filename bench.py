@@ -6,10 +6,13 @@ followed by the 8-stage Harris chain (Gaussian 5x5, Sobel, structure products,
 difference), partition chosen by the planner (full fusion).  One step = one
 pass of the whole chain over the whole video, input already resident in HBM.
 
-Prints one JSON line: fused throughput in Mpixel/s (`value`), the unfused
-sequence measured in the same process, the roofline of the dominant kernel
-(timed with HIP events on the stream it is launched on) and the CPU oracle on a
-bounded sample of the same workload.
+Prints one JSON line: fused throughput in Mpixel/s (`value`), the roofline of
+the dominant kernel (its launches timed with HIP events on the stream they run
+on, inside the timed region), and beside them, measured in the same process:
+the unfused sequence, the paper's "Two Fusion" partition, the input handed
+over from host memory, the smaller workloads (192x432 gray, gradient and
+Harris chains) fused and unfused, the 32-clip batch (one persistent graph
+launch against one launch per clip) and the CPU oracle on a bounded sample.
 """
 from __future__ import annotations
 
@@ -42,69 +45,19 @@ WORKLOADS = {
                     desc="32 gray u8 clips, frame sizes drawn from 192x432 / 320x240 / 640x480 / 800x600, "
                          "50-1000 frames, 8-stage Harris chain, one persistent graph launch"),
 }
-BATCH_SIZES = [(192, 432), (320, 240), (640, 480), (800, 600)]
-
-
-def batch_shapes(seed, n):
-    rng = np.random.default_rng(seed)
-    return [(*BATCH_SIZES[int(rng.integers(0, 4))], int(rng.integers(50, 1001))) for _ in range(n)]
-
-
-def run_batch_workload(args, wl):
-    """32 clips: one persistent launch in a replayed graph vs one launch per clip."""
-    import torch
-    from paper_1509_04394_amd import fz, synth
-    dev = torch.device("cuda:0")
-    ops = chain_ops(wl["chain"])
-    shapes = batch_shapes(wl["seed"], wl["clips"])
-    npx = sum(W * H * T for W, H, T in shapes)
-    log(f"generating {len(shapes)} clips, {npx / 1e9:.2f} Gpx")
-    items = []
-    for i, (W, H, T) in enumerate(shapes):
-        x = torch.from_numpy(synth.video(W, H, T, seed=4000 + i)).to(dev)
-        plan = fz.Plan(ops, W, H, T)
-        out, pts, cnt, ws = plan.alloc(dev, point_capacity=1 << 20)
-        items.append((x, out, pts, cnt, ws, plan))
-    stream = torch.cuda.current_stream(dev)
-    bplan = fz.Plan(ops, 800, 600, 1000)
-    clips = [fz.make_clip(x, out, pts, cnt) for (x, out, pts, cnt, _, _) in items]
-    ws = torch.empty((max(fz.fz_batch_workspace_bytes(bplan.handle, clips), 1),), dtype=torch.uint8, device=dev)
-
-    def batch_step():
-        fz.fz_run_batch(bplan.handle, clips, ws.data_ptr(), ws.numel(), stream.cuda_stream)
-
-    def single_step():
-        for (x, out, pts, cnt, w, plan) in items:
-            plan.run(x, out, pts, cnt, w, stream=stream.cuda_stream)
-
-    res = {}
-    for name, fn in [("batch", batch_step), ("per_clip", single_step)]:
-        for _ in range(args.warmup):
-            fn()
-        torch.cuda.synchronize()
-        a = torch.cuda.Event(enable_timing=True)
-        b = torch.cuda.Event(enable_timing=True)
-        a.record(stream)
-        for _ in range(args.steps):
-            fn()
-        b.record(stream)
-        torch.cuda.synchronize()
-        res[name] = a.elapsed_time(b) / args.steps
-        log(f"{name}: {res[name]:.3f} ms per pass over all clips")
-    value = npx / (res["batch"] * 1e-3) / 1e6
-    alg = sum(W * H * T * (1 + 1 + 1.0 / 16) for W, H, T in shapes)
-    rec = {"metric": "Mpixel/s, batched clips (persistent graph launch)", "value": round(value, 1),
-           "unit": "Mpixel/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-           "ms_per_step": round(res["batch"], 4), "higher_is_better": True, "scaling": "weak",
-           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-           "config": {"workload": wl["desc"], "clips": len(shapes), "pixels": npx,
-                      "shapes": [list(s) for s in shapes]},
-           "per_clip_launches": {"ms_per_step": round(res["per_clip"], 4),
-                                 "mpx_s": round(npx / (res["per_clip"] * 1e-3) / 1e6, 1)},
-           "hbm_algorithmic_GBs": round(alg / (res["batch"] * 1e-3) / 1e9, 1)}
-    print(json.dumps(rec), flush=True)
-
 METRIC = "Mpixel/s fused vs unfused and HBM GB/s (% of peak), 800×600×1000 chain"
+
+# Algorithmic VALU operations per output pixel, two counts:
+#  * MIN_OPS: the least work of each stage (separable passes, every
+#    intermediate formed once, 5x5 window sums as running sums);
+#  * KERNEL_OPS: the least work in the summation order every engine of the
+#    library keeps so that all partitions give the same bits -- the u8 -> f32
+#    conversion counted in the Gaussian (+1), and each 5-wide window sum as
+#    ((a+b)+(c+d))+e with the pair sums shared by neighbouring windows (3 + 3
+#    additions per channel instead of a running sum's 2 + 2: +6).
+MIN_OPS = {"rgb2gray": 9, "gauss5": 10, "sobel3": 6, "gradmag": 3, "products": 3, "boxsum5": 12,
+           "harris": 5, "threshold": 2, "nms3": 7, "framediff": 2}
+KERNEL_OPS = dict(MIN_OPS, gauss5=11, boxsum5=18)
 
 # HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE
 # passes, scaled by the plain-copy calibration (profiles/rowfuse_rgb800_counters.md).
@@ -115,6 +68,7 @@ COUNTER_TRAFFIC = {
                                                     "source": "profiles/rowfuse_rgb800_counters.md"},
 }
 KERNEL_SOURCES = ["rowfuse.h", "stage_math.h"]
+DRIVER_TIMEOUT_S = 600
 
 
 def kernel_source_hash():
@@ -135,50 +89,48 @@ def chain_ops(name):
     return {"rgb_harris": fz.RGB_HARRIS_CHAIN, "harris": fz.HARRIS_CHAIN, "grad": fz.GRAD_CHAIN}[name]
 
 
-def ops_per_px(ops):
-    """Algorithmic VALU operations per output pixel: separable passes with every
-    intermediate formed once (Sobel from one vertical smoothing and one vertical
-    difference per pixel; the 5x5 sums from pair sums that neighbouring windows
-    share, horizontally and vertically)."""
-    table = {"rgb2gray": 9, "gauss5": 11, "sobel3": 6, "gradmag": 3, "products": 3, "boxsum5": 18,
-             "harris": 5, "threshold": 2, "nms3": 7, "framediff": 2}
+def ops_per_px(ops, table=None):
+    """Algorithmic VALU operations per output pixel of a chain (KERNEL_OPS by
+    default).  Generic stages: one multiply-add per stencil tap, one addition
+    per window element, one operation per point stage (two for a clamp)."""
+    table = table or KERNEL_OPS
 
-    def generic(st):  # one multiply-add per stencil tap, one add per window element, point ops 1 (clamp 2)
+    def generic(st):
         if st[0] == "point":
             return 2 if st[1] == "clamp" else 1
         return (2 * st[1] + 1) * (2 * st[2] + 1)
     return sum(generic(o) if isinstance(o, tuple) else table[o] for o in ops)
 
 
+def hbm_bytes_per_px(plan, first, last):
+    """Algorithmic bytes per pixel of the group first..last of a plan: its input
+    read once and its output written once (the frame difference's temporal
+    halo re-read is not counted)."""
+    a, b = plan.stages[first], plan.stages[last]
+    size = lambda dt: 4 if dt == 2 else 1
+    return a.in_ch * size(a.in_dtype) + b.out_ch * size(b.out_dtype)
+
+
 def time_plan(plan, x, bufs, steps, warmup, stream):
-    """ms per run: `steps` runs back to back after `warmup`, bracketed by
-    synchronisations and one pair of HIP events on `stream` (total / steps);
-    then the same runs again with an event pair around each, whose median is
-    reported beside it."""
+    """Time `steps` runs back to back after `warmup` untimed runs.  Each run is
+    bracketed by its own pair of HIP events on `stream`; the events of one run
+    follow the previous run's with no synchronisation between them, so the
+    region from the first to the last event is the back-to-back time.
+    Returns (ms per step over the region, mean per-run event time, per-run times)."""
     import torch
     out, pts, cnt, ws = bufs
     for _ in range(warmup):
         plan.run(x, out, pts, cnt, ws, stream=stream.cuda_stream)
     torch.cuda.synchronize()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    ev0.record(stream)
-    for _ in range(steps):
-        plan.run(x, out, pts, cnt, ws, stream=stream.cuda_stream)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    mean = ev0.elapsed_time(ev1) / steps
-    per = []
-    for _ in range(steps):
-        a = torch.cuda.Event(enable_timing=True)
-        b = torch.cuda.Event(enable_timing=True)
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    for a, b in evs:
         a.record(stream)
         plan.run(x, out, pts, cnt, ws, stream=stream.cuda_stream)
         b.record(stream)
-        per.append((a, b))
     torch.cuda.synchronize()
-    times = [a.elapsed_time(b) for a, b in per]
-    return float(mean), float(np.median(times)), times
+    times = [a.elapsed_time(b) for a, b in evs]
+    region = evs[0][0].elapsed_time(evs[-1][1]) / steps
+    return float(region), float(np.mean(times)), times
 
 
 def copy_ceiling_gbs(dev, nbytes=1 << 30, reps=5):
@@ -226,34 +178,148 @@ def pcie_inclusive(plan, x, bufs, stream, reps=3):
     return float(np.median(tot)), float(np.median(cp))
 
 
-def cpu_baseline(wl, ops, budget_s=15.0):
-    """The oracle (FP64, unfused) on a bounded sample of the same workload."""
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(wl, ops, budget_s=15.0, one_thread_s=3.0):
+    """The oracle (FP64, unfused) on a bounded sample of the same workload:
+    all host threads, then one thread on a smaller sample.  The uint8 ->
+    float64 conversion of the input happens before the timed call."""
     import oracle
     from paper_1509_04394_amd import synth
     oracle.build(force=False)
     cores = os.cpu_count() or 1
     W, H = wl["W"], wl["H"]
-    n = 8
     generic = any(isinstance(o, tuple) for o in ops)
-    run = (lambda v, k: oracle.gchain(ops, v, nthreads=k)) if generic else (lambda v, k: oracle.chain(ops, v, nthreads=k))
-    vol = synth.video(W, H, n, seed=wl["seed"], rgb=wl["rgb"])
-    t = time.perf_counter()
-    run(vol, cores)
-    dt = time.perf_counter() - t
-    # grow the sample to about budget_s of work
+
+    def sample(frames):
+        vol = synth.video(W, H, frames, seed=wl["seed"], rgb=wl["rgb"])
+        return np.ascontiguousarray(vol, dtype=np.float64) if generic else oracle.to_planes(ops, vol)
+
+    def run(inp, k):
+        t = time.perf_counter()
+        if generic:
+            oracle.gchain(ops, inp, nthreads=k)
+        else:
+            oracle.chain_planes(ops, inp, nthreads=k)
+        return time.perf_counter() - t
+
+    n = 8
+    dt = run(sample(n), cores)
     frames = int(min(wl["T"], max(n, n * budget_s / max(dt, 1e-3))))
     frames = max(cores, frames - frames % cores) if frames >= cores else frames
-    vol = synth.video(W, H, frames, seed=wl["seed"], rgb=wl["rgb"])
-    t = time.perf_counter()
-    run(vol, min(cores, frames))
-    dt = time.perf_counter() - t
+    inp = sample(frames)
+    dt = run(inp, min(cores, frames))
+    del inp
     px = W * H * frames
-    return {"value": px / dt / 1e6, "unit": "Mpixel/s", "cores": min(cores, frames), "kind": "oracle",
-            "sample": f"frames 0-{frames - 1} of the {W}x{H}x{wl['T']} workload ({px / 1e6:.1f} Mpx), "
-                      f"whole chain unfused in FP64, {dt:.1f} s"}
+    rec = {"value": px / dt / 1e6, "unit": "Mpixel/s", "cores": min(cores, frames), "kind": "oracle",
+           "cpu_model": cpu_model(),
+           "sample": f"frames 0-{frames - 1} of the {W}x{H}x{wl['T']} workload ({px / 1e6:.1f} Mpx), "
+                     f"whole chain unfused in FP64, {dt:.1f} s (input converted to FP64 before timing)"}
+    n1 = max(1, int(frames * one_thread_s / max(dt * min(cores, frames), 1e-3)))
+    n1 = min(n1, frames)
+    inp = sample(n1)
+    dt1 = run(inp, 1)
+    rec["one_thread"] = {"value": W * H * n1 / dt1 / 1e6, "unit": "Mpixel/s", "cores": 1,
+                         "sample": f"frames 0-{n1 - 1} ({W * H * n1 / 1e6:.1f} Mpx), {dt1:.1f} s"}
+    return rec
+
+
+def fused_and_unfused(ops, W, H, T, seed, rgb, steps, warmup, dev, stream):
+    """Mpixel/s of the planner's partition and of one kernel per stage on a
+    smaller workload (whole video resident in HBM)."""
+    import torch
+    from paper_1509_04394_amd import fz, synth
+    x = torch.from_numpy(synth.video(W, H, T, seed=seed, rgb=rgb)).to(dev)
+    res = {}
+    for name, part in (("fused", "optimal"), ("unfused", "unfused")):
+        plan = fz.Plan(ops, W, H, T, partition=part)
+        bufs = plan.alloc(dev)
+        ms, _, _ = time_plan(plan, x, bufs, steps, warmup, stream)
+        res[name] = {"ms_per_step": round(ms, 4), "mpx_s": round(W * H * T / (ms * 1e-3) / 1e6, 1),
+                     "partition": plan.segments}
+        del bufs
+    res["speedup_vs_unfused"] = round(res["unfused"]["ms_per_step"] / res["fused"]["ms_per_step"], 3)
+    del x
+    torch.cuda.empty_cache()
+    return res
+
+
+def batch_leg(wl, steps, warmup, dev, stream):
+    """32 clips: one persistent launch replayed from a graph against one
+    planned run per clip.  Returns the record (Mpixel/s over all clips)."""
+    import torch
+    from paper_1509_04394_amd import fz, synth
+    ops = chain_ops(wl["chain"])
+    shapes = synth.batch_shapes(wl["seed"], wl["clips"])
+    npx = sum(W * H * T for W, H, T in shapes)
+    log(f"generating {len(shapes)} clips, {npx / 1e9:.2f} Gpx")
+    items = []
+    for i, (W, H, T) in enumerate(shapes):
+        x = torch.from_numpy(synth.video(W, H, T, seed=4000 + i)).to(dev)
+        plan = fz.Plan(ops, W, H, T)
+        out, pts, cnt, ws = plan.alloc(dev, point_capacity=1 << 18)
+        items.append((x, out, pts, cnt, ws, plan))
+    bplan = fz.Plan(ops, 800, 600, 1000)
+    clips = [fz.make_clip(x, out, pts, cnt, plan=bplan) for (x, out, pts, cnt, _, _) in items]
+    bws = torch.empty((max(fz.fz_batch_workspace_bytes(bplan.handle, clips), 1),), dtype=torch.uint8, device=dev)
+
+    def batch_step():
+        fz.fz_run_batch(bplan.handle, clips, bws.data_ptr(), bws.numel(), stream.cuda_stream)
+
+    def single_step():
+        for (x, out, pts, cnt, w, plan) in items:
+            plan.run(x, out, pts, cnt, w, stream=stream.cuda_stream)
+
+    res = {}
+    for name, fn in [("batch", batch_step), ("per_clip", single_step)]:
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(steps):
+            fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        res[name] = a.elapsed_time(b) / steps
+        log(f"batch leg {name}: {res[name]:.3f} ms per pass over all clips")
+    alg = sum(W * H * T * 2 for W, H, T in shapes)  # 1 B in + 1 B out per pixel
+    rec = {"workload": wl["desc"], "clips": len(shapes), "pixels": npx,
+           "ms_per_step": round(res["batch"], 4), "mpx_s": round(npx / (res["batch"] * 1e-3) / 1e6, 1),
+           "hbm_algorithmic_GBs": round(alg / (res["batch"] * 1e-3) / 1e9, 1),
+           "per_clip_launches": {"ms_per_step": round(res["per_clip"], 4),
+                                 "mpx_s": round(npx / (res["per_clip"] * 1e-3) / 1e6, 1)},
+           "speedup_vs_per_clip": round(res["per_clip"] / res["batch"], 3)}
+    del items, clips, bws
+    torch.cuda.empty_cache()
+    return rec
+
+
+def run_batch_workload(args, wl):
+    import torch
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    r = batch_leg(wl, args.steps, args.warmup, dev, stream)
+    rec = {"metric": "Mpixel/s, batched clips (persistent graph launch)", "value": r["mpx_s"], "unit": "Mpixel/s",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": r["ms_per_step"],
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": wl["desc"], "clips": r["clips"], "pixels": r["pixels"]},
+           "per_clip_launches": r["per_clip_launches"], "hbm_algorithmic_GBs": r["hbm_algorithmic_GBs"]}
+    print(json.dumps(rec), flush=True)
 
 
 def main():
+    wall0 = time.perf_counter()
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
@@ -267,6 +333,8 @@ def main():
                     help="measure every band / tile configuration of each fused group first (untimed) and "
                          "keep the fastest")
     ap.add_argument("--no-unfused", action="store_true", help="skip timing the unfused sequence")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the other workloads (small configs, batch) in the default run")
     ap.add_argument("--fused-only", action="store_true", help="time only the fused plan (for profiling)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run 5 plain device copies of MIB MiB (scale for memory counters)")
@@ -309,63 +377,77 @@ def main():
     stream = torch.cuda.current_stream(dev)
 
     fused = fz.Plan(ops, W, H, T, engine=args.engine)
-    tuned = None
     if args.autotune:
         from paper_1509_04394_amd import autotune
-        tuned = autotune.autotune(fused, x, reps=3)
-        log("autotuned", tuned)
+        log("autotuned", autotune.autotune(fused, x, reps=3))
     info = fused.segment_info()
     fb = fused.alloc(dev)
     log("fused plan groups", fused.segments, "tiles", [(s.tile_w, s.tile_h, s.frames_per_block) for s in info])
-    f_mean, f_med, _ = time_plan(fused, x, fb, args.steps, args.warmup, stream)
+    f_ms, f_launch, _ = time_plan(fused, x, fb, args.steps, args.warmup, stream)
     nfused = int(fb[2].item()) if fb[2] is not None else 0
-    log(f"fused: {f_mean:.4f} ms/step back to back, {f_med:.4f} median with events around each run, "
+    log(f"fused: {f_ms:.4f} ms/step back to back, {f_launch:.4f} ms mean per run between its events, "
         f"{nfused} points")
-    pcie = None
+    extra = {}
     if not args.fused_only:
         e2e, h2d = pcie_inclusive(fused, x, fb, stream)
-        pcie = {"ms_per_step": round(e2e, 4), "mpx_s": round(npx / (e2e * 1e-3) / 1e6, 1),
-                "h2d_ms": round(h2d, 4), "h2d_GBs": round(x.numel() * x.element_size() / (h2d * 1e-3) / 1e9, 1),
-                "note": "input copied from pinned host memory inside the timed pass; not the headline value"}
+        extra["pcie_inclusive"] = {
+            "ms_per_step": round(e2e, 4), "mpx_s": round(npx / (e2e * 1e-3) / 1e6, 1), "h2d_ms": round(h2d, 4),
+            "h2d_GBs": round(x.numel() * x.element_size() / (h2d * 1e-3) / 1e9, 1),
+            "note": "input copied from pinned host memory inside the timed pass; not the headline value"}
         log(f"with the host-to-device copy: {e2e:.3f} ms/step ({h2d:.3f} ms copy)")
     copy_gbs = None if args.fused_only else copy_ceiling_gbs(dev)
+    del fb
+    torch.cuda.empty_cache()
 
-    unf = None
+    others = {}
     if not (args.no_unfused or args.fused_only):
-        del fb
-        torch.cuda.empty_cache()
-        uplan = fz.Plan(ops, W, H, T, partition="unfused", engine=args.engine)
-        ub = uplan.alloc(dev)
-        u_mean, u_med, _ = time_plan(uplan, x, ub, max(3, args.steps // 2), 1, stream)
-        log(f"unfused: {u_mean:.3f} ms/step mean, {u_med:.3f} median")
-        unf = {"mpx_s": npx / (u_mean * 1e-3) / 1e6, "ms_per_step": u_mean,
-               "algorithmic_GBs": uplan.cost / (u_mean * 1e-3) / 1e9,
-               "hbm_frac": uplan.cost / (u_mean * 1e-3) / 1e9 / HBM_PEAK_GBS,
-               "kernels": len(uplan.segments)}
-        del ub
-        torch.cuda.empty_cache()
+        for name, part in (("unfused", "unfused"), ("two_fusion", [1])):
+            if name == "two_fusion" and ops != fz.RGB_HARRIS_CHAIN:
+                continue
+            p = fz.Plan(ops, W, H, T, partition=part, engine=args.engine)
+            b = p.alloc(dev)
+            ms, _, _ = time_plan(p, x, b, max(3, args.steps // 2), 2, stream)
+            log(f"{name}: {ms:.3f} ms/step, partition {p.segments}")
+            others[name] = {"mpx_s": round(npx / (ms * 1e-3) / 1e6, 1), "ms_per_step": round(ms, 4),
+                            "partition": p.segments, "kernels": len(p.segments),
+                            "algorithmic_GBs": round(p.cost / (ms * 1e-3) / 1e9, 1),
+                            "hbm_frac": round(p.cost / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+            if copy_gbs:
+                others[name]["hbm_frac_of_copy"] = round(p.cost / (ms * 1e-3) / 1e9 / copy_gbs, 4)
+            del b
+            torch.cuda.empty_cache()
+        if "two_fusion" in others:
+            others["two_fusion"]["note"] = ("the paper's Two Fusion (Sec. VII): the best partition whose "
+                                            "groups have halos of at most 4 px, a cut after the Gaussian")
+    del x
+    torch.cuda.empty_cache()
 
-    value = npx / (f_mean * 1e-3) / 1e6
-    alg_bytes = fused.cost  # compulsory bytes of the planned groups
+    # roofline of the dominant kernel: the algorithmic work of one launch over
+    # its mean duration between the HIP events around each run in the timed region
     dominant = info[0] if len(info) == 1 else max(info, key=lambda s: s.cost)
-    opx = ops_per_px(ops[dominant.first:dominant.last + 1])
-    achieved_gops = npx * opx / (f_mean * 1e-3) / 1e9
-    achieved_gbs = alg_bytes / (f_mean * 1e-3) / 1e9
+    sub = ops[dominant.first:dominant.last + 1]
+    opx_min = ops_per_px(sub, MIN_OPS)
+    opx_kernel = ops_per_px(sub, KERNEL_OPS)
+    gops = npx * opx_min / (f_launch * 1e-3) / 1e9
+    bpx = hbm_bytes_per_px(fused, dominant.first, dominant.last)
+    gbs = npx * bpx / (f_launch * 1e-3) / 1e9
     traffic = None
     ct = COUNTER_TRAFFIC.get((args.workload, kernel_source_hash(),
                               (dominant.tile_w, dominant.tile_h, dominant.frames_per_block)))
     if ct is not None and dominant.engine == fz.FZ_ENGINE_ROW:
-        # measured HBM bytes per launch over this run's launch time, GB/s
-        traffic = round((ct["fetch_bytes"] + ct["write_bytes"]) / (f_mean * 1e-3) / 1e9, 1)
-    roof = {"bound": "alu", "achieved": round(achieved_gops, 1), "peak": VALU_PEAK_GOPS, "unit": "Gop/s",
-            "frac": round(achieved_gops / VALU_PEAK_GOPS, 4), "traffic": traffic,
+        traffic = round((ct["fetch_bytes"] + ct["write_bytes"]) / (f_launch * 1e-3) / 1e9, 1)
+    roof = {"bound": "alu", "achieved": round(gops, 1), "peak": VALU_PEAK_GOPS, "unit": "Gop/s",
+            "frac": round(gops / VALU_PEAK_GOPS, 4), "traffic": traffic,
             "traffic_unit": "GB/s (counter bytes per launch / launch time)",
-            "ops_per_px": opx, "hbm_achieved_GBs": round(achieved_gbs, 1),
-            "hbm_frac": round(achieved_gbs / HBM_PEAK_GBS, 4)}
-    rec = {"metric": METRIC, "value": round(value, 1), "unit": "Mpixel/s", "n_gpus": 1, "steps": args.steps,
-           "warmup": args.warmup, "ms_per_step": round(f_mean, 4), "ms_per_step_events_each": round(f_med, 4),
-           "higher_is_better": True, "scaling": "weak",
-           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "ops_per_px": opx_min, "ops_per_px_kernel_order": opx_kernel,
+            "frac_kernel_order": round(npx * opx_kernel / (f_launch * 1e-3) / 1e9 / VALU_PEAK_GOPS, 4),
+            "launch_ms": round(f_launch, 4), "hbm_bytes_per_px": bpx, "hbm_achieved_GBs": round(gbs, 1),
+            "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
+    if copy_gbs:
+        roof["hbm_frac_of_copy"] = round(gbs / copy_gbs, 4)
+    rec = {"metric": METRIC, "value": round(npx / (f_ms * 1e-3) / 1e6, 1), "unit": "Mpixel/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(f_ms, 4),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
            "config": {"workload": wl["desc"], "partition": fused.segments,
                       "tile": [dominant.tile_w, dominant.tile_h, dominant.frames_per_block],
                       "engine": {fz.FZ_ENGINE_ROW: "row", fz.FZ_ENGINE_TILE: "tile",
@@ -374,20 +456,30 @@ def main():
                       "points_per_step": nfused},
            "roofline": roof}
     if copy_gbs is not None:
-        # the same bytes against a plain device copy measured in this run
         rec["copy_ceiling_GBs"] = round(copy_gbs, 1)
-        roof["hbm_frac_of_copy"] = round(achieved_gbs / copy_gbs, 4)
-        if unf is not None:
-            unf["hbm_frac_of_copy"] = unf["algorithmic_GBs"] / copy_gbs
-    if pcie is not None:
-        rec["pcie_inclusive"] = pcie
-    if unf is not None:
-        rec["unfused"] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in unf.items()}
-        rec["speedup_vs_unfused"] = round(u_mean / f_mean, 3)
+    rec.update(extra)
+    if "unfused" in others:
+        rec["unfused"] = others["unfused"]
+        rec["speedup_vs_unfused"] = round(others["unfused"]["ms_per_step"] / f_ms, 3)
         rec["paper_context"] = "2-3x fused over sequential kernels on Tesla C1060 / K20 / GTX 750 Ti (Abstract)"
+    if "two_fusion" in others:
+        rec["two_fusion"] = others["two_fusion"]
+    if args.workload == "rgb800" and not (args.no_extra or args.fused_only):
+        small = {}
+        for key in ("grad192", "harris192"):
+            w = WORKLOADS[key]
+            log(f"workload {key}")
+            small[key] = dict(workload=w["desc"], **fused_and_unfused(
+                chain_ops(w["chain"]), w["W"], w["H"], w["T"], w["seed"], w["rgb"], args.steps, args.warmup,
+                dev, stream))
+        rec["other_workloads"] = small
+        rec["batched"] = batch_leg(WORKLOADS["batch32"], max(3, args.steps // 4), 2, dev, stream)
     if not (args.no_cpu or args.fused_only):
         log("timing the CPU oracle on a sample")
         rec["cpu_baseline"] = cpu_baseline(wl, ops)
+    wall = time.perf_counter() - wall0
+    rec["bench_wall_s"] = round(wall, 1)
+    rec["fits_in_driver_run"] = wall < 0.8 * DRIVER_TIMEOUT_S
     print(json.dumps(rec), flush=True)
 
 

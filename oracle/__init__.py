@@ -79,6 +79,18 @@ def chain_channels(ops, in_ch=None):
     return first, ch
 
 
+def to_planes(ops, volume):
+    """The chain's input as contiguous float64 planes [C][T][H][W] (the
+    oracle's own layout): [T][H][W] one channel, [T][H][W][3] RGB interleaved
+    for a chain starting with rgb2gray, or [C][T][H][W] planar."""
+    v = np.asarray(volume)
+    if ops[0] == "rgb2gray":
+        return np.ascontiguousarray(np.moveaxis(v, -1, 0), dtype=np.float64)
+    if v.ndim == 3:
+        return np.ascontiguousarray(v[None], dtype=np.float64)
+    return np.ascontiguousarray(v, dtype=np.float64)
+
+
 def chain(ops, volume, in_ch=None, sigma=SIGMA, k=HARRIS_K, thr=THRESHOLD,
           nthreads=None, max_points=1 << 18):
     """Run the chain ``ops`` (list of names) over ``volume``.
@@ -89,13 +101,14 @@ def chain(ops, volume, in_ch=None, sigma=SIGMA, k=HARRIS_K, thr=THRESHOLD,
     (t, y, x, response)).
     """
     ops = list(ops)
-    v = np.asarray(volume)
-    if ops[0] == "rgb2gray":
-        planes = np.ascontiguousarray(np.moveaxis(v, -1, 0), dtype=np.float64)
-    elif v.ndim == 3:
-        planes = np.ascontiguousarray(v[None], dtype=np.float64)
-    else:
-        planes = np.ascontiguousarray(v, dtype=np.float64)
+    return chain_planes(ops, to_planes(ops, volume), sigma, k, thr, nthreads, max_points)
+
+
+def chain_planes(ops, planes, sigma=SIGMA, k=HARRIS_K, thr=THRESHOLD, nthreads=None, max_points=1 << 18):
+    """``chain`` on input already in the oracle's layout (``to_planes``)."""
+    ops = list(ops)
+    if planes.dtype != np.float64 or not planes.flags.c_contiguous or planes.ndim != 4:
+        raise ValueError("planes must be contiguous float64 [C][T][H][W]")
     cin, cout = chain_channels(ops, planes.shape[0])
     if planes.shape[0] != cin:
         raise ValueError(f"chain {ops} wants {cin} input channels, got {planes.shape[0]}")

@@ -27,6 +27,7 @@ struct Segment {
     int row_gen;            // 1: generic row kernel, 0: the Harris-chain kernel
     double bytes_per_px;
     double cost;
+    int refused;            // a requested band / frame run this group's kernel cannot run (cost is +inf)
 };
 
 struct Params {

@@ -89,6 +89,10 @@ Segment price_group(const fz_plan& p, int a, int b, int req_w, int req_h, int re
         s.nstrips = row_strips(p.W, s.row_k, row_generic ? s.halo : ROW_HX);
         const int slots = row_generic ? ROW_SLOTS_GENERIC : row_slots(s.row_k, rgb_in);
         const RowShape rs = row_shape(p.H, p.T, s.nstrips, diff, req_h, req_tpb, slots);
+        if (rs.band_h == 0) {
+            s.refused = 1;
+            return s;
+        }
         s.tpb = rs.tt;
         s.nchunks = (p.T + s.tpb - 1) / s.tpb;
         s.tile_h = rs.band_h;
@@ -438,6 +442,20 @@ fz_status fz_plan_chain(const fz_stage* stages, int32_t n, const fz_plan_opts* o
         sum = w[0] + 2.0 * w[1] + 2.0 * w[2];
         for (int i = 0; i < 3; ++i) p->prm.gw[i] = (float)(w[i] / sum);
     }
+    // a requested band or frame run that some row group cannot run is refused,
+    // not replaced by another shape
+    for (int a = 0; a < n; ++a)
+        for (int b = a; b < n; ++b) {
+            const Segment s = price_group(*p, a, b, opts->tile_w, opts->tile_h, opts->frames_per_block, opts->engine);
+            if (s.refused) {
+                delete p;
+                return fail(FZ_E_UNSUPPORTED, "requested band of " + std::to_string(opts->tile_h) +
+                                                  " rows: the row kernel of group " + std::to_string(a) + ".." +
+                                                  std::to_string(b) + " keeps at most " +
+                                                  std::to_string(ROW_DIFF_MAX_BAND) +
+                                                  " rows per band when it ends in the frame difference");
+            }
+        }
     // a stage that cannot run even alone makes the chain infeasible
     for (int i = 0; i < n; ++i) {
         Segment s = price_group(*p, i, i, opts->tile_w, opts->tile_h, opts->frames_per_block, opts->engine);
@@ -559,6 +577,10 @@ fz_status fz_plan_set_segment_config(fz_plan* plan, int32_t i, int32_t engine, i
     const Segment& old = plan->segs[i];
     Segment s = price_group(*plan, old.first, old.last, engine == FZ_ENGINE_TILE ? tile_w : 0, tile_h,
                             frames_per_block, engine);
+    if (s.refused)
+        return fail(FZ_E_UNSUPPORTED, "fz_plan_set_segment_config: a band of " + std::to_string(tile_h) +
+                                          " rows is over the " + std::to_string(ROW_DIFF_MAX_BAND) +
+                                          " the row kernel keeps when the group ends in the frame difference");
     if (!(s.cost < kInf)) return fail(FZ_E_LDS, "fz_plan_set_segment_config: configuration does not fit the budget");
     if (engine == FZ_ENGINE_ROW && s.engine != FZ_ENGINE_ROW)
         return fail(FZ_E_UNSUPPORTED, "fz_plan_set_segment_config: the row engine does not apply to this group");

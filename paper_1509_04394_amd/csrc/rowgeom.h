@@ -47,29 +47,41 @@ inline int row_strips_best(int W, bool rgb)
 
 inline int row_lds_bytes(int band_h) { return ROW_WAVES * band_h * 64; }
 
+// A frame-difference group keeps one byte of previous-frame mask bits per lane
+// and row in LDS: at most 256 rows per band keep that within 64 KB per
+// workgroup of ROW_WAVES wavefronts.
+constexpr int ROW_DIFF_MAX_BAND = 256;
+
 // Rows per band and frames per work item.  A work item marches band_h + 2*HX
 // rows per frame over tt frames (plus the frame before them when the group
 // ends in the frame difference); items run in rounds of `slots` wavefronts,
 // fewer when the frame difference's LDS rows (one workgroup of ROW_WAVES
 // wavefronts per SIMD slot) do not fit 160 KB per CU that many times.  Pick
-// the pair with the least (rounds x item length); explicit requests (> 0)
-// are kept.
+// the pair with the least (rounds x item length).  Explicit requests (> 0)
+// are kept as given, except that a frame run longer than the video is the
+// whole video and a band taller than the frame the whole frame; a request the
+// kernel cannot run (a band over ROW_DIFF_MAX_BAND rows on a frame-difference
+// group) gives band_h = 0 and is refused by the caller, never replaced.
 struct RowShape {
     int band_h, tt;
 };
 inline RowShape row_shape(int H, int T, int nstrips, bool diff, int req_h, int req_tt, int slots)
 {
-    RowShape best{H, 1};
+    if (req_h > 0 && diff && std::min(req_h, H) > ROW_DIFF_MAX_BAND) return RowShape{0, 0};
+    RowShape best{0, 0};
     double best_cost = -1.0;
     const int tts[] = {1, 2, 4, 8, 16, 32, 64};
     for (int tt : tts) {
-        if (req_tt > 0 && tt != 1) break;
-        const int t = req_tt > 0 ? req_tt : tt;
-        if (!diff && t != 1 && req_tt <= 0) continue;
-        if (t > T && t != 1) continue;
+        int t = tt;
+        if (req_tt > 0) {
+            if (tt != 1) break;
+            t = std::min(req_tt, T);
+        } else if ((!diff && t != 1) || (t > T && t != 1)) {
+            continue;
+        }
         for (int nb = 1; nb <= H; ++nb) {
-            int bh = req_h > 0 ? req_h : (H + nb - 1) / nb;
-            if (diff && bh > 256) continue;
+            const int bh = req_h > 0 ? std::min(req_h, H) : (H + nb - 1) / nb;
+            if (diff && bh > ROW_DIFF_MAX_BAND) continue;
             if (bh < 16 && req_h <= 0 && nb > 1) break;
             const long long items = (long long)nstrips * ((H + bh - 1) / bh) * ((T + t - 1) / t);
             long long fit = slots;
@@ -83,7 +95,6 @@ inline RowShape row_shape(int H, int T, int nstrips, bool diff, int req_h, int r
             if (req_h > 0) break;
         }
     }
-    if (best.band_h > H) best.band_h = H;
     return best;
 }
 

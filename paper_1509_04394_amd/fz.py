@@ -462,14 +462,17 @@ class Plan:
         ws = torch.empty((max(self.workspace_bytes, 1),), dtype=torch.uint8, device=device)
         return out, pts, cnt, ws
 
-    def run(self, x, out=None, points=None, count=None, workspace=None, stream=None):
-        """Run on device tensors (asynchronous on the current torch stream)."""
+    def input_dtype(self):
         import torch
-        if tuple(x.shape) != self.input_shape():
-            raise ValueError(f"input shape {tuple(x.shape)} != {self.input_shape()}")
-        want = torch.uint8 if self.stages[0].in_dtype == FZ_U8 else torch.float32
-        if x.dtype != want or not x.is_contiguous() or not x.is_cuda:
-            raise ValueError("input must be a contiguous CUDA tensor of the first stage's type")
+        return torch.uint8 if self.stages[0].in_dtype == FZ_U8 else torch.float32
+
+    def run(self, x, out=None, points=None, count=None, workspace=None, stream=None):
+        """Run on device tensors (asynchronous on the current torch stream).
+        Every buffer is checked for shape, type, device and contiguity before
+        the C call: a wrong buffer would otherwise be read or written out of
+        bounds on the device."""
+        import torch
+        check_tensor(x, self.input_shape(), self.input_dtype(), "input")
         if out is None:
             out, p2, c2, ws2 = self.alloc(x.device)
             points = points if points is not None else p2
@@ -477,6 +480,11 @@ class Plan:
             workspace = workspace if workspace is not None else ws2
         if workspace is None:
             workspace = torch.empty((max(self.workspace_bytes, 1),), dtype=torch.uint8, device=x.device)
+        check_tensor(out, self.output_shape(), self.output_dtype(), "output", x.device)
+        check_points(points, count, x.device)
+        check_tensor(workspace, None, torch.uint8, "workspace", x.device)
+        if workspace.numel() < self.workspace_bytes:
+            raise ValueError(f"workspace has {workspace.numel()} bytes, the plan needs {self.workspace_bytes}")
         if stream is None:
             stream = torch.cuda.current_stream(x.device).cuda_stream
         cap = points.shape[0] if points is not None else 0
@@ -487,14 +495,71 @@ class Plan:
         return out, points, count
 
 
-def make_clip(x, out, points=None, count=None, width=None, height=None, frames=None):
+def check_tensor(t, shape, dtype, what, device=None):
+    """A contiguous CUDA tensor of the given dtype (and shape, and device)."""
+    if t is None or not hasattr(t, "is_cuda") or not t.is_cuda:
+        raise ValueError(f"{what} must be a CUDA tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{what} must be contiguous")
+    if t.dtype != dtype:
+        raise ValueError(f"{what} must be {dtype}, got {t.dtype}")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{what} shape {tuple(t.shape)} != {tuple(shape)}")
+    if device is not None and t.device != device:
+        raise ValueError(f"{what} is on {t.device}, the input on {device}")
+
+
+def check_points(points, count, device=None):
+    """Feature-point buffer: (capacity, 4) int32 records {t, y, x, response};
+    count: at least one int32 (the library writes one uint32)."""
+    import torch
+    if points is not None:
+        check_tensor(points, None, torch.int32, "points", device)
+        if points.dim() != 2 or points.shape[1] != 4:
+            raise ValueError(f"points must be (capacity, 4) int32, got shape {tuple(points.shape)}")
+    if count is not None:
+        check_tensor(count, None, torch.int32, "count", device)
+        if count.numel() < 1:
+            raise ValueError("count must hold at least one int32")
+    if points is not None and count is None:
+        raise ValueError("a point buffer needs a count")
+
+
+def clip_shapes(ops_plan, W, H, T):
+    """(input shape, output shape) of a clip of W x H x T for a plan's chain."""
+    s0, s1 = ops_plan.stages[0], ops_plan.stages[-1]
+    if s0.op == OPS["rgb2gray"]:
+        ins = (T, H, W, 3)
+    elif s0.in_dtype == FZ_U8:
+        ins = (T, H, W)
+    else:
+        ins = (s0.in_ch, T, H, W)
+    outs = (T, H, W) if s1.out_dtype == FZ_U8 else (s1.out_ch, T, H, W)
+    return ins, outs
+
+
+def make_clip(x, out, points=None, count=None, width=None, height=None, frames=None, plan=None):
     """fz_clip for device tensors x (input) and out (output); sizes from out's shape
-    unless given."""
+    unless given.  With `plan`, x and out are checked against the clip shapes of
+    the plan's chain; either way both must hold the clip's W*H*T pixels."""
+    import torch
     c = fz_clip()
-    c.d_in = x.data_ptr()
-    c.d_out = out.data_ptr()
     shp = out.shape[-3:]
     c.frames, c.height, c.width = (int(frames or shp[0]), int(height or shp[1]), int(width or shp[2]))
+    if plan is not None:
+        ins, outs = clip_shapes(plan, c.width, c.height, c.frames)
+        check_tensor(x, ins, plan.input_dtype(), "clip input")
+        check_tensor(out, outs, plan.output_dtype(), "clip output", x.device)
+    else:
+        npx = c.width * c.height * c.frames
+        for t, what in ((x, "clip input"), (out, "clip output")):
+            if not t.is_cuda or not t.is_contiguous():
+                raise ValueError(f"{what} must be a contiguous CUDA tensor")
+            if t.dtype not in (torch.uint8, torch.float32) or t.numel() % npx != 0 or t.numel() == 0:
+                raise ValueError(f"{what} ({tuple(t.shape)}, {t.dtype}) does not hold {npx} pixels")
+    check_points(points, count, x.device)
+    c.d_in = x.data_ptr()
+    c.d_out = out.data_ptr()
     c.d_points = points.data_ptr() if points is not None else None
     c.d_point_count = count.data_ptr() if count is not None else None
     c.point_capacity = int(points.shape[0]) if points is not None else 0

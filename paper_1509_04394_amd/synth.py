@@ -209,3 +209,14 @@ def random_chain(seed: int, length: int | None = None, max_r: int = 3):
             r = int(rng.integers(1, max_r + 1))
             out.append(("box", r, r))
     return out
+
+
+BATCH_SIZES = [(192, 432), (320, 240), (640, 480), (800, 600)]
+
+
+def batch_shapes(seed: int, n: int, t_lo: int = 50, t_hi: int = 1000):
+    """(W, H, T) of n clips of a batch: frame size uniform over BATCH_SIZES,
+    frame count uniform in [t_lo, t_hi]; clip i's video uses seed 4000 + i."""
+    rng = np.random.default_rng(seed)
+    return [(*BATCH_SIZES[int(rng.integers(0, len(BATCH_SIZES)))], int(rng.integers(t_lo, t_hi + 1)))
+            for _ in range(n)]

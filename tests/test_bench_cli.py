@@ -23,8 +23,9 @@ def test_help_lists_the_contract_flags():
 
 
 def test_algorithmic_op_counts():
-    """The VALU roof's numerator: 63 ops per pixel for the RGB chain (separable
-    passes, intermediates formed once, shared pair sums in the window sums),
+    """The VALU roof's numerator: 56 ops per pixel for the RGB chain at the
+    least work per stage, 63 in the summation order the kernels keep (shared
+    pair sums in the window sums, the u8 conversion in the Gaussian),
     and the generic workload's per-stage counts (taps, window elements, one per
     point op)."""
     sys.path.insert(0, ROOT)
@@ -33,6 +34,9 @@ def test_algorithmic_op_counts():
     assert bench.ops_per_px(fz.RGB_HARRIS_CHAIN) == 63
     assert bench.ops_per_px(fz.HARRIS_CHAIN) == 54
     assert bench.ops_per_px(fz.GRAD_CHAIN) == 20
+    # the least work per stage (running window sums, no separate conversion)
+    assert bench.ops_per_px(fz.RGB_HARRIS_CHAIN, bench.MIN_OPS) == 56
+    assert bench.ops_per_px(fz.HARRIS_CHAIN, bench.MIN_OPS) == 47
     spec = bench.chain_ops("generic3")
     assert bench.ops_per_px(spec) == 9 + 1 + 9
     plan = fz.Plan(spec, 800, 600, 64)  # the three stages fuse into one group

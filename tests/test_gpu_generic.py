@@ -66,7 +66,9 @@ def test_random_chain_within_fp32_bound(dev, oracle_lib, seed):
         pytest.skip("chain leaves the FP32 range on this input")
     out, plan = run_gpu(spec, vol, dev)
     ratio = parity.assert_within_bound(out, ref, bound, f"seed {seed} {plan.segments}")
-    say("segments", plan.segments, "worst err/bound", ratio)
+    err = float(np.abs(out.astype(np.float64) - ref).max())
+    say("segments", plan.segments, "worst err/bound", ratio,
+        "err over the 1e-4-on-0..255 tolerance", err / parity.north_star_tol(spec))
     un, _ = run_gpu(spec, vol, dev, partition="unfused")
     assert np.array_equal(un.view(np.uint32), out.view(np.uint32))
 
@@ -77,7 +79,28 @@ def test_well_conditioned_chain_is_tight(dev, oracle_lib):
     assert (bound <= 1e-5 * np.abs(ref).max()).all()  # the bound itself is small here
     out, plan = run_gpu(WELL, vol, dev)
     parity.assert_within_bound(out, ref, bound, "well-conditioned")
-    say("well-conditioned: max abs err", float(np.abs(out - ref).max()), "segments", plan.segments)
+    err = float(np.abs(out - ref).max())
+    tol = parity.north_star_tol(WELL)
+    say("well-conditioned: max abs err", err, "= %.3g of the 1e-4-on-0..255 tolerance" % (err / tol),
+        "segments", plan.segments)
+    assert err <= tol, (err, tol)
+
+
+def test_generic_workload_full_size_within_tolerance(dev, oracle_lib):
+    """The benchmark's generic chain (3x3 binomial stencil -> |x| -> 3x3
+    window sum, one fused tile kernel) over the whole 800x600x64 video, against
+    the oracle, within 1e-4 on a 0..255 scale and within the FP32 bound."""
+    spec = [("stencil", 1, 1, (np.outer([1, 2, 1], [1, 2, 1]) / 16.0).astype(np.float32)),
+            ("point", "abs", 0.0, 0.0), ("box", 1, 1)]
+    vol = synth.video(800, 600, 64, seed=6)
+    ref, bound = parity.generic_reference(oracle_lib, spec, vol)
+    out, plan = run_gpu(spec, vol, dev)
+    assert plan.segments == [2]
+    parity.assert_within_bound(out, ref, bound, "generic 800x600x64")
+    err = float(np.abs(out - ref).max())
+    tol = parity.north_star_tol(spec)
+    say("generic 800x600x64: max abs err", err, "tolerance", tol, "ratio", err / tol)
+    assert err <= tol, (err, tol)
 
 
 @pytest.mark.parametrize("size", [(70, 45, 2), (131, 40, 1)])

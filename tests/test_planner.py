@@ -237,3 +237,37 @@ def test_measure_workspace_and_errors_before_any_launch():
     p2 = fz.fz_plan_chain(plan.stages, fz.make_opts(800, 600, 10, cost_model="measured"))
     assert fz.fz_plan_cost(p2) == plan.cost
     fz.fz_plan_destroy(p2)
+
+
+def test_band_and_frame_run_requests_are_kept_or_refused():
+    """A requested band height or frame run is either kept as given or refused
+    with FZ_E_UNSUPPORTED, never replaced by another shape."""
+    W, H, T = 800, 600, 1000
+    # a band of 300 rows on a group ending in the frame difference is over what
+    # the kernel's previous-frame LDS rows allow: refused, through fz_plan_chain
+    with pytest.raises(fz.FzError) as e:
+        fz.Plan(fz.RGB_HARRIS_CHAIN, W, H, T, engine="row", band_h=300, frames_per_block=8)
+    assert e.value.code == fz.FZ_E_UNSUPPORTED and "256" in str(e.value)
+    # kept: band and frame run exactly as requested
+    for band, run in [(256, 8), (55, 16), (8, 1), (100, 3)]:
+        s = fz.Plan(fz.RGB_HARRIS_CHAIN, W, H, T, engine="row", band_h=band, frames_per_block=run).segment_info()
+        assert len(s) == 1 and s[0].engine == fz.FZ_ENGINE_ROW
+        assert (s[0].tile_h, s[0].frames_per_block) == (band, run)
+        assert s[0].lds_bytes == 4 * 64 * band <= 65536
+    # a frame run longer than the video is the whole video; a band taller
+    # than the frame is the whole frame
+    s = fz.Plan(fz.HARRIS_CHAIN, 192, 200, 5, engine="row", band_h=250, frames_per_block=24).segment_info()[0]
+    assert (s.tile_h, s.frames_per_block) == (200, 5)
+    # groups without the frame difference take tall bands
+    s = fz.Plan(fz.RGB_HARRIS_CHAIN[:8], W, H, T, engine="row", band_h=300).segment_info()[0]
+    assert s.engine == fz.FZ_ENGINE_ROW and s.tile_h == 300 and s.lds_bytes == 0
+    # through fz_plan_set_segment_config: refused, and the plan is unchanged
+    plan = fz.Plan(fz.RGB_HARRIS_CHAIN, W, H, T)
+    before = (plan.segment_info()[0].tile_h, plan.segment_info()[0].frames_per_block, plan.cost)
+    with pytest.raises(fz.FzError) as e:
+        plan.set_segment_config(0, "row", (0, 300), 8)
+    assert e.value.code == fz.FZ_E_UNSUPPORTED
+    assert (plan.segment_info()[0].tile_h, plan.segment_info()[0].frames_per_block, plan.cost) == before
+    plan.set_segment_config(0, "row", (0, 120), 40)
+    s = plan.segment_info()[0]
+    assert (s.tile_h, s.frames_per_block) == (120, 40)
