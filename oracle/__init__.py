@@ -62,6 +62,9 @@ def _load():
         lib.or_gchain.restype = ctypes.c_int
         lib.or_gchain.argtypes = [i32, i32, i32, i32, d, d, d, ctypes.c_int32, d, ctypes.c_int32, ctypes.c_int32,
                                   ctypes.c_int32, d, ctypes.c_int32]
+        lib.or_gchain_seq.restype = ctypes.c_int
+        lib.or_gchain_seq.argtypes = [i32, i32, i32, i32, i32, d, d, d, ctypes.c_int32, d, ctypes.c_int32,
+                                      ctypes.c_int32, ctypes.c_int32, d]
         _lib = lib
     return _lib
 
@@ -130,8 +133,12 @@ def chain_planes(ops, planes, sigma=SIGMA, k=HARRIS_K, thr=THRESHOLD, nthreads=N
     return out, pts[:n].copy()
 
 
-GKINDS = {"point": 0, "stencil": 1, "box": 2}
+GKINDS = {"point": 0, "stencil": 1, "box": 2, "iir": 3}
 POINT_KINDS = {"affine": 0, "abs": 1, "square": 2, "sqrtabs": 3, "clamp": 4}
+
+
+def _temporal(stages):
+    return any(st[0] == "iir" or (st[0] == "stencil" and np.asarray(st[3]).ndim == 3) for st in stages)
 
 
 def gchain(stages, volume, nthreads=None):
@@ -141,10 +148,16 @@ def gchain(stages, volume, nthreads=None):
       ("point", kind, a, b)       kind in POINT_KINDS; affine is a*v + b,
                                   clamp is min(max(v, a), b)
       ("stencil", rx, ry, w)      w has shape (2ry+1, 2rx+1): correlation
-                                  weights, w[v+ry][u+rx] multiplies in(x+u, y+v)
+                                  weights, w[v+ry][u+rx] multiplies in(x+u, y+v);
+                                  or shape (rt+1, 2ry+1, 2rx+1): a spatio-temporal
+                                  stencil, w[tau] multiplies frame t - tau
+                                  (frames before the first are the first)
       ("box", rx, ry)             unweighted (2rx+1) x (2ry+1) window sum
+      ("iir", a)                  y[t] = a x[t] + (1 - a) y[t-1], y[-1] = x[0]
     Window stages clamp their reads to the frame (replicate borders).  Returns
-    out [T][H][W] float64.
+    out [T][H][W] float64.  Chains with a frame window or an IIR stage run
+    stage by stage over the whole volume (or_gchain_seq); the others frame by
+    frame (or_gchain).
     """
     v = np.ascontiguousarray(np.asarray(volume), dtype=np.float64)
     if v.ndim != 3:
@@ -154,6 +167,7 @@ def gchain(stages, volume, nthreads=None):
     kind = (ctypes.c_int32 * n)()
     rx = (ctypes.c_int32 * n)()
     ry = (ctypes.c_int32 * n)()
+    rt = (ctypes.c_int32 * n)()
     pk = (ctypes.c_int32 * n)()
     pa = np.zeros(n, np.float64)
     pb = np.zeros(n, np.float64)
@@ -164,19 +178,28 @@ def gchain(stages, volume, nthreads=None):
             pk[i] = POINT_KINDS[st[1]]
             pa[i] = st[2] if len(st) > 2 else 0.0
             pb[i] = st[3] if len(st) > 3 else 0.0
+        elif st[0] == "iir":
+            pa[i] = float(st[1])
         else:
             rx[i], ry[i] = int(st[1]), int(st[2])
             if st[0] == "stencil":
                 w = np.asarray(st[3], np.float64)
-                if w.shape != (2 * ry[i] + 1, 2 * rx[i] + 1):
-                    raise ValueError(f"stage {i}: weights must have shape {(2 * ry[i] + 1, 2 * rx[i] + 1)}")
+                if w.ndim == 2:
+                    w = w[None]
+                rt[i] = w.shape[0] - 1
+                if w.shape[1:] != (2 * ry[i] + 1, 2 * rx[i] + 1):
+                    raise ValueError(f"stage {i}: weights must have shape {(2 * ry[i] + 1, 2 * rx[i] + 1)} "
+                                     f"per frame")
                 ws.append(w.ravel())
     wcat = np.ascontiguousarray(np.concatenate(ws) if ws else np.zeros(1), dtype=np.float64)
     out = np.zeros_like(v)
-    if nthreads is None:
-        nthreads = min(os.cpu_count() or 1, T)
-    rc = _load().or_gchain(kind, rx, ry, pk, _dp(pa), _dp(pb), _dp(wcat), n, _dp(v), W, H, T, _dp(out),
-                           int(nthreads))
+    if _temporal(stages):
+        rc = _load().or_gchain_seq(kind, rx, ry, rt, pk, _dp(pa), _dp(pb), _dp(wcat), n, _dp(v), W, H, T, _dp(out))
+    else:
+        if nthreads is None:
+            nthreads = min(os.cpu_count() or 1, T)
+        rc = _load().or_gchain(kind, rx, ry, pk, _dp(pa), _dp(pb), _dp(wcat), n, _dp(v), W, H, T, _dp(out),
+                               int(nthreads))
     if rc != 0:
         raise RuntimeError(f"oracle generic chain failed with code {rc}")
     return out

@@ -27,9 +27,14 @@
  * square, square root of the absolute value, clamp), a weighted
  * (2rx+1) x (2ry+1) stencil and an unweighted (2rx+1) x (2ry+1) window sum.
  *
+ * Temporal generic stages (or_gchain_seq): an IIR filter (Table II, a
+ * multi-frame point operation) and a stencil with a frame window (Table I,
+ * spatio-temporal operation).
+ *
  * Parity status of each function: pinned by tests/test_oracle.py and, for the
- * generic stages, tests/test_generic_oracle.py (closed forms, invariants,
- * library routines, brute force); see the module docstrings there.
+ * generic stages, tests/test_generic_oracle.py and tests/test_temporal_oracle.py
+ * (closed forms, invariants, library routines, brute force); see the module
+ * docstrings there.
  */
 #include <math.h>
 #include <pthread.h>
@@ -445,5 +450,81 @@ int or_gchain(const int32_t* kind, const int32_t* rx, const int32_t* ry, const i
         if (jobs[i].status) status = jobs[i].status;
     }
     free(jobs); free(th);
+    return status;
+}
+
+/* ------------------------------------------------------------------ temporal generic chains */
+
+/*
+ * Generic chains whose stages may look at earlier frames: besides the point,
+ * stencil and window-sum stages above,
+ *   - a stencil with a frame window (Table I, spatio-temporal operation): rt
+ *     frames back, weights w[tau][v + ry][u + rx] for tau = 0..rt (tau = frames
+ *     back), out(x, y, t) = sum_{tau, v, u} w[tau][v][u] * in(x + u, y + v,
+ *     max(t - tau, 0)): replicate borders in space and, before the first
+ *     frame, in time;
+ *   - an IIR filter (Table II "IIR Filter", a multi-frame point operation):
+ *     y[t] = a * x[t] + (1 - a) * y[t - 1] per pixel, with y[-1] := x[0] (so
+ *     y[0] = x[0]).
+ * Frames are no longer independent, so the chain runs stage by stage over the
+ * whole volume: every stage's output for all frames is formed from its input
+ * for all frames before the next stage starts.
+ */
+enum { OR_G_IIR = 3 };
+
+int or_gchain_seq(const int32_t* kind, const int32_t* rx, const int32_t* ry, const int32_t* rt, const int32_t* pk,
+                  const double* pa, const double* pb, const double* w, int32_t n, const double* in, int32_t W,
+                  int32_t H, int32_t T, double* out)
+{
+    if (n <= 0 || W <= 0 || H <= 0 || T <= 0) return -10;
+    const size_t P = (size_t)W * H, V = P * T;
+    double* a = (double*)malloc(sizeof(double) * V);
+    double* b = (double*)malloc(sizeof(double) * V);
+    double* tmp = (double*)malloc(sizeof(double) * P);
+    if (!a || !b || !tmp) { free(a); free(b); free(tmp); return -1; }
+    memcpy(a, in, sizeof(double) * V);
+    size_t woff = 0;
+    int status = 0;
+    for (int s = 0; s < n && status == 0; ++s) {
+        switch (kind[s]) {
+        case OR_G_POINT:
+            for (int t = 0; t < T; ++t) or_point(a + t * P, b + t * P, W, H, pk[s], pa[s], pb[s]);
+            break;
+        case OR_G_BOX:
+            if (rx[s] < 0 || ry[s] < 0) { status = -12; break; }
+            for (int t = 0; t < T; ++t) or_box(a + t * P, b + t * P, W, H, rx[s], ry[s]);
+            break;
+        case OR_G_STENCIL: {
+            if (rx[s] < 0 || ry[s] < 0 || rt[s] < 0) { status = -12; break; }
+            const size_t nw = (size_t)(2 * rx[s] + 1) * (2 * ry[s] + 1);
+            for (int t = 0; t < T; ++t) {
+                double* o = b + t * P;
+                for (size_t i = 0; i < P; ++i) o[i] = 0.0;
+                for (int tau = 0; tau <= rt[s]; ++tau) {
+                    const int tf = t - tau < 0 ? 0 : t - tau;
+                    or_stencil(a + tf * P, tmp, W, H, rx[s], ry[s], w + woff + tau * nw);
+                    for (size_t i = 0; i < P; ++i) o[i] += tmp[i];
+                }
+            }
+            woff += nw * (rt[s] + 1);
+            break;
+        }
+        case OR_G_IIR: {
+            const double c = pa[s];
+            for (size_t i = 0; i < P; ++i) {
+                double y = a[i];  /* y[-1] := x[0] */
+                for (int t = 0; t < T; ++t) {
+                    y = c * a[t * P + i] + (1.0 - c) * y;
+                    b[t * P + i] = y;
+                }
+            }
+            break;
+        }
+        default: status = -3;
+        }
+        double* sw = a; a = b; b = sw;
+    }
+    if (status == 0) memcpy(out, a, sizeof(double) * V);
+    free(a); free(b); free(tmp);
     return status;
 }
