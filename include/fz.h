@@ -245,6 +245,26 @@ fz_status fz_run_chain(const fz_plan* plan, const void* d_in, void* d_out, fz_po
                        uint32_t* d_point_count, uint32_t point_capacity, void* d_workspace,
                        size_t ws_bytes, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same run
+ * as fz_run_chain, with the workspace for intermediates between groups taken
+ * from a fixed device array inside the library instead of a caller buffer.
+ * The caller still owns d_in, d_out, d_points and d_point_count (meanings as
+ * in fz_run_chain).  The call itself allocates nothing.
+ *   - Limit: plans whose fz_workspace_bytes() exceeds FZ_STATIC_WORKSPACE_BYTES
+ *     (64 MiB) are refused with FZ_E_WORKSPACE before anything is launched or
+ *     any device is touched; a fully fused plan needs no workspace at all.
+ *   - Each GPU the library runs on holds its own 64 MiB array from the first
+ *     call on that device (which looks its address up) until the process ends.
+ *   - Every call on one GPU shares that GPU's array and leaves its contents
+ *     behind: calls that overlap in time on one device (two streams or two
+ *     host threads) race on it and must be serialised by the caller.
+ * Runs on the current device; FZ_E_HIP if the array's address cannot be
+ * found. */
+#define FZ_STATIC_WORKSPACE_BYTES ((size_t)64 << 20)
+fz_status fz_run_chain_static(const fz_plan* plan, const void* d_in, void* d_out, fz_point* d_points,
+                              uint32_t* d_point_count, uint32_t point_capacity, void* stream);
+
 /* One clip of a batch: its own input, output, size and feature-point buffer. */
 typedef struct fz_clip {
     const void* d_in;               /* input video, layout of the plan's first stage */

@@ -103,6 +103,8 @@ SIGNATURES = [
     ("fz_run_chain", ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                       ctypes.c_void_p, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_size_t,
                                       ctypes.c_void_p]),
+    ("fz_run_chain_static", ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                             ctypes.c_void_p, ctypes.c_uint32, ctypes.c_void_p]),
     ("fz_batch_workspace_bytes", ctypes.c_size_t, [ctypes.c_void_p, ctypes.POINTER(fz_clip), ctypes.c_int32]),
     ("fz_run_batch", ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(fz_clip), ctypes.c_int32, ctypes.c_void_p,
                                       ctypes.c_size_t, ctypes.c_void_p]),
@@ -249,6 +251,13 @@ def fz_plan_measure(plan, d_in, d_workspace, ws_bytes, reps, stream):
 def fz_run_chain(plan, d_in, d_out, d_points, d_point_count, point_capacity, d_workspace, ws_bytes, stream):
     _check(lib().fz_run_chain(plan, d_in, d_out, d_points, d_point_count, point_capacity, d_workspace, ws_bytes,
                               stream))
+
+
+FZ_STATIC_WORKSPACE_BYTES = 64 << 20
+
+
+def fz_run_chain_static(plan, d_in, d_out, d_points, d_point_count, point_capacity, stream):
+    _check(lib().fz_run_chain_static(plan, d_in, d_out, d_points, d_point_count, point_capacity, stream))
 
 
 def fz_batch_workspace_bytes(plan, clips) -> int:
@@ -494,6 +503,23 @@ class Plan:
                      workspace.data_ptr(), workspace.numel(), stream)
         return out, points, count
 
+
+    def run_static(self, x, out=None, points=None, count=None, stream=None):
+        """fz_run_chain_static: the same run with the library's own fixed
+        workspace (no workspace tensor).  Buffers are checked as in run()."""
+        import torch
+        check_tensor(x, self.input_shape(), self.input_dtype(), "input")
+        if out is None:
+            out = torch.empty(self.output_shape(), dtype=self.output_dtype(), device=x.device)
+        check_tensor(out, self.output_shape(), self.output_dtype(), "output", x.device)
+        check_points(points, count, x.device)
+        if stream is None:
+            stream = torch.cuda.current_stream(x.device).cuda_stream
+        cap = points.shape[0] if points is not None else 0
+        fz_run_chain_static(self.handle, x.data_ptr(), out.data_ptr(),
+                            points.data_ptr() if points is not None else None,
+                            count.data_ptr() if count is not None else None, cap, stream)
+        return out, points, count
 
 def check_tensor(t, shape, dtype, what, device=None):
     """A contiguous CUDA tensor of the given dtype (and shape, and device)."""

@@ -25,6 +25,19 @@ def test_library_exports_every_declared_symbol():
     assert declared == {n for n, _, _ in fz.SIGNATURES}
 
 
+def test_static_workspace_refuses_oversized_plans_on_the_host():
+    """fz_run_chain_static checks the plan's workspace against its fixed
+    array before touching any device: an unfused 800x600x40 plan needs more
+    than 64 MiB and is refused (the buffer addresses are never used)."""
+    plan = fz.Plan(fz.RGB_HARRIS_CHAIN, 800, 600, 40, partition="unfused")
+    assert plan.workspace_bytes > fz.FZ_STATIC_WORKSPACE_BYTES
+    rc = fz.lib().fz_run_chain_static(plan.handle, 1, 1, None, None, 0, None)
+    assert rc == fz.FZ_E_WORKSPACE
+    assert "static" in fz.fz_last_error()
+    rc = fz.lib().fz_run_chain_static(plan.handle, None, 1, None, None, 0, None)
+    assert rc == fz.FZ_E_INVALID
+
+
 @pytest.mark.parametrize("n", range(1, 11))
 def test_dp_equals_exhaustive_random_tables(n):
     rng = np.random.default_rng(100 + n)
