@@ -11,6 +11,8 @@ never imports it.
 * ``partition``: brute-force enumeration of every contiguous partition of a
   kernel sequence (Sec. VI, Fig. 5 model).
 * ``mlp``: FP64 forward / backward of the cost-model network.
+* ``track``: Kalman tracking of feature points (``track.c``), the stage the
+  paper applies after the chain (Sec. III, Table II).
 """
 from __future__ import annotations
 
@@ -41,7 +43,8 @@ def build(force: bool = True) -> str:
     if force or not os.path.exists(_LIB_PATH):
         tmp = _LIB_PATH + ".tmp"
         subprocess.check_call(["gcc", "-O2", "-fno-fast-math", "-ffp-contract=off", "-fPIC", "-shared",
-                               "-std=c99", "-o", tmp, os.path.join(_HERE, "oracle.c"), "-lm", "-lpthread"])
+                               "-std=c99", "-o", tmp, os.path.join(_HERE, "oracle.c"), os.path.join(_HERE, "track.c"),
+                               "-lm", "-lpthread"])
         os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
 
@@ -65,6 +68,9 @@ def _load():
         lib.or_gchain_seq.restype = ctypes.c_int
         lib.or_gchain_seq.argtypes = [i32, i32, i32, i32, i32, d, d, d, ctypes.c_int32, d, ctypes.c_int32,
                                       ctypes.c_int32, ctypes.c_int32, d]
+        lib.or_track.restype = ctypes.c_int64
+        lib.or_track.argtypes = [i32, ctypes.c_int64, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
+                                 ctypes.c_double, ctypes.c_int32, ctypes.c_double, i32, d, ctypes.c_int64]
         _lib = lib
     return _lib
 
@@ -203,3 +209,28 @@ def gchain(stages, volume, nthreads=None):
     if rc != 0:
         raise RuntimeError(f"oracle generic chain failed with code {rc}")
     return out
+
+
+# ---------------------------------------------------------------- tracking
+TRACK_DEFAULTS = dict(q=0.5, r=1.0, gate=9.21, v0=4.0, max_miss=3)
+
+
+def track(points, T, q=0.5, r=1.0, gate=9.21, max_miss=3, v0=4.0):
+    """Kalman tracking of feature points (``track.c``): points [n][>=3] rows
+    (t, y, x, ...) in any order, frames 0..T-1.  Returns (ints [m][3] rows
+    (t, id, status), states [m][4] rows (x, y, vx, vy)), one row per live
+    track and frame, ordered by frame, then by id (status 0 predicted only,
+    1 updated, 2 started)."""
+    lib = _load()
+    p = np.ascontiguousarray(np.asarray(points)[:, :3], dtype=np.int32) if len(points) else np.zeros((0, 3), np.int32)
+    cap = max(1, 4 * len(p) * (max_miss + 2) + 16)
+    oi = np.zeros((cap, 3), np.int32)
+    od = np.zeros((cap, 4), np.float64)
+    i32 = ctypes.POINTER(ctypes.c_int32)
+    n = lib.or_track(p.ctypes.data_as(i32), len(p), int(T), float(q), float(r), float(gate), int(max_miss),
+                     float(v0), oi.ctypes.data_as(i32), _dp(od), cap)
+    if n < 0:
+        raise RuntimeError(f"oracle tracker failed with code {n}")
+    if n > cap:
+        raise RuntimeError("oracle tracker output overflow")
+    return oi[:n].copy(), od[:n].copy()
