@@ -71,10 +71,19 @@ enum {
      * window reads use replicate borders. */
     FZ_OP_STENCIL = 11,   /* rectangular, radii rx, ry in [0, 3]: out(x,y) = sum_{v,u} w[v+ry][u+rx] in(x+u, y+v),
                              `weights` = (2ry+1) x (2rx+1) floats, row-major; summed in row order v = -ry..ry,
-                             each row u = -rx..rx, by fused multiply-adds from 0 */
+                             each row u = -rx..rx, by fused multiply-adds from 0.
+                             Spatio-temporal (Table I) when rt in [1, 3]: the stencil also reads the rt frames
+                             before t, out(x,y,t) = sum_{tau=0..rt} sum_{v,u} w[tau][v+ry][u+rx] in(x+u, y+v, t-tau)
+                             with frames before the first replicating the first; `weights` then holds
+                             (rt+1) x (2ry+1) x (2rx+1) floats (tau = 0 is the current frame), summed frame by
+                             frame from tau = 0, each frame as above, one multiply-add chain */
     FZ_OP_BOX = 12,       /* rectangular, radii rx, ry in [0, 3]: unweighted window sum; each row summed
                              left to right, the row sums added top to bottom */
-    FZ_OP_POINT = 13      /* point op: param[0] = FZ_POINT_* kind, param[1] = a, param[2] = b */
+    FZ_OP_POINT = 13,     /* point op: param[0] = FZ_POINT_* kind, param[1] = a, param[2] = b */
+    FZ_OP_IIR = 14        /* multi-frame point op (Table II "IIR filter"), rt = -1 (every earlier frame):
+                             y[t] = a x[t] + (1 - a) y[t-1] per pixel with y[-1] := x[0], param[0] = a in (0, 1];
+                             the state and fma(a, x, (1 - a) y_prev) in double precision, each output rounded
+                             once to f32.  A group holding an IIR marches every frame of the clip in order */
 };
 
 /* Kinds of FZ_OP_POINT. */
@@ -140,8 +149,15 @@ typedef struct fz_plan_opts {
  * columns keeping each stage's live rows in registers (the Harris chain from
  * the Gaussian or the gray conversion to the suppression or the frame
  * difference, frames at least 128 pixels wide).  AUTO picks ROW where it
- * applies, TILE elsewhere. */
-enum { FZ_ENGINE_AUTO = 0, FZ_ENGINE_TILE = 1, FZ_ENGINE_ROW = 2, FZ_ENGINE_STREAM = 3 };
+ * applies, TILE elsewhere.  JIT (generic chains only; Sec. X's generated
+ * fused kernels): each generic group with a window stage and no temporal
+ * stage gets a kernel written out for its stage list -- radii, box sizes and
+ * weights as constants, point stages inline -- compiled for gfx950 with
+ * hipRTC when the plan is made (a compile error fails fz_plan_chain), loaded
+ * on each device at its first run and cached for the process; tiles 16x16,
+ * 32x16, 32x32, 64x16, 64x32.  Its output equals TILE's to the bit.  Other
+ * groups of a JIT plan run as in AUTO. */
+enum { FZ_ENGINE_AUTO = 0, FZ_ENGINE_TILE = 1, FZ_ENGINE_ROW = 2, FZ_ENGINE_STREAM = 3, FZ_ENGINE_JIT = 4 };
 
 typedef struct fz_plan fz_plan;  /* opaque, host memory */
 
@@ -165,6 +181,16 @@ typedef struct fz_segment_info {
  * unknown op. */
 fz_status fz_stage_describe(int32_t op, fz_stage* out);
 
+/* Box sizing of Sec. VI-E (Eq. 6): of the boxes x * x * t with x^2 t = beta
+ * (pixels), the one whose input box (x + 2 dx)^2 (t + dt) is least, for a halo
+ * of dx pixels per side and dt frames: x = cbrt(2 beta dx / dt),
+ * t = cbrt(beta) (dt / dx)^(2/3) / 2^(2/3).  With dt = 0 the flattest box
+ * (t = 1, x = sqrt(beta)); with dx = 0 the thinnest (x = 1, t = beta).
+ * The planner uses it for the frame run of groups with a stencil that looks
+ * back, with beta = W H T / 1024 output pixels per work item (the work items
+ * that fill the device).  FZ_E_INVALID for beta <= 0 or a negative halo. */
+fz_status fz_box_eq6(double beta, double dx, double dt, double* x, double* t);
+
 /* Plan a chain (Sec. VI-A): validate the n stage descriptors (host array),
  * split them into fusable sets at kernel-to-kernel dependences, price every
  * contiguous group, and pick the partition of least total cost (ties: fewer
@@ -174,9 +200,15 @@ fz_status fz_stage_describe(int32_t op, fz_stage* out);
  * *out owns a new plan the caller frees with fz_plan_destroy().  The chain must
  * be a contiguous part of  rgb2gray, gauss5, sobel3, products, boxsum5,
  * harris, threshold, nms3, framediff  or of  gauss5, sobel3, gradmag, or a
- * sequence of generic stages (FZ_OP_STENCIL / FZ_OP_BOX / FZ_OP_POINT; a
- * window stage must declare FZ_DEP_TMT or FZ_DEP_KK); other sequences give
- * FZ_E_UNSUPPORTED.  Stencil weights must be finite and are copied. */
+ * sequence of generic stages (FZ_OP_STENCIL / FZ_OP_BOX / FZ_OP_POINT /
+ * FZ_OP_IIR; a window stage must declare FZ_DEP_TMT or FZ_DEP_KK); other
+ * sequences give FZ_E_UNSUPPORTED.  Stencil weights must be finite and are
+ * copied.  A group's stencils may hold at most 784 weights in all (over every
+ * frame they read); larger groups are not formed.  Chains with temporal
+ * generic stages (an IIR, a stencil with rt > 0) cannot use FZ_COST_LEARNED
+ * (FZ_E_UNSUPPORTED: the cost network was not trained on them), and a
+ * frames_per_block request below the clip length is refused for a group that
+ * holds an IIR. */
 fz_status fz_plan_chain(const fz_stage* stages, int32_t n, const fz_plan_opts* opts, fz_plan** out);
 
 void fz_plan_destroy(fz_plan* plan);
@@ -290,6 +322,77 @@ size_t fz_batch_workspace_bytes(const fz_plan* plan, const fz_clip* clips, int32
  * once.  n_clips in [1, 1024]. */
 fz_status fz_run_batch(fz_plan* plan, const fz_clip* clips, int32_t n_clips, void* d_workspace, size_t ws_bytes,
                        void* stream);
+
+/* ---------------------------------------------------------------- tracking
+ * The paper's pipeline ends by applying a Kalman filter to the extracted
+ * feature points (Sec. III; Table II "Apply Kalman Filter": single point,
+ * multi-frame); Table IV marks it kernel-to-kernel dependent, so it is never
+ * fused with the kernels before it.  fz_track_points runs it on the point
+ * list a chain's FZ_OP_NMS3 stage produced (its own launches, after the
+ * chain, on the same stream).  The paper gives no model; this one is the
+ * discrete Kalman filter with a constant-velocity state s = (x, y, vx, vy)
+ * (column, row, pixels per frame):
+ *   F = [[1,0,1,0],[0,1,0,1],[0,0,1,0],[0,0,0,1]],
+ *   Q = q [[1/4,0,1/2,0],[0,1/4,0,1/2],[1/2,0,1,0],[0,1/2,0,1]],
+ *   H = [[1,0,0,0],[0,1,0,0]], R = r I.
+ * Per frame t, with the frame's points ordered by (y, x):
+ *   1. every live track is predicted: s = F s, P = F P F^T + Q;
+ *   2. every (track, point) pair with d2 = nu^T S^-1 nu <= gate is a candidate
+ *      (nu = (x, y) - H s, S = H P H^T + R, S^-1 = adj(S) / det(S));
+ *   3. candidates are taken in increasing (d2, track id, point index) order
+ *      when neither side is taken yet (greedy nearest neighbour);
+ *   4. a matched track is updated (K = P H^T S^-1, s += K nu,
+ *      P = (I - K H) P); an unmatched one keeps its prediction and is dropped
+ *      after more than max_miss missed frames in a row;
+ *   5. every point left over starts a track: s = (x, y, 0, 0),
+ *      P = diag(r, r, v0, v0), ids counting up from 0 in point order.
+ * Double precision throughout, every matrix product summed over k = 0, 1, ...
+ * from 0.0 without contraction, so the association and the states are
+ * reproducible to the bit. */
+enum {
+    FZ_TRACK_MAX_TRACKS = 4096,              /* live tracks at once */
+    FZ_TRACK_TOO_MANY_POINTS = 1,            /* a frame had more than 1024 points: the rest were ignored */
+    FZ_TRACK_TOO_MANY_CANDIDATES = 2,        /* a frame had more than 2048 gated pairs: the rest were ignored */
+    FZ_TRACK_TOO_MANY_TRACKS = 4             /* more than max_tracks live tracks: the newest were not started */
+};
+
+typedef struct fz_track_opts {
+    double q;           /* process-noise intensity (pixels^2 per frame^4 of acceleration), >= 0 */
+    double r;           /* measurement variance (pixels^2), > 0 */
+    double gate;        /* candidate threshold on the squared Mahalanobis distance, >= 0 */
+    double v0;          /* initial velocity variance of a new track (pixels^2 per frame^2), >= 0 */
+    int32_t max_miss;   /* frames a track may go unmatched in a row before it is dropped, >= 0 */
+    int32_t max_tracks; /* live tracks kept at once, 1 .. FZ_TRACK_MAX_TRACKS */
+} fz_track_opts;
+
+/* One live track after frame t. */
+typedef struct fz_track {
+    uint32_t t, id;
+    int32_t status;     /* 0 predicted only, 1 updated by a point, 2 started by a point */
+    uint32_t pad;
+    double x, y, vx, vy;
+} fz_track;
+
+/* Defaults: q = 0.5, r = 1, gate = 9.21 (chi-square, 2 degrees of freedom,
+ * 99%), v0 = 4, max_miss = 3, max_tracks = FZ_TRACK_MAX_TRACKS. */
+fz_status fz_track_default_opts(fz_track_opts* out);
+/* Device workspace fz_track_points needs for `frames` frames and a point
+ * buffer of `point_capacity` records. */
+size_t fz_track_workspace_bytes(int32_t frames, uint32_t point_capacity, const fz_track_opts* opts);
+/* Track the points of a clip of `frames` frames:
+ *   d_points, d_point_count, point_capacity: the chain's point buffer as
+ *           fz_run_chain left it (device; min(*d_point_count, capacity)
+ *           records are read; points with t >= frames are ignored);
+ *   d_tracks, track_capacity: output records (device, caller-owned), one per
+ *           live track and frame, in unspecified order;
+ *   d_track_count: two device uint32: [0] the number of records (counting
+ *           past the capacity), [1] FZ_TRACK_* flags of limits hit.
+ * Asynchronous on `stream`; read the counts after it synchronises.
+ * FZ_E_INVALID for bad sizes or options, FZ_E_WORKSPACE if ws_bytes is below
+ * fz_track_workspace_bytes(). */
+fz_status fz_track_points(const fz_point* d_points, const uint32_t* d_point_count, uint32_t point_capacity,
+                          int32_t frames, const fz_track_opts* opts, fz_track* d_tracks, uint32_t* d_track_count,
+                          uint32_t track_capacity, void* d_workspace, size_t ws_bytes, void* stream);
 
 /* Message for the calling thread's last failed call ("" if none). */
 const char* fz_last_error(void);

@@ -68,7 +68,7 @@ def build(jobs: int | None = None, verbose: bool = False, incremental: bool = Fa
     if failed:
         raise RuntimeError("compilation failed: " + ", ".join(os.path.basename(f[0]) for f in failed))
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + [t[1] for t in tasks]
+    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + [t[1] for t in tasks] + ["-lhiprtc"]
     subprocess.check_call(cmd)
     os.replace(tmp, LIB)
     return LIB

@@ -130,18 +130,23 @@ def init_params(F, seed):
     return np.concatenate([W1.ravel(), np.zeros(H), W2.ravel(), np.full(H, 0.01), W3, [0.0]]).astype(np.float32)
 
 
-def train_mlp(X, y, steps=4000, lr=3e-3, seed=0, log_every=0, batch=0, X_val=None, y_val=None, eval_every=250):
+def train_mlp(X, y, steps=4000, lr=3e-3, seed=0, log_every=0, batch=0, X_val=None, y_val=None, eval_every=250,
+              p_init=None):
     """Adam with the library's GPU kernels: full batch (batch = 0) or mini-batches
-    of `batch` rows drawn from a seeded shuffle.  With a validation set, the
-    parameters of least validation loss (checked every `eval_every` steps) are
-    returned.  Returns (params, {"best_step", "val": [(step, loss)]})."""
+    of `batch` rows drawn from a seeded shuffle, from a seeded initialisation or
+    from `p_init`.  With a validation set, the parameters of least validation
+    loss (checked every `eval_every` steps) are returned.  Returns (params,
+    {"best_step", "val": [(step, loss)]})."""
     import torch
     dev = torch.device("cuda:0")
     F = X.shape[1]
     n = X.shape[0]
     P = fz.fz_mlp_param_count(F)
-    p0 = init_params(F, seed)
-    p0[-1] = float(np.mean(y))  # start the output bias at the mean target
+    if p_init is not None:
+        p0 = np.array(p_init, np.float32)
+    else:
+        p0 = init_params(F, seed)
+        p0[-1] = float(np.mean(y))  # start the output bias at the mean target
     rng = np.random.default_rng(seed)
     perm = rng.permutation(n) if batch else np.arange(n)
     dp = torch.tensor(p0, device=dev)
@@ -309,6 +314,128 @@ def campaign():
             "test": cases(1005, 8) + random_cases(9500, 500)}
 
 
+# Fixed-chain sizes: a grid for training, and held-out (chain, W, H, T) tuples
+# that the grid never contains (frame counts off the grid), for the tests.
+FIXED_T_GRID = [8, 16, 32, 64, 128, 256]
+FIXED_HELD_OUT = [("rgb_harris", 640, 480, 40), ("harris", 320, 240, 100), ("grad", 800, 600, 48),
+                  ("rgb_harris", 192, 432, 90), ("harris", 800, 600, 20), ("grad", 640, 480, 150),
+                  ("harris", 192, 432, 300), ("rgb_harris", 320, 240, 200)]
+
+
+def fixed_campaign():
+    """Fixed chains: training = every chain at the four frame sizes and the
+    frame counts of FIXED_T_GRID; test = FIXED_HELD_OUT (sizes off the grid)."""
+    train = [(c, W, H, T) for c in sorted(CHAINS) for (W, H) in FRAME_SIZES for T in FIXED_T_GRID]
+    held = set(FIXED_HELD_OUT)
+    assert not held & set(train)
+    return {"train": train, "test": list(FIXED_HELD_OUT)}
+
+
+def forward_np(params, X):
+    """The cost network on the host in FP64 (numpy), parameter layout of fz_mlp_forward."""
+    X = np.asarray(X, np.float64)
+    F, Hd = X.shape[1], 64
+    p = np.asarray(params, np.float64)
+    o = 0
+    W1 = p[o:o + Hd * F].reshape(Hd, F); o += Hd * F
+    b1 = p[o:o + Hd]; o += Hd
+    W2 = p[o:o + Hd * Hd].reshape(Hd, Hd); o += Hd * Hd
+    b2 = p[o:o + Hd]; o += Hd
+    W3 = p[o:o + Hd]; o += Hd
+    b3 = p[o]
+    h1 = np.maximum(X @ W1.T + b1, 0.0)
+    h2 = np.maximum(h1 @ W2.T + b2, 0.0)
+    return h2 @ W3 + b3
+
+
+def group_feature_rows(ops, W, H, T):
+    """Features of every contiguous group of a chain in every configuration
+    (host only: planning needs no device)."""
+    rows = []
+    n = len(ops)
+    for a in range(n):
+        for b in range(a, n):
+            for cfg in group_configs(ops, a, b):
+                extra = {"in_dtype": _in_dtype(ops, a)} if isinstance(ops[0], tuple) else {}
+                try:
+                    plan = fz.Plan(ops[a:b + 1], W, H, T, partition=[], **cfg, **extra)
+                except fz.FzError:
+                    continue
+                rows.append(fz.fz_plan_segment_features(plan.handle, 0))
+    return np.array(rows, np.float32).reshape(-1, fz.fz_cost_n_features())
+
+
+def distill_rows(params, first_seed, n_chains):
+    """Features of the random generic chains' groups (the random workload of the
+    original training, seeds first_seed..), labelled by the current network:
+    fine-tuning on measured fixed-chain times keeps what the network learned
+    of random chains by fitting its own predictions there."""
+    X = np.concatenate([group_feature_rows(case_ops(name), W, H, T)
+                        for name, W, H, T in random_cases(first_seed, n_chains)])
+    return X, forward_np(params, X).astype(np.float32)
+
+
+def measure_fixed(directory, split, reps=5, log=print):
+    """Measure the fixed-chain campaign split into directory/fixed_<split>_NNNN.npz."""
+    os.makedirs(directory, exist_ok=True)
+    todo = fixed_campaign()[split]
+    t0 = time.time()
+    for i, (name, W, H, T) in enumerate(todo):
+        path = os.path.join(directory, f"fixed_{split}_{i:04d}.npz")
+        if os.path.exists(path):
+            continue
+        tab = measure_table(case_ops(name), W, H, T, seed=60000 + 1000 * (split == "test") + i, reps=reps)
+        save_table(path, todo[i], tab)
+        log(f"[costmodel] fixed {split} {i} {name} {W}x{H}x{T}: {len(tab)} samples ({time.time() - t0:.0f} s)")
+
+
+def finetune_fixed(directory, params0, meta0, steps=3000, batch=4096, distill_chains=400, fixed_weight=4,
+                   out=WEIGHTS_PATH, log=print):
+    """Fine-tune the network on measured fixed-chain times (training grid),
+    replicated `fixed_weight` times, together with distillation rows that hold
+    its random-chain predictions; keep the step of least loss on the held-out
+    fixed cases' measured rows; evaluate plan quality on the held-out fixed
+    cases and on any measured random test tables in the directory."""
+    t0 = time.time()
+    train = [load_table(os.path.join(directory, f)) for f in sorted(os.listdir(directory))
+             if f.startswith("fixed_train_")]
+    test = [load_table(os.path.join(directory, f)) for f in sorted(os.listdir(directory))
+            if f.startswith("fixed_test_")]
+    rtest = [load_table(os.path.join(directory, f)) for f in sorted(os.listdir(directory))
+             if f.startswith("test_")]
+    Xf, yf = _rows(train)
+    Xd, yd = distill_rows(params0, 5000, distill_chains)
+    X = np.concatenate([np.repeat(Xf, fixed_weight, axis=0), Xd])
+    y = np.concatenate([np.repeat(yf, fixed_weight), yd])
+    Xv, yv = _rows(test)
+    params, curve = train_mlp(X, y, steps=steps, lr=1e-3, seed=11, batch=batch, X_val=Xv, y_val=yv,
+                              eval_every=100, p_init=params0)
+    rmse = lambda A, b: float(np.sqrt(np.mean((forward_np(params, A) - b) ** 2)))
+    evals = []
+    for (name, W, H, T), tab in test + rtest:
+        r = evaluate_case(case_ops(name), W, H, T, params, tab)
+        r["chain"] = name
+        evals.append(r)
+    geo = lambda rs: float(np.exp(np.mean([math.log(r["learned_ratio"]) for r in rs]))) if rs else None
+    geo_a = lambda rs: float(np.exp(np.mean([math.log(r["analytic_ratio"]) for r in rs]))) if rs else None
+    fixed = [r for r in evals if not r["chain"].startswith("random:")]
+    rnd = [r for r in evals if r["chain"].startswith("random:")]
+    meta = dict(meta0)
+    meta["finetune"] = {
+        "fixed_train_cases": len(train), "fixed_train_rows": int(len(yf)), "fixed_weight": fixed_weight,
+        "distill_chains": distill_chains, "distill_rows": int(len(yd)), "steps": steps, "best_step": curve["best_step"],
+        "rmse_log_us": {"fixed_train": rmse(Xf, yf), "fixed_test": rmse(Xv, yv), "distill": rmse(Xd, yd)},
+        "held_out_fixed_cases": [list(c) for c, _ in test],
+        "geomean_learned_over_best_fixed": geo(fixed), "geomean_analytic_over_best_fixed": geo_a(fixed),
+        "worst_learned_over_best_fixed": max((r["learned_ratio"] for r in fixed), default=None),
+        "geomean_learned_over_best_random": geo(rnd), "geomean_analytic_over_best_random": geo_a(rnd),
+        "random_test_cases": len(rnd), "evaluation": evals, "seconds": time.time() - t0}
+    save_weights(params, meta, out)
+    log(f"[costmodel] fine-tuned: fixed held-out geomean learned {geo(fixed):.4f} (analytic {geo_a(fixed):.4f}), "
+        f"random {geo(rnd) if rnd else float('nan'):.4f} over {len(rnd)} cases")
+    return params, meta
+
+
 def measure_cases(directory, split, first=0, count=None, reps=3, max_seconds=None, log=print):
     """Measure cases [first, first+count) of a campaign split into
     directory/<split>_NNNN.npz, skipping files that exist; stops starting new
@@ -397,6 +524,15 @@ if __name__ == "__main__":
     m.add_argument("--count", type=int, default=None)
     m.add_argument("--reps", type=int, default=3)
     m.add_argument("--max-seconds", type=float, default=None)
+    mf = sub.add_parser("measure-fixed", help="measure the fixed-chain campaign (train grid or held-out test)")
+    mf.add_argument("directory")
+    mf.add_argument("split", choices=["train", "test"])
+    mf.add_argument("--reps", type=int, default=5)
+    ft = sub.add_parser("finetune", help="fine-tune the shipped network on the fixed-chain tables")
+    ft.add_argument("directory")
+    ft.add_argument("out", nargs="?", default=WEIGHTS_PATH)
+    ft.add_argument("--steps", type=int, default=3000)
+    ft.add_argument("--distill-chains", type=int, default=400)
     t = sub.add_parser("train", help="train and evaluate from a directory of tables")
     t.add_argument("directory")
     t.add_argument("out", nargs="?", default=WEIGHTS_PATH)
@@ -407,5 +543,10 @@ if __name__ == "__main__":
     if a.cmd == "measure":
         complete = measure_cases(a.directory, a.split, a.first, a.count, a.reps, a.max_seconds, log=say)
         say(f"[costmodel] {a.split} measurement {'complete' if complete else 'incomplete'}")
+    elif a.cmd == "measure-fixed":
+        measure_fixed(a.directory, a.split, a.reps, log=say)
+    elif a.cmd == "finetune":
+        p0, m0 = load_weights()
+        finetune_fixed(a.directory, p0, m0, steps=a.steps, distill_chains=a.distill_chains, out=a.out, log=say)
     else:
         train_from_tables(a.directory, a.steps, a.batch, 5, a.out, log=say)

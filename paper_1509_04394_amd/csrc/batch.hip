@@ -150,6 +150,17 @@ fz_status run_batch(fz_plan& p, const fz_clip* clips, int n, void* ws, size_t ws
         p.capture_stream = cs;
     }
     hipStream_t cs = (hipStream_t)p.capture_stream;
+    // generated kernels are compiled and their modules loaded before the capture
+    for (int i = 0; i < n; ++i) {
+        bool any = false;
+        for (const Segment& g : p.segs) any |= g.engine == FZ_ENGINE_JIT || p.req_engine == FZ_ENGINE_JIT;
+        if (!any) break;
+        std::unique_ptr<fz_plan> cp(plan_for_size(p, clips[i].width, clips[i].height, clips[i].frames));
+        if (!cp) return fail(FZ_E_LDS, "batch: the partition does not fit clip " + std::to_string(i));
+        for (const Segment& g : cp->segs)
+            if (g.engine == FZ_ENGINE_JIT && (e = (hipError_t)jit_load(*cp, g)) != hipSuccess)
+                return fail(FZ_E_HIP, std::string("batch: loading a generated kernel: ") + hipGetErrorString(e));
+    }
     e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return fail(FZ_E_HIP, std::string("begin capture: ") + hipGetErrorString(e));
     fz_status st = enqueue_batch(p, clips, n, ws, ws_bytes, cs, cus);

@@ -24,9 +24,9 @@ void group_features(const fz_plan& p, const Segment& g, float* f)
     if (p.generic) {
         for (int j = g.first; j <= g.last; ++j) {
             const fz_stage& s = p.stages[j];
-            const int kind = s.op == FZ_OP_POINT ? G_POINT : (s.op == FZ_OP_STENCIL ? G_STENCIL : G_BOX);
-            nwin += kind != G_POINT;
-            ops += generic_ops(kind, s.rx, s.ry, (int)s.param[0]);
+            const int kind = g_kind(s.op);
+            nwin += g_is_window(kind);
+            ops += generic_ops(kind, s.rx, s.ry, (int)s.param[0], s.rt > 0 ? s.rt : 0);
         }
         bytes_in = dt_bytes(p.stages[g.first].in_dtype);
         bytes_out = 4;

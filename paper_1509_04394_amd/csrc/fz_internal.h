@@ -27,7 +27,7 @@ struct Segment {
     int row_gen;            // 1: generic row kernel, 0: the Harris-chain kernel
     double bytes_per_px;
     double cost;
-    int refused;            // a requested band / frame run this group's kernel cannot run (cost is +inf)
+    int refused;            // a request this group's kernel cannot run (cost is +inf): 1 a band, 2 an IIR frame run
 };
 
 struct Params {
@@ -73,7 +73,9 @@ fz_status fail(fz_status code, const std::string& msg);
 Segment price_group(const fz_plan& p, int a, int b, int tile_req_w, int tile_req_h, int tpb_req, int engine_req);
 
 // Generic chains: price of group [a..b] (planner.cpp) and its launch (generic.hip)
-Segment price_generic(const fz_plan& p, int a, int b, int req_w, int req_h, int req_engine);
+Segment price_generic(const fz_plan& p, int a, int b, int req_w, int req_h, int req_tpb, int req_engine);
+// Sec. VI-E, Eq. 6 box for a volume beta and halos dx (per side), dt (frames)
+void eq6_box(double beta, double dx, double dt, double* x, double* t);
 int launch_generic(const fz_plan& p, const Segment& g, const void* in, void* out, void* stream);  // hipError_t
 
 // Learned prices (cost.cpp)
@@ -101,5 +103,16 @@ fz_plan* plan_for_size(const fz_plan& base, int W, int H, int T);
 fz_status run_batch(fz_plan& p, const fz_clip* clips, int n, void* ws, size_t ws_bytes, void* stream);
 size_t batch_workspace_bytes(const fz_plan& p, const fz_clip* clips, int n);
 void release_batch(fz_plan& p);
+
+// Generated kernels of generic groups (jit.cpp): source text, compile (no device needed), launch
+std::string jit_source(const fz_plan& p, const Segment& g);
+fz_status jit_prepare(const fz_plan& p, const Segment& g);
+int launch_jit(const fz_plan& p, const Segment& g, const void* in, void* out, void* stream);  // hipError_t
+int jit_load(const fz_plan& p, const Segment& g);  // hipError_t: compile and load on the current device
+
+// Kalman tracking of feature points (track.hip)
+size_t track_workspace_bytes(int T, uint32_t point_capacity, uint32_t max_tracks);
+fz_status track_points(const fz_point* d_points, const uint32_t* d_count, uint32_t cap, int T, const fz_track_opts& o,
+                       fz_track* d_tracks, uint32_t* d_track_count, uint32_t track_cap, void* ws, void* stream);
 
 }  // namespace fz

@@ -40,12 +40,17 @@ FZ_HD constexpr OpInfo op_info(int op)
     case FZ_OP_STENCIL: return {op, 1, 0, 1, 1, FZ_F32, FZ_F32, FZ_DEP_TMT, 9};
     case FZ_OP_BOX: return {op, 1, 0, 1, 1, FZ_F32, FZ_F32, FZ_DEP_TMT, 9};
     case FZ_OP_POINT: return {op, 0, 0, 1, 1, FZ_F32, FZ_F32, FZ_DEP_TT, 1};
+    // IIR filter (Table II): a point operation over every earlier frame (rt = -1)
+    case FZ_OP_IIR: return {op, 0, -1, 1, 1, FZ_F32, FZ_F32, FZ_DEP_TT, 2};
     default: return {0, 0, 0, 0, 0, 0, 0, 0, 0};
     }
 }
 
 FZ_HD constexpr int dt_bytes(int dt) { return dt == FZ_F32 ? 4 : 1; }
-FZ_HD constexpr bool is_generic_op(int op) { return op == FZ_OP_STENCIL || op == FZ_OP_BOX || op == FZ_OP_POINT; }
+FZ_HD constexpr bool is_generic_op(int op)
+{
+    return op == FZ_OP_STENCIL || op == FZ_OP_BOX || op == FZ_OP_POINT || op == FZ_OP_IIR;
+}
 
 // The stage sequences the kernels are compiled for.  A user chain is any
 // contiguous part of one of them.

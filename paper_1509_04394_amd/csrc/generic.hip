@@ -84,11 +84,11 @@ struct UDiv {
 // coprime with the LDS bank count, so the lanes of a read or write fall on
 // distinct banks (with four cells per thread, four lanes share each bank).
 constexpr int GQ = 5;
+// The window of GQ cells is added into acc, which the caller zeroes first (a
+// stencil that looks back over several frames adds one frame after another).
 template <bool STENCIL, int RX, int RY>
-__device__ __forceinline__ void windowq(const float* src, int RW, int base, const float* w, float (&acc)[GQ])
+__device__ __forceinline__ void windowq_add(const float* src, int RW, int base, const float* w, float (&acc)[GQ])
 {
-#pragma unroll
-    for (int k = 0; k < GQ; ++k) acc[k] = 0.0f;
 #pragma unroll
     for (int v = -RY; v <= RY; ++v) {
         float x[GQ + 2 * RX];
@@ -118,10 +118,10 @@ __device__ __forceinline__ void windowq_ry(int ry, const float* src, int RW, int
                                            float (&acc)[GQ])
 {
     switch (ry) {
-    case 0: windowq<STENCIL, RX, 0>(src, RW, base, w, acc); break;
-    case 1: windowq<STENCIL, RX, 1>(src, RW, base, w, acc); break;
-    case 2: windowq<STENCIL, RX, 2>(src, RW, base, w, acc); break;
-    default: windowq<STENCIL, RX, 3>(src, RW, base, w, acc); break;
+    case 0: windowq_add<STENCIL, RX, 0>(src, RW, base, w, acc); break;
+    case 1: windowq_add<STENCIL, RX, 1>(src, RW, base, w, acc); break;
+    case 2: windowq_add<STENCIL, RX, 2>(src, RW, base, w, acc); break;
+    default: windowq_add<STENCIL, RX, 3>(src, RW, base, w, acc); break;
     }
 }
 template <bool STENCIL>
@@ -192,6 +192,8 @@ __global__ __launch_bounds__(BLOCK_THREADS) void k_gtile(const GParams p)
                 const int cy = by_nq.quot(e, qx), cx = qx * GQ;
                 const int lx = bx + cx, ly = by + cy;
                 float acc[GQ];
+#pragma unroll
+                for (int k = 0; k < GQ; ++k) acc[k] = 0.0f;
                 if (s.kind == G_STENCIL)
                     windowq_r<true>(s.rx, s.ry, src, RW, ly * RW + lx, w, acc);
                 else
@@ -261,22 +263,272 @@ __global__ __launch_bounds__(BLOCK_THREADS) void k_gstream(const GParams p)
     }
 }
 
-template <int TW, int TH>
-static hipError_t launch_tile(const GParams& gp, int lds, hipStream_t s)
+// ------------------------------------------------------------ temporal stages
+//
+// Table II's IIR filter is a point operation over several frames: per pixel,
+// y[t] = a x[t] + (1 - a) y[t-1] with y[-1] := x[0].  It runs in double
+// precision -- the state and fma(a, x, (1 - a) y_prev), with 1 - a exact in
+// double for an f32 a -- and each output is rounded once to f32: in f32 the
+// recursion's rounding errors would pile up over about 1/a frames (a = 0.05
+// gave 1.1e-4 on a 0-255 scale).  A stencil
+// may also look rt frames back (Table I's spatio-temporal class):
+// out(t) = sum over tau = 0..rt (this frame first) of the frame t - tau
+// window, frames before the first replicating the first; each frame's window
+// is summed as the spatial stencil sums it, continuing one fused multiply-add
+// chain.  Groups with such stages march through frames in order.
+
+// One IIR step of the cell whose running state is *state (first: frame 0).
+__device__ __forceinline__ float giir(const GStage& s, float v, double* state, bool first)
 {
-    if (lds > 65536) {  // allow the dynamic LDS beyond 64 KB (the CU has 160 KB)
-        hipError_t e = hipFuncSetAttribute((const void*)k_gtile<TW, TH>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           163840);
-        if (e != hipSuccess) return e;
+    const double a = (double)s.a, x = (double)v;
+    const double prev = first ? x : *state;
+    const double y = fma(a, x, (1.0 - a) * prev);
+    *state = y;
+    return (float)y;
+}
+
+// Point and IIR stages q0..q1-1 on one value of box cell `cell`.  Each stage
+// descriptor is copied out of the kernel arguments first: a reference into
+// them next to the IIR's LDS store made the compiler copy the whole argument
+// block into scratch memory.
+__device__ __forceinline__ float gtrail(const GParams& p, float* lds, int q0, int q1, float v, int cell, bool first)
+{
+    for (int q = q0; q < q1; ++q) {
+        const GStage s = p.st[q];
+        v = s.kind == G_IIR ? giir(s, v, (double*)(lds + s.buf) + cell, first) : gpoint(s, v);
     }
-    const long long blocks = (long long)gp.tiles_x * gp.tiles_y * gp.T;
+    return v;
+}
+
+// A group with a window stage and a temporal stage (an IIR, or a stencil that
+// looks back): one workgroup owns an output tile and a run of tt frames and
+// marches through frames t0 - ht .. t0 + tt - 1 in order (from frame 0 when the
+// run starts within ht frames of it, and always from frame 0 for an IIR, whose
+// runs are the whole clip).  Per frame it loads the input box once and runs the
+// stages as the tile kernel does; a stencil that looks back reads its earlier
+// input frames from a ring in LDS, an IIR keeps its state per box cell in
+// LDS (layout: march_layout).  The frames before t0 only fill the rings: a
+// stage skips a frame whose ring is not yet full, and nothing is stored before
+// t0.  Every stage evaluates exactly as in the tile kernel, so the bits do not
+// depend on the partition, the tile or the frame run.
+template <int TW, int TH>
+__global__ __launch_bounds__(BLOCK_THREADS) void k_gmarch(const GParams p)
+{
+    extern __shared__ float glds[];
+    const int RW = TW + 2 * p.hx, RH = TH + 2 * p.hy, CELLS = RW * RH;
+    int b = xcd_contiguous(blockIdx.x, gridDim.x);
+    const int tx = b % p.tiles_x;
+    b /= p.tiles_x;
+    const int ty = b % p.tiles_y;
+    const int t0 = (b / p.tiles_y) * p.tt;
+    const int t1 = min(p.T, t0 + p.tt);
+    const int fs = max(0, t0 - p.ht);  // first frame marched
+    const int ox = tx * TW - p.hx, oy = ty * TH - p.hy;
+    const size_t P = (size_t)p.W * p.H;
+    const bool interior = ox >= 0 && oy >= 0 && ox + RW <= p.W && oy + RH <= p.H;
+
+    int lead = 0;
+    while (lead < p.n && !g_is_window(p.st[lead].kind)) ++lead;
+    const UDiv by_rw(RW);
+
+    for (int f = fs; f < t1; ++f) {
+        const bool first = f == 0;
+        const size_t fbase = (size_t)f * P;
+        {
+            const GStage& s0 = p.st[lead];
+            float* dst = glds + s0.buf + (f % s0.slots) * CELLS;
+            for (int e = threadIdx.x; e < CELLS; e += BLOCK_THREADS) {
+                int lx;
+                const int ly = by_rw.quot(e, lx);
+                const int gx = ox + lx, gy = oy + ly;
+                if (gx < 0 || gx >= p.W || gy < 0 || gy >= p.H) continue;
+                const size_t gi = fbase + (size_t)gy * p.W + gx;
+                const float v = p.in_u8 ? (float)((const uint8_t*)p.in)[gi] : ((const float*)p.in)[gi];
+                dst[e] = gtrail(p, glds, 0, lead, v, e, first);
+            }
+        }
+        __syncthreads();
+
+        int i = lead, hx = p.hx, hy = p.hy, back = 0;
+        while (true) {
+            const GStage s = p.st[i];
+            int j = i + 1;
+            while (j < p.n && !g_is_window(p.st[j].kind)) ++j;
+            const bool last = j == p.n;
+            back += s.rt;
+            const int ohx = hx - s.rx, ohy = hy - s.ry;
+            const int OW = TW + 2 * ohx, OH = TH + 2 * ohy;
+            const int bx = p.hx - ohx, by = p.hy - ohy;
+            // this stage's input ring holds frames f - rt .. f (replicated before frame 0)
+            const bool ready = fs == 0 || f >= fs + back;
+            if (ready && (!last || f >= t0)) {
+                float* dst = last ? nullptr : glds + p.st[j].buf + (f % p.st[j].slots) * CELLS;
+                const int nw = (2 * s.rx + 1) * (2 * s.ry + 1);
+                if (interior) {
+                    const int NQ = (OW + GQ - 1) / GQ;
+                    const UDiv by_nq(NQ);
+                    for (int e = threadIdx.x; e < NQ * OH; e += BLOCK_THREADS) {
+                        int qx;
+                        const int cy = by_nq.quot(e, qx), cx = qx * GQ;
+                        const int lx = bx + cx, ly = by + cy;
+                        float acc[GQ];
+#pragma unroll
+                        for (int k = 0; k < GQ; ++k) acc[k] = 0.0f;
+                        for (int tau = 0; tau <= s.rt; ++tau) {
+                            const float* src = glds + s.buf + (max(f - tau, 0) % s.slots) * CELLS;
+                            if (s.kind == G_STENCIL)
+                                windowq_r<true>(s.rx, s.ry, src, RW, ly * RW + lx, p.w + s.woff + tau * nw, acc);
+                            else
+                                windowq_r<false>(s.rx, s.ry, src, RW, ly * RW + lx, nullptr, acc);
+                        }
+                        const int nk = min(GQ, OW - cx);
+#pragma unroll
+                        for (int k = 0; k < GQ; ++k) {
+                            if (k >= nk) break;
+                            const float v = gtrail(p, glds, i + 1, j, acc[k], ly * RW + lx + k, first);
+                            if (last)
+                                p.out[fbase + (size_t)(oy + ly) * p.W + (ox + lx + k)] = v;
+                            else
+                                dst[ly * RW + lx + k] = v;
+                        }
+                    }
+                } else {
+                    const int kw = 2 * s.rx + 1;
+                    const UDiv by_ow(OW);
+                    for (int e = threadIdx.x; e < OW * OH; e += BLOCK_THREADS) {
+                        int cx;
+                        const int cy = by_ow.quot(e, cx);
+                        const int lx = bx + cx, ly = by + cy;
+                        const int gx = ox + lx, gy = oy + ly;
+                        if (gx < 0 || gx >= p.W || gy < 0 || gy >= p.H) continue;
+                        float acc = 0.0f;
+                        for (int tau = 0; tau <= s.rt; ++tau) {
+                            const float* src = glds + s.buf + (max(f - tau, 0) % s.slots) * CELLS;
+                            for (int v = -s.ry; v <= s.ry; ++v) {
+                                const int row = (clampi(gy + v, 0, p.H - 1) - oy) * RW - ox;
+                                if (s.kind == G_STENCIL) {
+                                    const int w0 = s.woff + tau * nw + (v + s.ry) * kw + s.rx;
+                                    for (int u = -s.rx; u <= s.rx; ++u)
+                                        acc = fmaf(p.w[w0 + u], src[row + clampi(gx + u, 0, p.W - 1)], acc);
+                                } else {
+                                    float h = 0.0f;
+                                    for (int u = -s.rx; u <= s.rx; ++u) h = h + src[row + clampi(gx + u, 0, p.W - 1)];
+                                    acc = acc + h;
+                                }
+                            }
+                        }
+                        const float v = gtrail(p, glds, i + 1, j, acc, ly * RW + lx, first);
+                        if (last)
+                            p.out[fbase + (size_t)gy * p.W + gx] = v;
+                        else
+                            dst[ly * RW + lx] = v;
+                    }
+                }
+            }
+            if (last) break;
+            __syncthreads();
+            hx = ohx;
+            hy = ohy;
+            i = j;
+        }
+        __syncthreads();  // the next frame's load reuses the buffers
+    }
+}
+
+// A group of point and IIR stages only: each thread owns PX neighbouring
+// pixels and marches through every frame in order; D frames are loaded before
+// any is processed, so D loads per thread are in flight at once.  The IIR
+// states (doubles) live in LDS, PX per thread and IIR stage (GStage::buf is
+// the stage's offset there, in doubles); registers indexed by a stage number
+// only known at run time would have gone to scratch memory.
+template <int PX, int D>
+__global__ __launch_bounds__(BLOCK_THREADS) void k_gstream_t(const GParams p)
+{
+    extern __shared__ double gstate[];
+    const size_t P = (size_t)p.W * p.H;
+    const size_t i0 = ((size_t)blockIdx.x * BLOCK_THREADS + threadIdx.x) * PX;
+    if (i0 >= P) return;  // no barrier below
+    for (int t = 0; t < p.T; t += D) {
+        float v[D][PX];
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            if (t + d >= p.T) break;
+            const size_t gi = (size_t)(t + d) * P + i0;
+            if constexpr (PX == 4) {
+                if (p.in_u8) {
+                    const uchar4 q = *(const uchar4*)((const uint8_t*)p.in + gi);
+                    v[d][0] = q.x;
+                    v[d][1] = q.y;
+                    v[d][2] = q.z;
+                    v[d][3] = q.w;
+                } else {
+                    const float4 q = *(const float4*)((const float*)p.in + gi);
+                    v[d][0] = q.x;
+                    v[d][1] = q.y;
+                    v[d][2] = q.z;
+                    v[d][3] = q.w;
+                }
+            } else {
+                v[d][0] = p.in_u8 ? (float)((const uint8_t*)p.in)[gi] : ((const float*)p.in)[gi];
+            }
+        }
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            if (t + d >= p.T) break;
+            const bool first = t + d == 0;
+            for (int j = 0; j < p.n; ++j) {
+                const GStage s = p.st[j];
+                if (s.kind == G_IIR) {
+                    double* sp = gstate + s.buf + threadIdx.x * PX;
+                    const double a = (double)s.a;
+#pragma unroll
+                    for (int k = 0; k < PX; ++k) {
+                        const double x = (double)v[d][k];
+                        const double y = fma(a, x, (1.0 - a) * (first ? x : sp[k]));
+                        sp[k] = y;
+                        v[d][k] = (float)y;
+                    }
+                } else {
+#pragma unroll
+                    for (int k = 0; k < PX; ++k) v[d][k] = gpoint(s, v[d][k]);
+                }
+            }
+            const size_t gi = (size_t)(t + d) * P + i0;
+            if constexpr (PX == 4)
+                *(float4*)(p.out + gi) = make_float4(v[d][0], v[d][1], v[d][2], v[d][3]);
+            else
+                p.out[gi] = v[d][0];
+        }
+    }
+}
+
+template <typename K>
+static hipError_t allow_lds(K kernel, int lds)
+{
+    if (lds <= 65536) return hipSuccess;
+    // dynamic LDS beyond 64 KB (the CU has 160 KB)
+    return hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, 163840);
+}
+
+template <int TW, int TH>
+static hipError_t launch_tile(const GParams& gp, int lds, bool march, int nchunks, hipStream_t s)
+{
+    const long long blocks = (long long)gp.tiles_x * gp.tiles_y * (march ? nchunks : gp.T);
     if (blocks > 0x7fffffffLL) return hipErrorInvalidConfiguration;
-    k_gtile<TW, TH><<<dim3((unsigned)blocks), dim3(BLOCK_THREADS), lds, s>>>(gp);
+    hipError_t e;
+    if (march) {
+        if ((e = allow_lds(k_gmarch<TW, TH>, lds)) != hipSuccess) return e;
+        k_gmarch<TW, TH><<<dim3((unsigned)blocks), dim3(BLOCK_THREADS), lds, s>>>(gp);
+    } else {
+        if ((e = allow_lds(k_gtile<TW, TH>, lds)) != hipSuccess) return e;
+        k_gtile<TW, TH><<<dim3((unsigned)blocks), dim3(BLOCK_THREADS), lds, s>>>(gp);
+    }
     return hipGetLastError();
 }
 
 int launch_generic(const fz_plan& p, const Segment& g, const void* in, void* out, void* stream)
 {
+    if (g.engine == FZ_ENGINE_JIT) return launch_jit(p, g, in, out, stream);
     hipStream_t s = (hipStream_t)stream;
     GParams gp{};
     gp.in = in;
@@ -288,25 +540,42 @@ int launch_generic(const fz_plan& p, const Segment& g, const void* in, void* out
     gp.n = g.last - g.first + 1;
     gp.hx = g.halo;
     gp.hy = g.halo_y;
+    if (gp.n > G_MAX_STAGES) return hipErrorInvalidValue;
+    const int need = g_stage_list(p.stages.data(), g.first, g.last, gp.st);
+    if (need > G_MAX_WEIGHTS) return hipErrorInvalidValue;  // the planner never forms such a group
     int nw = 0;
     for (int j = g.first; j <= g.last; ++j) {
-        const fz_stage& st = p.stages[j];
         GStage& d = gp.st[j - g.first];
-        d.kind = st.op == FZ_OP_POINT ? G_POINT : (st.op == FZ_OP_STENCIL ? G_STENCIL : G_BOX);
-        d.rx = st.rx;
-        d.ry = st.ry;
-        d.pk = (int)st.param[0];
-        d.a = st.param[1];
-        d.b = st.param[2];
-        if (d.kind == G_STENCIL) {
-            const int cnt = (2 * st.rx + 1) * (2 * st.ry + 1);
-            d.woff = nw;
-            std::copy(p.gweights.begin() + p.gwoff[j], p.gweights.begin() + p.gwoff[j] + cnt, gp.w + nw);
-            nw += cnt;
-        }
+        if (d.kind != G_STENCIL) continue;
+        const int cnt = (2 * d.rx + 1) * (2 * d.ry + 1) * (d.rt + 1);
+        d.woff = nw;
+        std::copy(p.gweights.begin() + p.gwoff[j], p.gweights.begin() + p.gwoff[j] + cnt, gp.w + nw);
+        nw += cnt;
     }
+    bool has_iir = false;
+    const bool temporal = g_temporal(gp.st, gp.n, &has_iir, &gp.ht);
+    const size_t P = (size_t)p.W * p.H;
     if (g.engine == FZ_ENGINE_STREAM) {
-        const size_t n = (size_t)p.W * p.H * p.T;
+        if (temporal) {  // point and IIR stages: one thread per run of pixels, all frames
+            const bool vec = P % 4 == 0 && ((uintptr_t)in % (gp.in_u8 ? 4 : 16)) == 0 && ((uintptr_t)out % 16) == 0;
+            const int px = vec ? 4 : 1;
+            int n_iir = 0;
+            for (int j = 0; j < gp.n; ++j)
+                if (gp.st[j].kind == G_IIR) gp.st[j].buf = (n_iir++) * BLOCK_THREADS * px;
+            const int lds = n_iir * BLOCK_THREADS * px * 8;  // doubles; a 4-pixel run with 16 IIRs: 128 KB
+            if (lds > 65536) {
+                hipError_t e = vec ? allow_lds(k_gstream_t<4, 8>, lds) : allow_lds(k_gstream_t<1, 8>, lds);
+                if (e != hipSuccess) return e;
+            }
+            const size_t threads = P / px;
+            const unsigned blocks = (unsigned)((threads + BLOCK_THREADS - 1) / BLOCK_THREADS);
+            if (vec)
+                k_gstream_t<4, 8><<<dim3(blocks), dim3(BLOCK_THREADS), lds, s>>>(gp);
+            else
+                k_gstream_t<1, 8><<<dim3(blocks), dim3(BLOCK_THREADS), lds, s>>>(gp);
+            return hipGetLastError();
+        }
+        const size_t n = P * p.T;
         const size_t want = (n + BLOCK_THREADS - 1) / BLOCK_THREADS;
         const unsigned blocks = (unsigned)std::min<size_t>(want, 256 * 32);
         k_gstream<<<dim3(blocks), dim3(BLOCK_THREADS), 0, s>>>(gp);
@@ -314,10 +583,18 @@ int launch_generic(const fz_plan& p, const Segment& g, const void* in, void* out
     }
     gp.tiles_x = (p.W + g.tile_w - 1) / g.tile_w;
     gp.tiles_y = (p.H + g.tile_h - 1) / g.tile_h;
+    int nchunks = 1;
+    if (temporal) {
+        gp.tt = g.tpb;
+        if (gp.tt < 1 || (has_iir && gp.tt < p.T)) return hipErrorInvalidValue;
+        nchunks = (p.T + gp.tt - 1) / gp.tt;
+        const int floats = march_layout(gp.st, gp.n, (g.tile_w + 2 * gp.hx) * (g.tile_h + 2 * gp.hy));
+        if ((floats + GEN_PAD) * 4 != g.lds_bytes) return hipErrorInvalidValue;
+    }
     switch (g.tile) {
-    case 0: return launch_tile<tile_w(0), tile_h(0)>(gp, g.lds_bytes, s);
-    case 1: return launch_tile<tile_w(1), tile_h(1)>(gp, g.lds_bytes, s);
-    case 2: return launch_tile<tile_w(2), tile_h(2)>(gp, g.lds_bytes, s);
+    case 0: return launch_tile<tile_w(0), tile_h(0)>(gp, g.lds_bytes, temporal, nchunks, s);
+    case 1: return launch_tile<tile_w(1), tile_h(1)>(gp, g.lds_bytes, temporal, nchunks, s);
+    case 2: return launch_tile<tile_w(2), tile_h(2)>(gp, g.lds_bytes, temporal, nchunks, s);
     default: return hipErrorInvalidValue;
     }
 }

@@ -63,7 +63,7 @@ Segment price_group(const fz_plan& p, int a, int b, int req_w, int req_h, int re
     s.tile = -1;
     for (int j = a + 1; j <= b; ++j)
         if (p.stages[j].dep == FZ_DEP_KK) return s;  // kernel-to-kernel: never fused (Sec. VI-A)
-    if (p.generic) return price_generic(p, a, b, req_w, req_h, req_engine);
+    if (p.generic) return price_generic(p, a, b, req_w, req_h, req_tpb, req_engine);
     const int ch = p.chain, A = s.cfirst, B = s.clast;
     s.halo = s.halo_y = group_halo(ch, A, B);
     s.halo_t = group_halo_t(ch, A, B);
@@ -129,13 +129,47 @@ Segment price_group(const fz_plan& p, int a, int b, int req_w, int req_h, int re
     return s;
 }
 
-// A generic group: halos are the sums of its window radii per axis; a group
-// with a window stage runs in the generic LDS tile kernel (the tile of best
-// data utilisation, Eq. 3, that fits the budget), a group of point stages in
-// one streaming pass.  Cost: compulsory bytes, input once and output once.
-Segment price_generic(const fz_plan& p, int a, int b, int req_w, int req_h, int req_engine)
+// Sec. VI-E, Eq. 6: among boxes x * x * t of fixed volume x^2 t = beta, the one
+// whose input box (x + 2 dx)^2 (t + dt) is least (dx: halo per side, dt:
+// frames of temporal halo; with the halo per side, Eq. 6 is exactly this
+// minimiser).  Degenerate halos: no temporal halo -> the flattest box (t = 1);
+// no spatial halo -> the thinnest (x = 1).
+void eq6_box(double beta, double dx, double dt, double* x, double* t)
 {
-    (void)req_engine;  // one kernel family per kind of group
+    if (dt <= 0.0) {
+        *t = 1.0;
+        *x = sqrt(beta);
+    } else if (dx <= 0.0) {
+        *x = 1.0;
+        *t = beta;
+    } else {
+        *x = cbrt(2.0 * beta * dx / dt);
+        *t = cbrt(beta) * pow(dt / dx, 2.0 / 3.0) / pow(2.0, 2.0 / 3.0);
+    }
+}
+
+// A generic group: halos are the sums of its window radii per axis, its
+// temporal halo the sum of its stencils' frames back.
+//  * Point stages only: one streaming pass; with an IIR, one thread per run of
+//    four pixels marches through every frame.
+//  * A window stage and no temporal stage: the LDS tile kernel, the tile of
+//    best data utilisation (Eq. 3) that fits the budget.
+//  * A window stage and a temporal stage: the frame-marching tile kernel.  Its
+//    on-chip footprint does not grow with the frame run (each stencil keeps
+//    only its rt + 1 input frames), so the frame run is set by how many work
+//    items fill the device instead: Eq. 6 with beta = W H T / G_FILL_ITEMS
+//    output pixels per item gives t; then the tile of best Eq. 3 utilisation
+//    for that t, discounted by the idle share of the device when the tile
+//    leaves fewer work items than fill it.  An IIR's work items march the
+//    whole clip (t = T).
+// Cost: compulsory bytes (input once, output once, the temporal halo re-read
+// once per frame run), times G_FILL_ITEMS / items when a marching group has
+// fewer work items than fill the device (its frames are a sequential chain
+// per item, so the idle share of the device is lost time).  A group whose
+// stencil weights exceed the kernel-argument store, or that asks for a frame
+// run an IIR cannot keep, is not allowed.
+Segment price_generic(const fz_plan& p, int a, int b, int req_w, int req_h, int req_tpb, int req_engine)
+{
     Segment s{};
     s.first = s.cfirst = a;
     s.last = s.clast = b;
@@ -143,25 +177,41 @@ Segment price_generic(const fz_plan& p, int a, int b, int req_w, int req_h, int 
     s.tile = -1;
     for (int j = a + 1; j <= b; ++j)
         if (p.stages[j].dep == FZ_DEP_KK) return s;
-    int hx = 0, hy = 0, nwin = 0;
-    for (int j = a; j <= b; ++j)
-        if (p.stages[j].op != FZ_OP_POINT) {
-            hx += p.stages[j].rx;
-            hy += p.stages[j].ry;
+    GStage st[G_MAX_STAGES];
+    const int n = b - a + 1;
+    if (g_stage_list(p.stages.data(), a, b, st) > G_MAX_WEIGHTS) return s;
+    int hx = 0, hy = 0, nwin = 0, ht = 0;
+    bool iir = false;
+    const bool temporal = g_temporal(st, n, &iir, &ht);
+    for (int j = 0; j < n; ++j)
+        if (g_is_window(st[j].kind)) {
+            hx += st[j].rx;
+            hy += st[j].ry;
             ++nwin;
         }
     s.halo = hx;
     s.halo_y = hy;
-    s.halo_t = 0;
+    s.halo_t = ht;
     s.tpb = 1;
     s.streaming = nwin == 0;
+    if (iir && req_tpb > 0 && req_tpb < p.T) {
+        s.refused = 2;  // an IIR needs every earlier frame: its work items march the whole clip
+        return s;
+    }
+    const double P = (double)p.W * p.H;
+    double items = 0.0;
     if (s.streaming) {
         s.engine = FZ_ENGINE_STREAM;
-    } else {
-        s.engine = FZ_ENGINE_TILE;
+        if (iir) {
+            s.tpb = p.T;
+            items = ceil(P / (4.0 * BLOCK_THREADS));
+        }
+    } else if (req_engine == FZ_ENGINE_JIT && !temporal) {
+        // a generated kernel: the tile of best data utilisation among the generated tiles
+        s.engine = FZ_ENGINE_JIT;
         double best_du = -1.0;
-        for (int t = 0; t < N_TILES; ++t) {
-            const int tw = tile_w(t), th = tile_h(t);
+        for (int t = 0; t < N_JIT_TILES; ++t) {
+            const int tw = JIT_TILES[t][0], th = JIT_TILES[t][1];
             if (req_w > 0 && (tw != req_w || th != req_h)) continue;
             const int lds = generic_lds_bytes(tw, th, hx, hy, nwin);
             if (lds > p.lds_budget) continue;
@@ -175,9 +225,53 @@ Segment price_generic(const fz_plan& p, int a, int b, int req_w, int req_h, int 
             }
         }
         if (s.tile < 0) return s;
+    } else {
+        s.engine = FZ_ENGINE_TILE;
+        int tt = 1;
+        if (iir) {
+            tt = p.T;
+        } else if (temporal) {
+            if (req_tpb > 0) {
+                tt = std::min(req_tpb, p.T);
+            } else {
+                double x, t;
+                eq6_box(P * p.T / G_FILL_ITEMS, 0.5 * (hx + hy), ht, &x, &t);
+                tt = (int)std::min<double>(std::max(1.0, std::floor(t + 0.5)), p.T);
+            }
+        }
+        double best_du = -1.0;
+        for (int t = 0; t < N_TILES; ++t) {
+            const int tw = tile_w(t), th = tile_h(t);
+            if (req_w > 0 && (tw != req_w || th != req_h)) continue;
+            const int cells = (tw + 2 * hx) * (th + 2 * hy);
+            const int lds = temporal ? (march_layout(st, n, cells) + GEN_PAD) * 4
+                                     : generic_lds_bytes(tw, th, hx, hy, nwin);
+            if (lds > p.lds_budget) continue;
+            double du = (double)tw * th / ((double)(tw + 2 * hx) * (th + 2 * hy));
+            if (temporal) {
+                du *= (double)tt / (tt + (iir ? 0 : ht));
+                // under-filled marching groups lose the idle share of the device
+                const double it = ceil((double)p.W / tw) * ceil((double)p.H / th) * ceil((double)p.T / tt);
+                if (it < G_FILL_ITEMS) du *= it / G_FILL_ITEMS;
+            }
+            if (du > best_du) {
+                best_du = du;
+                s.tile = t;
+                s.tile_w = tw;
+                s.tile_h = th;
+                s.lds_bytes = lds;
+            }
+        }
+        if (s.tile < 0) return s;
+        if (temporal) {
+            s.tpb = tt;
+            items = ceil((double)p.W / s.tile_w) * ceil((double)p.H / s.tile_h) * ceil((double)p.T / tt);
+        }
     }
-    s.bytes_per_px = dt_bytes(p.stages[a].in_dtype) + 4.0;
-    s.cost = s.bytes_per_px * (double)p.W * p.H * p.T;
+    const double bin = dt_bytes(p.stages[a].in_dtype);
+    s.bytes_per_px = bin + 4.0 + (ht > 0 && !s.streaming ? bin * ht / s.tpb : 0.0);
+    s.cost = s.bytes_per_px * P * p.T;
+    if (temporal && items > 0.0 && items < G_FILL_ITEMS) s.cost *= G_FILL_ITEMS / items;
     return s;
 }
 
@@ -266,11 +360,21 @@ static fz_status validate_generic(const fz_stage* stages, int n)
     for (int i = 0; i < n; ++i) {
         const fz_stage& s = stages[i];
         const std::string where = "stage " + std::to_string(i) + ": ";
-        if (s.in_ch != 1 || s.out_ch != 1 || s.out_dtype != FZ_F32 || s.rt != 0)
-            return fail(FZ_E_INVALID, where + "generic stages have one channel, f32 output and no frame window");
+        if (s.in_ch != 1 || s.out_ch != 1 || s.out_dtype != FZ_F32)
+            return fail(FZ_E_INVALID, where + "generic stages have one channel and f32 output");
         if (!(s.in_dtype == FZ_F32 || (i == 0 && s.in_dtype == FZ_U8)))
             return fail(FZ_E_INVALID, where + "input must be f32 (u8 allowed for the first stage)");
         if (s.dep < FZ_DEP_TT || s.dep > FZ_DEP_KK) return fail(FZ_E_INVALID, where + "bad dependence type");
+        if (s.op == FZ_OP_IIR) {
+            if (s.rx != 0 || s.ry != 0 || s.rt != -1)
+                return fail(FZ_E_INVALID, where + "an IIR stage has radius 0 and reads every earlier frame (rt = -1)");
+            if (!(s.param[0] > 0.0f && s.param[0] <= 1.0f))
+                return fail(FZ_E_INVALID, where + "the IIR coefficient a must lie in (0, 1]");
+            continue;
+        }
+        if (s.rt != 0 && !(s.op == FZ_OP_STENCIL && s.rt > 0 && s.rt <= G_MAX_RT))
+            return fail(FZ_E_INVALID, where + "only a stencil may look back, at most " + std::to_string(G_MAX_RT) +
+                                          " frames");
         if (s.op == FZ_OP_POINT) {
             const float k = s.param[0];
             if (s.rx != 0 || s.ry != 0) return fail(FZ_E_INVALID, where + "a point stage has radius 0");
@@ -288,7 +392,7 @@ static fz_status validate_generic(const fz_stage* stages, int n)
             return fail(FZ_E_INVALID, where + "a window stage cannot have a thread-to-thread dependence");
         if (s.op == FZ_OP_STENCIL) {
             if (!s.weights) return fail(FZ_E_INVALID, where + "stencil without weights");
-            for (int q = 0; q < (2 * s.rx + 1) * (2 * s.ry + 1); ++q)
+            for (int q = 0; q < (2 * s.rx + 1) * (2 * s.ry + 1) * (s.rt + 1); ++q)
                 if (!std::isfinite(s.weights[q])) return fail(FZ_E_INVALID, where + "stencil weights must be finite");
         }
     }
@@ -323,10 +427,21 @@ fz_status fz_stage_describe(int32_t op, fz_stage* out)
     if (op == FZ_OP_HARRIS) out->param[0] = 0.04f;
     if (op == FZ_OP_THRESHOLD) out->param[0] = 1.0e8f;
     if (op == FZ_OP_STENCIL || op == FZ_OP_BOX) out->rx = out->ry = 1;
+    if (op == FZ_OP_IIR) out->param[0] = 0.5f;
     if (op == FZ_OP_POINT) {
         out->param[0] = (float)FZ_POINT_AFFINE;
         out->param[1] = 1.0f;
     }
+    return FZ_OK;
+}
+
+fz_status fz_box_eq6(double beta, double dx, double dt, double* x, double* t)
+{
+    if (!x || !t) return fail(FZ_E_INVALID, "fz_box_eq6: null output");
+    if (!(beta > 0.0) || !(dx >= 0.0) || !(dt >= 0.0) || !std::isfinite(beta) || !std::isfinite(dx) ||
+        !std::isfinite(dt))
+        return fail(FZ_E_INVALID, "fz_box_eq6: beta must be positive and the halos non-negative");
+    eq6_box(beta, dx, dt, x, t);
     return FZ_OK;
 }
 
@@ -357,7 +472,7 @@ fz_status fz_plan_chain(const fz_stage* stages, int32_t n, const fz_plan_opts* o
         return fail(FZ_E_INVALID, "fz_plan_chain: the learned cost model needs weights for " +
                                       std::to_string(COST_FEATURES) + " features");
     if (opts->frames_per_block < 0) return fail(FZ_E_INVALID, "fz_plan_chain: negative frames_per_block");
-    if (opts->engine < FZ_ENGINE_AUTO || opts->engine > FZ_ENGINE_ROW)
+    if (opts->engine < FZ_ENGINE_AUTO || opts->engine > FZ_ENGINE_JIT || opts->engine == FZ_ENGINE_STREAM)
         return fail(FZ_E_INVALID, "fz_plan_chain: unknown engine");
     if (opts->tile_w > 0 && opts->tile_h <= 0)
         return fail(FZ_E_INVALID, "fz_plan_chain: a tile width needs a tile height");
@@ -368,9 +483,17 @@ fz_status fz_plan_chain(const fz_stage* stages, int32_t n, const fz_plan_opts* o
     if (n_generic > 0 && n_generic < n)
         return fail(FZ_E_UNSUPPORTED, "fz_plan_chain: generic stages cannot be mixed with the fixed operations");
     const bool generic = n_generic == n;
+    if (opts->engine == FZ_ENGINE_JIT && !generic)
+        return fail(FZ_E_UNSUPPORTED, "fz_plan_chain: generated kernels are made for generic stages only");
     if (generic) {
         fz_status st = validate_generic(stages, n);
         if (st != FZ_OK) return st;
+        if (opts->cost_model == FZ_COST_LEARNED)
+            for (int i = 0; i < n; ++i)
+                if (stages[i].op == FZ_OP_IIR || stages[i].rt > 0)
+                    return fail(FZ_E_UNSUPPORTED, "fz_plan_chain: the cost network was not trained on temporal "
+                                                  "stages (IIR, stencils that look back); use analytic or measured "
+                                                  "prices");
     }
     // validate the descriptors against the operation registry (Sec. IV access patterns)
     for (int i = 0; i < n && !generic; ++i) {
@@ -411,7 +534,8 @@ fz_status fz_plan_chain(const fz_stage* stages, int32_t n, const fz_plan_opts* o
             p->gwoff[i] = (int)p->gweights.size();
             if (stages[i].op == FZ_OP_STENCIL)
                 p->gweights.insert(p->gweights.end(), stages[i].weights,
-                                   stages[i].weights + (2 * stages[i].rx + 1) * (2 * stages[i].ry + 1));
+                                   stages[i].weights +
+                                       (2 * stages[i].rx + 1) * (2 * stages[i].ry + 1) * (stages[i].rt + 1));
         }
     }
     for (fz_stage& st : p->stages) st.weights = nullptr;
@@ -447,6 +571,12 @@ fz_status fz_plan_chain(const fz_stage* stages, int32_t n, const fz_plan_opts* o
     for (int a = 0; a < n; ++a)
         for (int b = a; b < n; ++b) {
             const Segment s = price_group(*p, a, b, opts->tile_w, opts->tile_h, opts->frames_per_block, opts->engine);
+            if (s.refused == 2) {
+                delete p;
+                return fail(FZ_E_UNSUPPORTED, "requested frame run of " + std::to_string(opts->frames_per_block) +
+                                                  " frames: group " + std::to_string(a) + ".." + std::to_string(b) +
+                                                  " holds an IIR, whose work items march every frame of the clip");
+            }
             if (s.refused) {
                 delete p;
                 return fail(FZ_E_UNSUPPORTED, "requested band of " + std::to_string(opts->tile_h) +
@@ -520,6 +650,14 @@ fz_status fz_plan_chain(const fz_stage* stages, int32_t n, const fz_plan_opts* o
         a = last + 1;
     }
     p->total = total;
+    for (const Segment& g : p->segs)
+        if (g.engine == FZ_ENGINE_JIT) {
+            const fz_status st = jit_prepare(*p, g);
+            if (st != FZ_OK) {
+                delete p;
+                return st;
+            }
+        }
     p->req_w = opts->tile_w;
     p->req_h = opts->tile_h;
     p->req_tpb = opts->frames_per_block;
@@ -565,8 +703,29 @@ fz_status fz_plan_set_segment_config(fz_plan* plan, int32_t i, int32_t engine, i
 {
     if (!plan) return fail(FZ_E_INVALID, "fz_plan_set_segment_config: null plan");
     if (i < 0 || i >= (int32_t)plan->segs.size()) return fail(FZ_E_INVALID, "fz_plan_set_segment_config: bad index");
-    if (engine < FZ_ENGINE_AUTO || engine > FZ_ENGINE_ROW || tile_w < 0 || tile_h < 0 || frames_per_block < 0)
+    if (engine < FZ_ENGINE_AUTO || engine > FZ_ENGINE_JIT || engine == FZ_ENGINE_STREAM || tile_w < 0 || tile_h < 0 ||
+        frames_per_block < 0)
         return fail(FZ_E_INVALID, "fz_plan_set_segment_config: bad configuration");
+    if (engine == FZ_ENGINE_JIT) {
+        if (!plan->generic)
+            return fail(FZ_E_UNSUPPORTED, "fz_plan_set_segment_config: generated kernels are for generic stages only");
+        if (tile_w > 0) {
+            bool ok = false;
+            for (int t = 0; t < N_JIT_TILES; ++t) ok |= JIT_TILES[t][0] == tile_w && JIT_TILES[t][1] == tile_h;
+            if (!ok) return fail(FZ_E_UNSUPPORTED, "fz_plan_set_segment_config: not a generated-kernel tile");
+        }
+        const Segment& o = plan->segs[i];
+        Segment s = price_group(*plan, o.first, o.last, tile_w, tile_h, 0, FZ_ENGINE_JIT);
+        if (!(s.cost < kInf)) return fail(FZ_E_LDS, "fz_plan_set_segment_config: configuration does not fit the budget");
+        if (s.engine != FZ_ENGINE_JIT)
+            return fail(FZ_E_UNSUPPORTED, "fz_plan_set_segment_config: no generated kernel for this group");
+        const fz_status st = jit_prepare(*plan, s);
+        if (st != FZ_OK) return st;
+        plan->total += s.cost - o.cost;
+        plan->segs[i] = s;
+        release_batch(*plan);
+        return FZ_OK;
+    }
     if (engine == FZ_ENGINE_TILE && tile_w > 0 && tile_h <= 0)
         return fail(FZ_E_INVALID, "fz_plan_set_segment_config: a tile width needs a tile height");
     if (engine == FZ_ENGINE_TILE && tile_w > 0) {
@@ -577,6 +736,9 @@ fz_status fz_plan_set_segment_config(fz_plan* plan, int32_t i, int32_t engine, i
     const Segment& old = plan->segs[i];
     Segment s = price_group(*plan, old.first, old.last, engine == FZ_ENGINE_TILE ? tile_w : 0, tile_h,
                             frames_per_block, engine);
+    if (s.refused == 2)
+        return fail(FZ_E_UNSUPPORTED, "fz_plan_set_segment_config: the group holds an IIR, whose work items march "
+                                      "every frame of the clip (frames_per_block must be 0 or the clip length)");
     if (s.refused)
         return fail(FZ_E_UNSUPPORTED, "fz_plan_set_segment_config: a band of " + std::to_string(tile_h) +
                                           " rows is over the " + std::to_string(ROW_DIFF_MAX_BAND) +

@@ -1,0 +1,480 @@
+// Kalman tracking of the extracted feature points: the stage after the chain.
+//
+// The paper's pipeline ends by applying a Kalman filter to the feature points
+// (Sec. III; Table II: a single-point, multi-frame operation); Table IV marks
+// it kernel-to-kernel dependent, so it is never fused with the kernels before
+// it and runs here as its own launches on the chain's point list.  The model
+// (the paper gives none) is the discrete Kalman filter with a constant-
+// velocity state s = (x, y, vx, vy):
+//   F = [[1,0,1,0],[0,1,0,1],[0,0,1,0],[0,0,0,1]],
+//   Q = q [[1/4,0,1/2,0],[0,1/4,0,1/2],[1/2,0,1,0],[0,1/2,0,1]],
+//   H = [[1,0,0,0],[0,1,0,0]], R = r I,
+// with greedy nearest-neighbour association by Mahalanobis distance d2 =
+// nu^T S^-1 nu (candidates d2 <= gate, taken in increasing (d2, track id,
+// point index) order), a track dropped after more than max_miss missed frames
+// in a row, and a new track, s = (x, y, 0, 0), P = diag(r, r, v0, v0), for
+// every point left over (ids in (y, x) order).  All arithmetic is double
+// precision, every matrix product the plain sum over k = 0, 1, ... from 0.0,
+// evaluated without contraction: the association is a discrete decision, and
+// this makes it (and every state) reproducible to the bit.
+//
+// Launches: the points are bucketed by frame (a histogram, one scan, a
+// scatter into the workspace), then one wavefront marches the frames in
+// order: it sorts the frame's points by (y, x) (rank by counting), predicts
+// every live track, lists the gated candidate pairs, sorts them (rank by
+// counting), lets one lane take them greedily, updates the tracks, appends the
+// new ones and writes one record per live track.  Tracks live in the
+// workspace in two buffers (ping-pong on compaction), kept in id order.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <string>
+
+#include "fz_internal.h"
+
+namespace fz {
+
+constexpr int TRK_THREADS = 64;       // one wavefront marches the frames
+constexpr int TRK_MAX_POINTS = 1024;  // points of one frame
+constexpr int TRK_MAX_CANDS = 2048;   // gated (track, point) pairs of one frame
+
+struct DevTrack {
+    int32_t id, miss;
+    int32_t status, pad;  // 0 predicted only, 1 updated, 2 started (this frame)
+    double s[4];
+    double P[16];
+    double Si[4];  // S^-1 of the current frame's prediction
+};
+
+struct TrkState {  // workspace header
+    uint32_t n_tracks, next_id, cur;
+    uint32_t pad;
+};
+
+// C = A (n x m) B (m x p), row-major, plain sums from 0.0 in k order
+template <int N, int M, int P>
+__device__ __forceinline__ void mm(const double* A, const double* B, double* C)
+{
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+#pragma unroll
+        for (int j = 0; j < P; ++j) {
+            double acc = 0.0;
+#pragma unroll
+            for (int k = 0; k < M; ++k) acc = acc + A[i * M + k] * B[k * P + j];
+            C[i * P + j] = acc;
+        }
+}
+
+struct KModel {
+    double F[16], Ft[16], Q[16], H[8], Ht[8];
+    double r;
+    __device__ KModel(double q, double rr) : r(rr)
+    {
+        const double f[16] = {1, 0, 1, 0, 0, 1, 0, 1, 0, 0, 1, 0, 0, 0, 0, 1};
+        const double qq[16] = {0.25 * q, 0, 0.5 * q, 0, 0, 0.25 * q, 0, 0.5 * q,
+                               0.5 * q,  0, q,       0, 0, 0.5 * q,  0, q};
+        const double h[8] = {1, 0, 0, 0, 0, 1, 0, 0};
+        for (int i = 0; i < 16; ++i) {
+            F[i] = f[i];
+            Q[i] = qq[i];
+        }
+        for (int i = 0; i < 4; ++i)
+            for (int j = 0; j < 4; ++j) Ft[j * 4 + i] = f[i * 4 + j];
+        for (int i = 0; i < 8; ++i) H[i] = h[i];
+        for (int i = 0; i < 2; ++i)
+            for (int j = 0; j < 4; ++j) Ht[j * 2 + i] = h[i * 4 + j];
+    }
+};
+
+__global__ void k_trk_zero(uint32_t* counts, int n, TrkState* st, uint32_t* track_count)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) counts[i] = 0u;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        st->n_tracks = 0u;
+        st->next_id = 0u;
+        st->cur = 0u;
+        track_count[0] = 0u;
+        track_count[1] = 0u;
+    }
+}
+
+// per-frame point counts (points outside 0..T-1 are ignored)
+__global__ void k_trk_hist(const fz_point* pts, const uint32_t* count, uint32_t cap, int T, uint32_t* counts)
+{
+    const uint32_t n = min(*count, cap);
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const uint32_t t = pts[i].t;
+        if (t < (uint32_t)T) atomicAdd(&counts[t], 1u);
+    }
+}
+
+// exclusive scan of counts[0..T) into offs[0..T] and cursor[0..T), one workgroup
+__global__ void k_trk_scan(const uint32_t* counts, int T, uint32_t* offs, uint32_t* cursor)
+{
+    __shared__ uint32_t part[256];
+    __shared__ uint32_t base;
+    if (threadIdx.x == 0) base = 0u;
+    __syncthreads();
+    for (int c0 = 0; c0 < T; c0 += 256) {
+        const int i = c0 + threadIdx.x;
+        const uint32_t v = i < T ? counts[i] : 0u;
+        part[threadIdx.x] = v;
+        __syncthreads();
+        for (int d = 1; d < 256; d <<= 1) {  // inclusive Hillis-Steele scan
+            const uint32_t a = threadIdx.x >= (unsigned)d ? part[threadIdx.x - d] : 0u;
+            __syncthreads();
+            part[threadIdx.x] += a;
+            __syncthreads();
+        }
+        if (i < T) {
+            offs[i] = base + part[threadIdx.x] - v;
+            cursor[i] = offs[i];
+        }
+        __syncthreads();
+        if (threadIdx.x == 255) base += part[255];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) offs[T] = base;
+}
+
+__global__ void k_trk_scatter(const fz_point* pts, const uint32_t* count, uint32_t cap, int T, uint32_t* cursor,
+                              int2* bucket)
+{
+    const uint32_t n = min(*count, cap);
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const fz_point p = pts[i];
+        if (p.t >= (uint32_t)T) continue;
+        const uint32_t slot = atomicAdd(&cursor[p.t], 1u);
+        bucket[slot] = make_int2((int)p.x, (int)p.y);
+    }
+}
+
+struct Cand {
+    double d2;
+    int32_t id;
+    int16_t ti, pj;
+};
+
+__device__ __forceinline__ bool cand_less(const Cand& a, const Cand& b)
+{
+    if (a.d2 != b.d2) return a.d2 < b.d2;
+    if (a.id != b.id) return a.id < b.id;
+    return a.pj < b.pj;
+}
+
+__device__ __forceinline__ void put_record(fz_track* out, uint32_t* count, uint32_t cap, int t, const DevTrack& tr,
+                                           int status)
+{
+    const uint32_t k = atomicAdd(&count[0], 1u);
+    if (k < cap) {
+        fz_track r;
+        r.t = (uint32_t)t;
+        r.id = (uint32_t)tr.id;
+        r.status = status;
+        r.pad = 0;
+        r.x = tr.s[0];
+        r.y = tr.s[1];
+        r.vx = tr.s[2];
+        r.vy = tr.s[3];
+        out[k] = r;
+    }
+}
+
+__global__ __launch_bounds__(TRK_THREADS) void k_trk_run(const int2* bucket, const uint32_t* offs, int T,
+                                                          fz_track_opts o, DevTrack* buf0, DevTrack* buf1,
+                                                          uint32_t max_tracks, fz_track* out, uint32_t* count,
+                                                          uint32_t cap)
+{
+    __shared__ int2 pin[TRK_MAX_POINTS];   // the frame's points as loaded
+    __shared__ int2 pts[TRK_MAX_POINTS];   // sorted by (y, x)
+    __shared__ Cand cand[TRK_MAX_CANDS];
+    __shared__ int16_t order[TRK_MAX_CANDS];  // order[rank] = candidate index
+    __shared__ uint8_t ptaken[TRK_MAX_POINTS];
+    __shared__ int16_t tmatch[FZ_TRACK_MAX_TRACKS];  // point matched to each track, -1 none
+    __shared__ uint32_t s_nc, s_flags, s_alive, s_new;
+    const int lane = threadIdx.x;
+    const KModel M(o.q, o.r);
+    DevTrack* cur = buf0;
+    DevTrack* nxt = buf1;
+    uint32_t ntr = 0, next_id = 0;
+    if (lane == 0) s_flags = 0u;
+    if (max_tracks > (uint32_t)FZ_TRACK_MAX_TRACKS) max_tracks = FZ_TRACK_MAX_TRACKS;
+
+    for (int t = 0; t < T; ++t) {
+        uint32_t np = offs[t + 1] - offs[t];
+        if (np > (uint32_t)TRK_MAX_POINTS) {
+            if (lane == 0) s_flags |= FZ_TRACK_TOO_MANY_POINTS;
+            np = TRK_MAX_POINTS;
+        }
+        // 1. the frame's points, sorted by (y, x) (keys are distinct)
+        for (uint32_t j = lane; j < np; j += TRK_THREADS) {
+            pin[j] = bucket[offs[t] + j];
+            ptaken[j] = 0;
+        }
+        if (lane == 0) s_nc = 0u;
+        __syncthreads();
+        for (uint32_t j = lane; j < np; j += TRK_THREADS) {
+            const int2 a = pin[j];
+            uint32_t rank = 0;
+            for (uint32_t k = 0; k < np; ++k) {
+                const int2 b = pin[k];
+                rank += (b.y < a.y || (b.y == a.y && b.x < a.x)) ? 1u : 0u;
+            }
+            pts[rank] = a;
+        }
+        // 2. predict every live track
+        for (uint32_t i = lane; i < ntr; i += TRK_THREADS) {
+            DevTrack& tr = cur[i];
+            double sp[4], FP[16], Pp[16], HP[8], S[4];
+            mm<4, 4, 1>(M.F, tr.s, sp);
+            mm<4, 4, 4>(M.F, tr.P, FP);
+            mm<4, 4, 4>(FP, M.Ft, Pp);
+            for (int e = 0; e < 16; ++e) Pp[e] = Pp[e] + M.Q[e];
+            mm<2, 4, 4>(M.H, Pp, HP);
+            mm<2, 4, 2>(HP, M.Ht, S);
+            S[0] = S[0] + M.r;
+            S[3] = S[3] + M.r;
+            const double det = S[0] * S[3] - S[1] * S[2];
+            for (int e = 0; e < 4; ++e) tr.s[e] = sp[e];
+            for (int e = 0; e < 16; ++e) tr.P[e] = Pp[e];
+            tr.Si[0] = S[3] / det;
+            tr.Si[1] = -S[1] / det;
+            tr.Si[2] = -S[2] / det;
+            tr.Si[3] = S[0] / det;
+        }
+        __syncthreads();
+        // 3. gated candidate pairs
+        const uint32_t pairs = ntr * np;
+        for (uint32_t e = lane; e < pairs; e += TRK_THREADS) {
+            const uint32_t i = e / np, j = e - i * np;
+            const DevTrack& tr = cur[i];
+            double hs[2], nu[2];
+            mm<2, 4, 1>(M.H, tr.s, hs);
+            nu[0] = (double)pts[j].x - hs[0];
+            nu[1] = (double)pts[j].y - hs[1];
+            double d2 = 0.0;
+            for (int a = 0; a < 2; ++a)
+                for (int b = 0; b < 2; ++b) d2 = d2 + nu[a] * tr.Si[2 * a + b] * nu[b];
+            if (d2 <= o.gate) {
+                const uint32_t k = atomicAdd(&s_nc, 1u);
+                if (k < (uint32_t)TRK_MAX_CANDS) {
+                    Cand c;
+                    c.d2 = d2;
+                    c.id = tr.id;
+                    c.ti = (int16_t)i;
+                    c.pj = (int16_t)j;
+                    cand[k] = c;
+                } else {
+                    atomicOr(&s_flags, (uint32_t)FZ_TRACK_TOO_MANY_CANDIDATES);
+                }
+            }
+        }
+        __syncthreads();
+        const uint32_t nc = min(s_nc, (uint32_t)TRK_MAX_CANDS);
+        // 4. candidates in increasing (d2, id, point) order
+        for (uint32_t c = lane; c < nc; c += TRK_THREADS) {
+            const Cand a = cand[c];
+            uint32_t rank = 0;
+            for (uint32_t k = 0; k < nc; ++k) rank += cand_less(cand[k], a) ? 1u : 0u;
+            order[rank] = (int16_t)c;
+        }
+        for (uint32_t i = lane; i < ntr; i += TRK_THREADS) tmatch[i] = -1;
+        __syncthreads();
+        // 5. greedy association by one lane
+        if (lane == 0) {
+            for (uint32_t k = 0; k < nc; ++k) {
+                const Cand c = cand[order[k]];
+                if (tmatch[c.ti] < 0 && !ptaken[c.pj]) {
+                    tmatch[c.ti] = c.pj;
+                    ptaken[c.pj] = 1;
+                }
+            }
+        }
+        __syncthreads();
+        // 6. update or count a miss
+        for (uint32_t i = lane; i < ntr; i += TRK_THREADS) {
+            DevTrack& tr = cur[i];
+            const int j = tmatch[i];
+            if (j >= 0) {
+                double hs[2], nu[2], PHt[8], K[8], Knu[4], KH[16], IKH[16], Pn[16];
+                mm<2, 4, 1>(M.H, tr.s, hs);
+                nu[0] = (double)pts[j].x - hs[0];
+                nu[1] = (double)pts[j].y - hs[1];
+                mm<4, 4, 2>(tr.P, M.Ht, PHt);
+                mm<4, 2, 2>(PHt, tr.Si, K);
+                mm<4, 2, 1>(K, nu, Knu);
+                for (int e = 0; e < 4; ++e) tr.s[e] = tr.s[e] + Knu[e];
+                mm<4, 2, 4>(K, M.H, KH);
+                for (int a = 0; a < 4; ++a)
+                    for (int b = 0; b < 4; ++b) IKH[4 * a + b] = (a == b ? 1.0 : 0.0) - KH[4 * a + b];
+                mm<4, 4, 4>(IKH, tr.P, Pn);
+                for (int e = 0; e < 16; ++e) tr.P[e] = Pn[e];
+                tr.miss = 0;
+                tr.status = 1;
+            } else {
+                tr.miss += 1;
+                tr.status = 0;
+            }
+        }
+        __syncthreads();
+        // 7. compaction in id order, then the new tracks (ids in point order)
+        if (lane == 0) {
+            s_alive = 0u;
+            s_new = 0u;
+        }
+        __syncthreads();
+        for (uint32_t c0 = 0; c0 < ntr; c0 += TRK_THREADS) {
+            const uint32_t i = c0 + lane;
+            const bool alive = i < ntr && cur[i].miss <= o.max_miss;
+            const uint64_t m = __ballot(alive);
+            const uint32_t before = __popcll(m & ((1ull << lane) - 1ull));
+            const uint32_t base = s_alive;
+            if (alive) {
+                const DevTrack tr = cur[i];
+                nxt[base + before] = tr;
+                put_record(out, count, cap, t, tr, tr.status);
+            }
+            __syncthreads();
+            if (lane == 0) s_alive = base + (uint32_t)__popcll(m);
+            __syncthreads();
+        }
+        const uint32_t n_alive = s_alive;
+        for (uint32_t c0 = 0; c0 < np; c0 += TRK_THREADS) {
+            const uint32_t j = c0 + lane;
+            const bool fresh = j < np && !ptaken[j];
+            const uint64_t m = __ballot(fresh);
+            const uint32_t before = __popcll(m & ((1ull << lane) - 1ull));
+            const uint32_t base = s_new;
+            if (fresh) {
+                const uint32_t slot = n_alive + base + before;
+                if (slot < max_tracks) {
+                    DevTrack tr;
+                    tr.id = (int32_t)(next_id + base + before);
+                    tr.miss = 0;
+                    tr.status = 2;
+                    tr.pad = 0;
+                    tr.s[0] = (double)pts[j].x;
+                    tr.s[1] = (double)pts[j].y;
+                    tr.s[2] = 0.0;
+                    tr.s[3] = 0.0;
+                    for (int e = 0; e < 16; ++e) tr.P[e] = 0.0;
+                    tr.P[0] = o.r;
+                    tr.P[5] = o.r;
+                    tr.P[10] = o.v0;
+                    tr.P[15] = o.v0;
+                    for (int e = 0; e < 4; ++e) tr.Si[e] = 0.0;
+                    nxt[slot] = tr;
+                    put_record(out, count, cap, t, tr, 2);
+                } else {
+                    atomicOr(&s_flags, (uint32_t)FZ_TRACK_TOO_MANY_TRACKS);
+                }
+            }
+            __syncthreads();
+            if (lane == 0) s_new = base + (uint32_t)__popcll(m);
+            __syncthreads();
+        }
+        next_id += s_new;
+        ntr = min(n_alive + s_new, max_tracks);
+        DevTrack* sw = cur;
+        cur = nxt;
+        nxt = sw;
+        __syncthreads();
+    }
+    if (lane == 0) atomicOr(&count[1], s_flags);
+}
+
+static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+size_t track_workspace_bytes(int T, uint32_t point_capacity, uint32_t max_tracks)
+{
+    return align256(sizeof(TrkState)) + 3 * align256(sizeof(uint32_t) * ((size_t)T + 1)) +
+           align256(sizeof(int2) * (size_t)point_capacity) + 2 * align256(sizeof(DevTrack) * (size_t)max_tracks);
+}
+
+fz_status track_points(const fz_point* d_points, const uint32_t* d_count, uint32_t cap, int T, const fz_track_opts& o,
+                       fz_track* d_tracks, uint32_t* d_track_count, uint32_t track_cap, void* ws, void* stream)
+{
+    (void)hipGetLastError();
+    hipStream_t s = (hipStream_t)stream;
+    char* w = (char*)ws;
+    TrkState* st = (TrkState*)w;
+    w += align256(sizeof(TrkState));
+    uint32_t* counts = (uint32_t*)w;
+    w += align256(sizeof(uint32_t) * ((size_t)T + 1));
+    uint32_t* offs = (uint32_t*)w;
+    w += align256(sizeof(uint32_t) * ((size_t)T + 1));
+    uint32_t* cursor = (uint32_t*)w;
+    w += align256(sizeof(uint32_t) * ((size_t)T + 1));
+    int2* bucket = (int2*)w;
+    w += align256(sizeof(int2) * (size_t)cap);
+    DevTrack* b0 = (DevTrack*)w;
+    w += align256(sizeof(DevTrack) * (size_t)o.max_tracks);
+    DevTrack* b1 = (DevTrack*)w;
+    const unsigned gz = (unsigned)std::min<size_t>(((size_t)T + 256) / 256, 1024);
+    hipLaunchKernelGGL(k_trk_zero, dim3(gz), dim3(256), 0, s, counts, T + 1, st, d_track_count);
+    const unsigned gp = (unsigned)std::max<size_t>(1, std::min<size_t>(((size_t)cap + 255) / 256, 1024));
+    if (cap > 0) hipLaunchKernelGGL(k_trk_hist, dim3(gp), dim3(256), 0, s, d_points, d_count, cap, T, counts);
+    hipLaunchKernelGGL(k_trk_scan, dim3(1), dim3(256), 0, s, counts, T, offs, cursor);
+    if (cap > 0)
+        hipLaunchKernelGGL(k_trk_scatter, dim3(gp), dim3(256), 0, s, d_points, d_count, cap, T, cursor, bucket);
+    hipLaunchKernelGGL(k_trk_run, dim3(1), dim3(TRK_THREADS), 0, s, bucket, offs, T, o, b0, b1,
+                       (uint32_t)o.max_tracks, d_tracks, d_track_count, track_cap);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(FZ_E_HIP, std::string("fz_track_points: launch: ") + hipGetErrorString(e));
+    return FZ_OK;
+}
+
+}  // namespace fz
+
+using namespace fz;
+
+extern "C" {
+
+fz_status fz_track_default_opts(fz_track_opts* out)
+{
+    if (!out) return fail(FZ_E_INVALID, "fz_track_default_opts: null output");
+    out->q = 0.5;
+    out->r = 1.0;
+    out->gate = 9.21;
+    out->v0 = 4.0;
+    out->max_miss = 3;
+    out->max_tracks = FZ_TRACK_MAX_TRACKS;
+    return FZ_OK;
+}
+
+static fz_status check_opts(const fz_track_opts* o, const char* who)
+{
+    if (!o) return fail(FZ_E_INVALID, std::string(who) + ": null options");
+    if (!(o->q >= 0.0 && o->r > 0.0 && o->gate >= 0.0 && o->v0 >= 0.0) || !std::isfinite(o->q) ||
+        !std::isfinite(o->r) || !std::isfinite(o->gate) || !std::isfinite(o->v0))
+        return fail(FZ_E_INVALID, std::string(who) + ": need q >= 0, r > 0, gate >= 0, v0 >= 0, all finite");
+    if (o->max_miss < 0 || o->max_tracks < 1 || o->max_tracks > FZ_TRACK_MAX_TRACKS)
+        return fail(FZ_E_INVALID, std::string(who) + ": need max_miss >= 0 and max_tracks in [1, 4096]");
+    return FZ_OK;
+}
+
+size_t fz_track_workspace_bytes(int32_t frames, uint32_t point_capacity, const fz_track_opts* opts)
+{
+    if (frames <= 0 || check_opts(opts, "fz_track_workspace_bytes") != FZ_OK) return 0;
+    return track_workspace_bytes(frames, point_capacity, (uint32_t)opts->max_tracks);
+}
+
+fz_status fz_track_points(const fz_point* d_points, const uint32_t* d_point_count, uint32_t point_capacity,
+                          int32_t frames, const fz_track_opts* opts, fz_track* d_tracks, uint32_t* d_track_count,
+                          uint32_t track_capacity, void* d_workspace, size_t ws_bytes, void* stream)
+{
+    const fz_status st = check_opts(opts, "fz_track_points");
+    if (st != FZ_OK) return st;
+    if (frames <= 0) return fail(FZ_E_INVALID, "fz_track_points: frames must be positive");
+    if (!d_point_count || !d_track_count || (point_capacity > 0 && !d_points) || (track_capacity > 0 && !d_tracks))
+        return fail(FZ_E_INVALID, "fz_track_points: null buffer");
+    const size_t need = track_workspace_bytes(frames, point_capacity, (uint32_t)opts->max_tracks);
+    if (!d_workspace || ws_bytes < need)
+        return fail(FZ_E_WORKSPACE, "fz_track_points: workspace needs " + std::to_string(need) + " bytes");
+    return track_points(d_points, d_point_count, point_capacity, frames, *opts, d_tracks, d_track_count,
+                        track_capacity, d_workspace, stream);
+}
+
+}  // extern "C"

@@ -14,6 +14,8 @@ import ctypes
 import math
 import os
 
+import numpy as np
+
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libfz.so")
 
@@ -22,13 +24,16 @@ FZ_U8, FZ_F32 = 1, 2
 FZ_DEP_TT, FZ_DEP_TMT, FZ_DEP_KK = 0, 1, 2
 FZ_PART_OPTIMAL, FZ_PART_UNFUSED, FZ_PART_EXPLICIT = 0, 1, 2
 FZ_COST_ANALYTIC, FZ_COST_LEARNED, FZ_COST_MEASURED = 0, 1, 2
-FZ_ENGINE_AUTO, FZ_ENGINE_TILE, FZ_ENGINE_ROW, FZ_ENGINE_STREAM = 0, 1, 2, 3
-ENGINES = {"auto": FZ_ENGINE_AUTO, "tile": FZ_ENGINE_TILE, "row": FZ_ENGINE_ROW}
+FZ_ENGINE_AUTO, FZ_ENGINE_TILE, FZ_ENGINE_ROW, FZ_ENGINE_STREAM, FZ_ENGINE_JIT = 0, 1, 2, 3, 4
+ENGINES = {"auto": FZ_ENGINE_AUTO, "tile": FZ_ENGINE_TILE, "row": FZ_ENGINE_ROW, "jit": FZ_ENGINE_JIT}
+JIT_TILES = [(16, 16), (32, 16), (32, 32), (64, 16), (64, 32)]
+FZ_TRACK_MAX_TRACKS = 4096
+FZ_TRACK_TOO_MANY_POINTS, FZ_TRACK_TOO_MANY_CANDIDATES, FZ_TRACK_TOO_MANY_TRACKS = 1, 2, 4
 
 OPS = {
     "rgb2gray": 1, "gauss5": 2, "sobel3": 3, "gradmag": 4, "products": 5,
     "boxsum5": 6, "harris": 7, "threshold": 8, "nms3": 9, "framediff": 10,
-    "stencil": 11, "box": 12, "point": 13,
+    "stencil": 11, "box": 12, "point": 13, "iir": 14,
 }
 POINT_KINDS = {"affine": 0, "abs": 1, "square": 2, "sqrtabs": 3, "clamp": 4}
 OP_NAMES = {v: k for k, v in OPS.items()}
@@ -69,6 +74,16 @@ class fz_segment_info(ctypes.Structure):
                 ("tile_h", ctypes.c_int32), ("frames_per_block", ctypes.c_int32), ("halo", ctypes.c_int32),
                 ("halo_t", ctypes.c_int32), ("lds_bytes", ctypes.c_int32), ("streaming", ctypes.c_int32),
                 ("engine", ctypes.c_int32), ("bytes_per_px", ctypes.c_double), ("cost", ctypes.c_double)]
+
+
+class fz_track_opts(ctypes.Structure):
+    _fields_ = [("q", ctypes.c_double), ("r", ctypes.c_double), ("gate", ctypes.c_double), ("v0", ctypes.c_double),
+                ("max_miss", ctypes.c_int32), ("max_tracks", ctypes.c_int32)]
+
+
+class fz_track(ctypes.Structure):
+    _fields_ = [("t", ctypes.c_uint32), ("id", ctypes.c_uint32), ("status", ctypes.c_int32), ("pad", ctypes.c_uint32),
+                ("x", ctypes.c_double), ("y", ctypes.c_double), ("vx", ctypes.c_double), ("vy", ctypes.c_double)]
 
 
 class fz_clip(ctypes.Structure):
@@ -121,6 +136,13 @@ SIGNATURES = [
     ("fz_mlp_adam_step", ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                           ctypes.c_int32, ctypes.c_int32, ctypes.c_float, ctypes.c_float,
                                           ctypes.c_float, ctypes.c_float, ctypes.c_void_p]),
+    ("fz_box_eq6", ctypes.c_int32, [ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                    ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
+    ("fz_track_default_opts", ctypes.c_int32, [ctypes.POINTER(fz_track_opts)]),
+    ("fz_track_workspace_bytes", ctypes.c_size_t, [ctypes.c_int32, ctypes.c_uint32, ctypes.POINTER(fz_track_opts)]),
+    ("fz_track_points", ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32, ctypes.c_int32,
+                                         ctypes.POINTER(fz_track_opts), ctypes.c_void_p, ctypes.c_void_p,
+                                         ctypes.c_uint32, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
     ("fz_last_error", ctypes.c_char_p, []),
     ("fz_version", ctypes.c_char_p, []),
 ]
@@ -260,6 +282,64 @@ def fz_run_chain_static(plan, d_in, d_out, d_points, d_point_count, point_capaci
     _check(lib().fz_run_chain_static(plan, d_in, d_out, d_points, d_point_count, point_capacity, stream))
 
 
+def fz_box_eq6(beta, dx, dt):
+    """Sec. VI-E, Eq. 6: (x, t) of the box x*x*t of volume beta whose input
+    box (x + 2 dx)^2 (t + dt) is least."""
+    x, t = ctypes.c_double(), ctypes.c_double()
+    _check(lib().fz_box_eq6(float(beta), float(dx), float(dt), ctypes.byref(x), ctypes.byref(t)))
+    return x.value, t.value
+
+
+def fz_track_points(d_points, d_point_count, point_capacity, frames, opts, d_tracks, d_track_count,
+                    track_capacity, d_workspace, ws_bytes, stream):
+    _check(lib().fz_track_points(d_points, d_point_count, point_capacity, int(frames), ctypes.byref(opts), d_tracks,
+                                 d_track_count, track_capacity, d_workspace, ws_bytes, stream))
+
+
+def fz_track_workspace_bytes(frames, point_capacity, opts) -> int:
+    return int(lib().fz_track_workspace_bytes(int(frames), int(point_capacity), ctypes.byref(opts)))
+
+
+def track_opts(**kw):
+    """fz_track_opts with the library's defaults, fields overridden by kw."""
+    o = fz_track_opts()
+    _check(lib().fz_track_default_opts(ctypes.byref(o)))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+def track_points(points, count, frames, opts=None, capacity=None, stream=None):
+    """Kalman tracking (fz_track_points) of a point buffer (device tensors as
+    Plan.run returns them: points (cap, 4) int32, count (>= 1) int32) over a
+    clip of `frames` frames.  Returns (records numpy structured rows (t, id,
+    status, x, y, vx, vy), flags).  Synchronises."""
+    import torch
+    o = opts or track_opts()
+    check_points(points, count, points.device if points is not None else None)
+    dev = count.device
+    cap_in = points.shape[0] if points is not None else 0
+    if capacity is None:
+        capacity = max(1024, 4 * cap_in * (o.max_miss + 2))
+    out = torch.empty((max(capacity, 1), 12), dtype=torch.int32, device=dev)  # 48-byte records
+    tc = torch.zeros((2,), dtype=torch.int32, device=dev)
+    need = int(lib().fz_track_workspace_bytes(int(frames), cap_in, ctypes.byref(o)))
+    ws = torch.empty((max(need, 1),), dtype=torch.uint8, device=dev)
+    if stream is None:
+        stream = torch.cuda.current_stream(dev).cuda_stream
+    _check(lib().fz_track_points(points.data_ptr() if points is not None else None, count.data_ptr(), cap_in,
+                                 int(frames), ctypes.byref(o), out.data_ptr(), tc.data_ptr(), capacity,
+                                 ws.data_ptr(), ws.numel(), stream))
+    torch.cuda.synchronize(dev)
+    n, flags = int(tc[0].item()), int(tc[1].item())
+    if n > capacity:
+        raise RuntimeError(f"track buffer overflow: {n} records, capacity {capacity}")
+    raw = out[:n].cpu().numpy()
+    dt = np.dtype([("t", "<u4"), ("id", "<u4"), ("status", "<i4"), ("pad", "<u4"), ("x", "<f8"), ("y", "<f8"),
+                   ("vx", "<f8"), ("vy", "<f8")])
+    return raw.view(dt).reshape(-1), flags
+
+
 def fz_batch_workspace_bytes(plan, clips) -> int:
     arr = (fz_clip * len(clips))(*clips)
     return int(lib().fz_batch_workspace_bytes(plan, arr, len(clips)))
@@ -336,8 +416,9 @@ def make_opts(W, H, T, partition="optimal", lds_budget=0, tile=None, frames_per_
 
 def generic_stages(spec, in_dtype="u8"):
     """fz_stage descriptors for a generic chain given as tuples
-    ("stencil", rx, ry, w[2ry+1][2rx+1]), ("box", rx, ry) or ("point", kind, a, b)
-    (kind a name of POINT_KINDS).  The first stage reads `in_dtype` ("u8" or
+    ("stencil", rx, ry, w[2ry+1][2rx+1]) (or w[rt+1][2ry+1][2rx+1]: a stencil
+    that also reads the rt frames before t, w[tau] on frame t - tau), ("box",
+    rx, ry), ("point", kind, a, b) (kind a name of POINT_KINDS) or ("iir", a).  The first stage reads `in_dtype` ("u8" or
     "f32").  Returns (stages, keep): `keep` holds the weight arrays the
     descriptors point to until the plan has copied them."""
     stages, keep = [], []
@@ -347,10 +428,18 @@ def generic_stages(spec, in_dtype="u8"):
             s.param[0] = float(POINT_KINDS[st[1]])
             s.param[1] = float(st[2]) if len(st) > 2 else 0.0
             s.param[2] = float(st[3]) if len(st) > 3 else 0.0
+        elif st[0] == "iir":
+            s.param[0] = float(st[1])
         else:
             s.rx, s.ry = int(st[1]), int(st[2])
             if st[0] == "stencil":
-                w = [float(v) for row in st[3] for v in row]
+                w = np.asarray(st[3], np.float64)
+                if w.ndim not in (2, 3) or w.shape[-2:] != (2 * s.ry + 1, 2 * s.rx + 1):
+                    raise ValueError(f"stage {i}: stencil weights must have shape ([rt+1,] {2 * s.ry + 1}, "
+                                     f"{2 * s.rx + 1}), got {w.shape}")
+                if w.ndim == 3:  # frames back: w[tau] multiplies frame t - tau
+                    s.rt = w.shape[0] - 1
+                w = [float(v) for v in w.ravel()]
                 arr = (ctypes.c_float * len(w))(*w)
                 keep.append(arr)
                 s.weights = ctypes.cast(arr, ctypes.POINTER(ctypes.c_float))

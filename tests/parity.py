@@ -213,10 +213,20 @@ def generic_reference(oracle_lib, spec, volume):
     for st in spec:
         Y = oracle_lib.gchain([st], X)
         A = np.abs(X) + E
-        if st[0] == "stencil":
+        if st[0] == "iir":
+            E = iir_bound(st[1], X, Y, E)
+        elif st[0] == "stencil":
             aw = np.abs(np.asarray(st[3], np.float64))
             g = _gamma(aw.size)
-            corr = lambda Z: np.stack([ndimage.correlate(z, aw, mode="nearest") for z in Z])
+            if aw.ndim == 3:  # frame window: w[tau] on frame t - tau, the first frame replicated
+                def corr(Z):
+                    out = np.zeros_like(Z)
+                    for tau in range(aw.shape[0]):
+                        src = Z[np.maximum(np.arange(Z.shape[0]) - tau, 0)]
+                        out += np.stack([ndimage.correlate(z, aw[tau], mode="nearest") for z in src])
+                    return out
+            else:
+                corr = lambda Z: np.stack([ndimage.correlate(z, aw, mode="nearest") for z in Z])
             E = corr(E) + g * corr(A)
         elif st[0] == "box":
             size = (2 * st[2] + 1, 2 * st[1] + 1)
@@ -240,6 +250,26 @@ def generic_reference(oracle_lib, spec, volume):
     return X, E
 
 
+def iir_bound(a, X, Y, E):
+    """Error bound of the IIR as the library evaluates it: the state in double
+    precision, y = fma(a, x, (1 - a) y_prev) on the f32 inputs x (bound E),
+    y[-1] := x[0], each output rounded once to f32:
+      G[t] = |a| E[t] + (1 - a) G[t-1]
+             + 2 u64 (|a| (|X[t]| + E[t]) + (1 - a) (|Y[t-1]| + G[t-1])),   G[-1] = E[0]
+      F[t] = G[t] + u32 (|Y[t]| + G[t])
+    from the exact input X and output Y ([T][H][W]); F bounds the f32 output."""
+    a = float(a)
+    b = 1.0 - a
+    u64 = 2.0 ** -53
+    F = np.zeros_like(E)
+    yprev, gprev = np.abs(X[0]), E[0].copy()
+    for t in range(X.shape[0]):
+        G = (abs(a) * E[t] + b * gprev + 2 * u64 * (abs(a) * (np.abs(X[t]) + E[t]) + b * (yprev + gprev)))
+        F[t] = G + U32 * (np.abs(Y[t]) + G)
+        yprev, gprev = np.abs(Y[t]), G
+    return F
+
+
 def assert_within_bound(gpu, ref, bound, what=""):
     """|gpu - ref| <= bound (with 1% slack for evaluating the bound itself in
     FP64), everywhere; reports the worst ratio."""
@@ -259,6 +289,8 @@ def generic_full_scale(spec, s=255.0):
     squares it, sqrt-abs takes its root, abs keeps it, clamp maps [-s, s]
     into [clamp(-s), clamp(s)]."""
     for st in spec:
+        if st[0] == "iir":
+            continue  # a convex combination of earlier inputs: the range is kept
         if st[0] == "stencil":
             s *= float(np.abs(np.asarray(st[3], np.float64)).sum())
         elif st[0] == "box":

@@ -17,7 +17,7 @@ from paper_1509_04394_amd import fz
 
 def test_library_exports_every_declared_symbol():
     header = open(fz.os.path.join(fz.os.path.dirname(fz.HERE), "include", "fz.h")).read()
-    declared = set(re.findall(r"\b(fz_[a-z_]+)\s*\(", header))
+    declared = set(re.findall(r"\b(fz_[a-z0-9_]+)\s*\(", header))
     declared -= {"fz_plan"}  # type name, not a function
     L = ctypes.CDLL(fz.LIB_PATH)
     for name in declared:
