@@ -41,6 +41,12 @@ WORKLOADS = {
                     desc="192x432x64 gray u8, Gaussian -> Sobel -> magnitude"),
     "generic800": dict(W=800, H=600, T=64, rgb=False, seed=6, chain="generic3",
                        desc="800x600x64 gray u8, plan-time generic chain: 3x3 stencil -> |x| -> 3x3 window sum"),
+    "paper5_800": dict(W=800, H=600, T=1000, rgb=False, seed=7, chain="paper5",
+                       desc="800x600x1000 gray u8, the paper's five-kernel chain with generic stages: IIR (a = 0.3) "
+                            "-> 5x5 Gaussian -> 3x3 horizontal Sobel -> |x| -> clamp [0, 200]"),
+    "spatio800": dict(W=800, H=600, T=1000, rgb=False, seed=8, chain="spatio",
+                      desc="800x600x1000 gray u8, stencils that look back: affine -> 3x3 over 3 frames -> 3x3 "
+                           "window sum -> 5x3 over 2 frames -> sqrt|x|"),
     "batch32": dict(W=800, H=600, T=1000, rgb=False, seed=4, chain="harris", clips=32,
                     desc="32 gray u8 clips, frame sizes drawn from 192x432 / 320x240 / 640x480 / 800x600, "
                          "50-1000 frames, 8-stage Harris chain, one persistent graph launch"),
@@ -86,6 +92,17 @@ def chain_ops(name):
     if name == "generic3":  # stages given at plan time (weights: the 3x3 binomial, normalised)
         w3 = (np.outer([1, 2, 1], [1, 2, 1]) / 16.0).astype(np.float32)
         return [("stencil", 1, 1, w3), ("point", "abs", 0.0, 0.0), ("box", 1, 1)]
+    if name == "paper5":  # IIR -> Gaussian -> gradient -> magnitude -> clamp (Table II's kernels K2..K5)
+        g = np.exp(-np.arange(-2, 3) ** 2 / 2.0)
+        g5 = (np.outer(g, g) / np.outer(g, g).sum()).astype(np.float32)
+        sx = np.array([[-1, 0, 1], [-2, 0, 2], [-1, 0, 1]], np.float32)
+        return [("iir", float(np.float32(0.3))), ("stencil", 2, 2, g5), ("stencil", 1, 1, sx),
+                ("point", "abs", 0.0, 0.0), ("point", "clamp", 0.0, 200.0)]
+    if name == "spatio":  # stencils over several frames (Table I, spatio-temporal)
+        w33 = (np.arange(27, dtype=np.float32).reshape(3, 3, 3) % 5 + 1.0) / 60.0
+        w253 = ((np.arange(30, dtype=np.float32).reshape(2, 3, 5) % 7) - 3.0) / 40.0
+        return [("point", "affine", 0.5, 1.0), ("stencil", 1, 1, w33), ("box", 1, 1), ("stencil", 2, 1, w253),
+                ("point", "sqrtabs", 0.0, 0.0)]
     return {"rgb_harris": fz.RGB_HARRIS_CHAIN, "harris": fz.HARRIS_CHAIN, "grad": fz.GRAD_CHAIN}[name]
 
 
@@ -98,7 +115,10 @@ def ops_per_px(ops, table=None):
     def generic(st):
         if st[0] == "point":
             return 2 if st[1] == "clamp" else 1
-        return (2 * st[1] + 1) * (2 * st[2] + 1)
+        if st[0] == "iir":
+            return 2
+        frames = np.asarray(st[3]).shape[0] if st[0] == "stencil" and np.asarray(st[3]).ndim == 3 else 1
+        return (2 * st[1] + 1) * (2 * st[2] + 1) * frames
     return sum(generic(o) if isinstance(o, tuple) else table[o] for o in ops)
 
 
@@ -233,9 +253,11 @@ def cpu_baseline(wl, ops, budget_s=15.0, one_thread_s=3.0):
     return rec
 
 
-def fused_and_unfused(ops, W, H, T, seed, rgb, steps, warmup, dev, stream):
-    """Mpixel/s of the planner's partition and of one kernel per stage on a
-    smaller workload (whole video resident in HBM)."""
+def fused_and_unfused(ops, W, H, T, seed, rgb, steps, warmup, dev, stream, hbm=False):
+    """Mpixel/s of the planner's partition and of one kernel per stage on
+    another workload (whole video resident in HBM).  With `hbm`, each form's
+    algorithmic bytes (every group's input once and output once) over its
+    time, and the fused plan's groups (engine, tile, frames per work item)."""
     import torch
     from paper_1509_04394_amd import fz, synth
     x = torch.from_numpy(synth.video(W, H, T, seed=seed, rgb=rgb)).to(dev)
@@ -246,8 +268,85 @@ def fused_and_unfused(ops, W, H, T, seed, rgb, steps, warmup, dev, stream):
         ms, _, _ = time_plan(plan, x, bufs, steps, warmup, stream)
         res[name] = {"ms_per_step": round(ms, 4), "mpx_s": round(W * H * T / (ms * 1e-3) / 1e6, 1),
                      "partition": plan.segments}
+        if hbm:
+            byts = sum(hbm_bytes_per_px(plan, s.first, s.last) for s in plan.segment_info()) * W * H * T
+            gbs = byts / (ms * 1e-3) / 1e9
+            res[name].update(algorithmic_GBs=round(gbs, 1), hbm_frac=round(gbs / HBM_PEAK_GBS, 4))
+            if name == "fused":
+                eng = {fz.FZ_ENGINE_ROW: "row", fz.FZ_ENGINE_TILE: "tile", fz.FZ_ENGINE_STREAM: "stream",
+                       fz.FZ_ENGINE_JIT: "jit"}
+                res[name]["groups"] = [[s.first, s.last, eng[s.engine], s.tile_w, s.tile_h, s.frames_per_block]
+                                       for s in plan.segment_info()]
+        log(f"  {name}: {ms:.3f} ms/step, partition {plan.segments}")
         del bufs
     res["speedup_vs_unfused"] = round(res["unfused"]["ms_per_step"] / res["fused"]["ms_per_step"], 3)
+    del x
+    torch.cuda.empty_cache()
+    return res
+
+
+def tracking_leg(points, count, T, stream, reps=3, cpu=True):
+    """The Kalman tracking stage after the chain (its own launches on the
+    chain's point list): ms per pass over the whole clip, records and tracks;
+    beside it the oracle tracking the same points on one host thread."""
+    import torch
+    from paper_1509_04394_amd import fz
+    rec, flags = fz.track_points(points, count, T)  # the records (and a warm-up)
+    o = fz.track_opts()
+    cap = points.shape[0]
+    out = torch.empty((max(len(rec), 1), 12), dtype=torch.int32, device=points.device)
+    tc = torch.zeros((2,), dtype=torch.int32, device=points.device)
+    ws = torch.empty((fz.fz_track_workspace_bytes(T, cap, o),), dtype=torch.uint8, device=points.device)
+    times = []
+    for _ in range(reps):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        fz.fz_track_points(points.data_ptr(), count.data_ptr(), cap, T, o, out.data_ptr(), tc.data_ptr(),
+                           out.shape[0], ws.data_ptr(), ws.numel(), stream.cuda_stream)
+        b.record(stream)
+        torch.cuda.synchronize()
+        times.append(a.elapsed_time(b))
+    del out, ws
+    ms = float(np.median(times))
+    n = int(count.item())
+    res = {"ms_per_pass": round(ms, 3), "points": n, "records": int(len(rec)), "tracks": int(len(set(rec["id"].tolist()))),
+           "flags": flags, "points_per_s": round(n / (ms * 1e-3), 1),
+           "note": "Table II's Kalman filter on the chain's feature points, kernel-to-kernel after the chain "
+                   "(bucketing by frame, then one wavefront marching the frames); latency-bound, sequential in t"}
+    if cpu:
+        import oracle
+        host = points[:n, :3].cpu().numpy()
+        t0 = time.perf_counter()
+        oracle.track(host, T)
+        dt = time.perf_counter() - t0
+        res["cpu_oracle"] = {"ms_per_pass": round(dt * 1e3, 3), "cores": 1, "kind": "oracle"}
+    log(f"tracking: {ms:.3f} ms for {n} points, {len(rec)} records")
+    return res
+
+
+def engines_leg(key, steps, warmup, dev, stream):
+    """A generic workload fused with the interpreted tile kernel, fused with the
+    generated (hipRTC) kernel, and unfused."""
+    import torch
+    from paper_1509_04394_amd import fz, synth
+    w = WORKLOADS[key]
+    ops = chain_ops(w["chain"])
+    W, H, T = w["W"], w["H"], w["T"]
+    x = torch.from_numpy(synth.video(W, H, T, seed=w["seed"])).to(dev)
+    res = {"workload": w["desc"]}
+    for name, kw in (("fused_tile", dict(engine="tile")), ("fused_jit", dict(engine="jit")),
+                     ("unfused", dict(partition="unfused"))):
+        plan = fz.Plan(ops, W, H, T, **kw)
+        bufs = plan.alloc(dev)
+        ms, _, _ = time_plan(plan, x, bufs, steps, warmup, stream)
+        byts = sum(hbm_bytes_per_px(plan, s.first, s.last) for s in plan.segment_info()) * W * H * T
+        res[name] = {"ms_per_step": round(ms, 4), "mpx_s": round(W * H * T / (ms * 1e-3) / 1e6, 1),
+                     "partition": plan.segments, "algorithmic_GBs": round(byts / (ms * 1e-3) / 1e9, 1),
+                     "tiles": [[s.tile_w, s.tile_h] for s in plan.segment_info()]}
+        log(f"  {key} {name}: {ms:.4f} ms/step")
+        del bufs
+    res["jit_over_tile"] = round(res["fused_tile"]["ms_per_step"] / res["fused_jit"]["ms_per_step"], 3)
     del x
     torch.cuda.empty_cache()
     return res
@@ -327,8 +426,9 @@ def main():
                     help="untimed runs first (the GPU clock rises over the first ~10 ms of load)")
     ap.add_argument("--workload", default="rgb800", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--engine", default="auto", choices=["auto", "tile", "row"],
-                    help="kernel family for the fused plan's groups (auto: the planner's choice)")
+    ap.add_argument("--engine", default="auto", choices=["auto", "tile", "row", "jit"],
+                    help="kernel family for the fused plan's groups (auto: the planner's choice; jit: generated "
+                         "kernels for generic groups)")
     ap.add_argument("--autotune", action="store_true",
                     help="measure every band / tile configuration of each fused group first (untimed) and "
                          "keep the fastest")
@@ -388,6 +488,8 @@ def main():
     log(f"fused: {f_ms:.4f} ms/step back to back, {f_launch:.4f} ms mean per run between its events, "
         f"{nfused} points")
     extra = {}
+    if nfused and not args.fused_only:
+        extra["tracking"] = tracking_leg(fb[1], fb[2], T, stream, cpu=not args.no_cpu)
     if not args.fused_only:
         e2e, h2d = pcie_inclusive(fused, x, fb, stream)
         extra["pcie_inclusive"] = {
@@ -451,7 +553,7 @@ def main():
            "config": {"workload": wl["desc"], "partition": fused.segments,
                       "tile": [dominant.tile_w, dominant.tile_h, dominant.frames_per_block],
                       "engine": {fz.FZ_ENGINE_ROW: "row", fz.FZ_ENGINE_TILE: "tile",
-                                 fz.FZ_ENGINE_STREAM: "stream"}[dominant.engine],
+                                 fz.FZ_ENGINE_STREAM: "stream", fz.FZ_ENGINE_JIT: "jit"}[dominant.engine],
                       "sizing": "autotuned" if args.autotune else "planner",
                       "points_per_step": nfused},
            "roofline": roof}
@@ -472,6 +574,14 @@ def main():
             small[key] = dict(workload=w["desc"], **fused_and_unfused(
                 chain_ops(w["chain"]), w["W"], w["H"], w["T"], w["seed"], w["rgb"], args.steps, args.warmup,
                 dev, stream))
+        for key in ("paper5_800", "spatio800"):
+            w = WORKLOADS[key]
+            log(f"workload {key}")
+            small[key] = dict(workload=w["desc"], **fused_and_unfused(
+                chain_ops(w["chain"]), w["W"], w["H"], w["T"], w["seed"], w["rgb"], max(3, args.steps // 4), 2,
+                dev, stream, hbm=True))
+        log("workload generic800, interpreted and generated kernels")
+        small["generic800"] = engines_leg("generic800", args.steps, args.warmup, dev, stream)
         rec["other_workloads"] = small
         rec["batched"] = batch_leg(WORKLOADS["batch32"], max(3, args.steps // 4), 2, dev, stream)
     if not (args.no_cpu or args.fused_only):
