@@ -325,9 +325,28 @@ def tracking_leg(points, count, T, stream, reps=3, cpu=True):
     return res
 
 
+def autotune_leg(ops, W, H, T, x, steps, warmup, dev, stream, planner_ms):
+    """The fused plan after the autotuner (every band / frame run around the
+    Eq. 6 seed and every tile timed on the input, the fastest kept), timed as
+    the headline is, beside the planner-sized headline."""
+    from paper_1509_04394_amd import autotune, fz
+    plan = fz.Plan(ops, W, H, T)
+    report = autotune.autotune(plan, x, reps=3)
+    bufs = plan.alloc(dev)
+    ms, _, _ = time_plan(plan, x, bufs, steps, warmup, stream)
+    del bufs
+    s = plan.segment_info()
+    log(f"autotuned: {ms:.4f} ms/step ({[(g.tile_w, g.tile_h, g.frames_per_block) for g in s]})")
+    return {"ms_per_step": round(ms, 4), "mpx_s": round(W * H * T / (ms * 1e-3) / 1e6, 1),
+            "groups": [[g.first, g.last, g.engine, g.tile_w, g.tile_h, g.frames_per_block] for g in s],
+            "configs_tried": sum(1 for _ in report), "planner_ms_per_step": round(planner_ms, 4),
+            "speedup_over_planner": round(planner_ms / ms, 3)}
+
+
 def engines_leg(key, steps, warmup, dev, stream):
-    """A generic workload fused with the interpreted tile kernel, fused with the
-    generated (hipRTC) kernel, and unfused."""
+    """A generic workload fused with the interpreted kernels, fused with the
+    generated (hipRTC) kernels, and unfused (the planner's partition for the
+    fused forms; groups: first, last, tile, frames per work item)."""
     import torch
     from paper_1509_04394_amd import fz, synth
     w = WORKLOADS[key]
@@ -343,10 +362,12 @@ def engines_leg(key, steps, warmup, dev, stream):
         byts = sum(hbm_bytes_per_px(plan, s.first, s.last) for s in plan.segment_info()) * W * H * T
         res[name] = {"ms_per_step": round(ms, 4), "mpx_s": round(W * H * T / (ms * 1e-3) / 1e6, 1),
                      "partition": plan.segments, "algorithmic_GBs": round(byts / (ms * 1e-3) / 1e9, 1),
-                     "tiles": [[s.tile_w, s.tile_h] for s in plan.segment_info()]}
+                     "groups": [[s.first, s.last, s.tile_w, s.tile_h, s.frames_per_block]
+                                for s in plan.segment_info()]}
         log(f"  {key} {name}: {ms:.4f} ms/step")
         del bufs
     res["jit_over_tile"] = round(res["fused_tile"]["ms_per_step"] / res["fused_jit"]["ms_per_step"], 3)
+    res["jit_over_unfused"] = round(res["unfused"]["ms_per_step"] / res["fused_jit"]["ms_per_step"], 3)
     del x
     torch.cuda.empty_cache()
     return res
@@ -490,6 +511,8 @@ def main():
     extra = {}
     if nfused and not args.fused_only:
         extra["tracking"] = tracking_leg(fb[1], fb[2], T, stream, cpu=not args.no_cpu)
+    if not (args.fused_only or args.autotune):
+        extra["autotuned"] = autotune_leg(ops, W, H, T, x, args.steps, args.warmup, dev, stream, f_ms)
     if not args.fused_only:
         e2e, h2d = pcie_inclusive(fused, x, fb, stream)
         extra["pcie_inclusive"] = {
@@ -574,14 +597,10 @@ def main():
             small[key] = dict(workload=w["desc"], **fused_and_unfused(
                 chain_ops(w["chain"]), w["W"], w["H"], w["T"], w["seed"], w["rgb"], args.steps, args.warmup,
                 dev, stream))
-        for key in ("paper5_800", "spatio800"):
-            w = WORKLOADS[key]
-            log(f"workload {key}")
-            small[key] = dict(workload=w["desc"], **fused_and_unfused(
-                chain_ops(w["chain"]), w["W"], w["H"], w["T"], w["seed"], w["rgb"], max(3, args.steps // 4), 2,
-                dev, stream, hbm=True))
-        log("workload generic800, interpreted and generated kernels")
-        small["generic800"] = engines_leg("generic800", args.steps, args.warmup, dev, stream)
+        for key in ("paper5_800", "spatio800", "generic800"):
+            log(f"workload {key}, interpreted and generated kernels")
+            steps = args.steps if key == "generic800" else max(3, args.steps // 4)
+            small[key] = engines_leg(key, steps, min(args.warmup, 3), dev, stream)
         rec["other_workloads"] = small
         rec["batched"] = batch_leg(WORKLOADS["batch32"], max(3, args.steps // 4), 2, dev, stream)
     if not (args.no_cpu or args.fused_only):

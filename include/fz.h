@@ -150,12 +150,12 @@ typedef struct fz_plan_opts {
  * the Gaussian or the gray conversion to the suppression or the frame
  * difference, frames at least 128 pixels wide).  AUTO picks ROW where it
  * applies, TILE elsewhere.  JIT (generic chains only; Sec. X's generated
- * fused kernels): each generic group with a window stage and no temporal
- * stage gets a kernel written out for its stage list -- radii, box sizes and
- * weights as constants, point stages inline -- compiled for gfx950 with
- * hipRTC when the plan is made (a compile error fails fz_plan_chain), loaded
- * on each device at its first run and cached for the process; tiles 16x16,
- * 32x16, 32x32, 64x16, 64x32.  Its output equals TILE's to the bit.  Other
+ * fused kernels): each generic group with a window stage gets a kernel
+ * written out for its stage list -- radii, box sizes, frame rings and weights
+ * as constants, point and IIR stages inline -- compiled for gfx950 with hipRTC
+ * when the plan is made (a compile error fails fz_plan_chain), loaded on each
+ * device at its first run and cached for the process; tiles 16x16, 32x16,
+ * 32x32, 64x16, 64x32.  Its output equals TILE's to the bit.  Point-only
  * groups of a JIT plan run as in AUTO. */
 enum { FZ_ENGINE_AUTO = 0, FZ_ENGINE_TILE = 1, FZ_ENGINE_ROW = 2, FZ_ENGINE_STREAM = 3, FZ_ENGINE_JIT = 4 };
 

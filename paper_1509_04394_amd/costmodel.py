@@ -316,10 +316,11 @@ def campaign():
 
 # Fixed-chain sizes: a grid for training, and held-out (chain, W, H, T) tuples
 # that the grid never contains (frame counts off the grid), for the tests.
-FIXED_T_GRID = [8, 16, 32, 64, 128, 256]
+FIXED_T_GRID = [8, 16, 32, 64, 128, 256, 512, 1000]
 FIXED_HELD_OUT = [("rgb_harris", 640, 480, 40), ("harris", 320, 240, 100), ("grad", 800, 600, 48),
                   ("rgb_harris", 192, 432, 90), ("harris", 800, 600, 20), ("grad", 640, 480, 150),
-                  ("harris", 192, 432, 300), ("rgb_harris", 320, 240, 200)]
+                  ("harris", 192, 432, 300), ("rgb_harris", 320, 240, 200), ("rgb_harris", 800, 600, 700),
+                  ("harris", 640, 480, 600)]
 
 
 def fixed_campaign():

@@ -28,6 +28,7 @@ struct Segment {
     double bytes_per_px;
     double cost;
     int refused;            // a request this group's kernel cannot run (cost is +inf): 1 a band, 2 an IIR frame run
+    int ckpt;               // generic groups: IIR states checkpointed per frame run (two launches, workspace)
 };
 
 struct Params {
@@ -76,7 +77,8 @@ Segment price_group(const fz_plan& p, int a, int b, int tile_req_w, int tile_req
 Segment price_generic(const fz_plan& p, int a, int b, int req_w, int req_h, int req_tpb, int req_engine);
 // Sec. VI-E, Eq. 6 box for a volume beta and halos dx (per side), dt (frames)
 void eq6_box(double beta, double dx, double dt, double* x, double* t);
-int launch_generic(const fz_plan& p, const Segment& g, const void* in, void* out, void* stream);  // hipError_t
+int launch_generic(const fz_plan& p, const Segment& g, const void* in, void* out, void* ckpt, void* stream);  // hipError_t
+size_t ckpt_bytes(const fz_plan& p, const Segment& g);  // IIR checkpoints of group g (0 if none)
 
 // Learned prices (cost.cpp)
 constexpr int COST_FEATURES = 20;
@@ -107,7 +109,8 @@ void release_batch(fz_plan& p);
 // Generated kernels of generic groups (jit.cpp): source text, compile (no device needed), launch
 std::string jit_source(const fz_plan& p, const Segment& g);
 fz_status jit_prepare(const fz_plan& p, const Segment& g);
-int launch_jit(const fz_plan& p, const Segment& g, const void* in, void* out, void* stream);  // hipError_t
+int launch_jit(const fz_plan& p, const Segment& g, const void* in, void* out, const void* ckpt,
+               void* stream);  // hipError_t
 int jit_load(const fz_plan& p, const Segment& g);  // hipError_t: compile and load on the current device
 
 // Kalman tracking of feature points (track.hip)

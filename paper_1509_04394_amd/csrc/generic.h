@@ -47,7 +47,8 @@ struct GParams {
     int32_t tiles_x, tiles_y;
     int32_t tt;         // marching kernel: output frames per work item
     int32_t ht;         // marching kernel: temporal halo, the sum of the stencils' frames back
-    int32_t pad;
+    int32_t ck_n;       // IIR stages restored from checkpoints (0: none)
+    const double* ckpt; // IIR checkpoints: [chunk - 1][IIR][H][W] states after frame chunk * tt - 1
     GStage st[G_MAX_STAGES];
     float w[G_MAX_WEIGHTS];
 };
@@ -153,6 +154,27 @@ inline bool g_temporal(const GStage* st, int n, bool* has_iir = nullptr, int* ht
 // Output tiles of the generated (hipRTC) kernels, x by y.
 constexpr int N_JIT_TILES = 5;
 extern const int JIT_TILES[N_JIT_TILES][2];
+
+// A group whose IIR stages all come before its first window stage, and whose
+// stencils do not look back, can run in frame runs shorter than the clip: a
+// first pass marches the IIRs alone over every pixel and writes their state at
+// the end of every run (a checkpoint), and each work item of the group starts
+// its run from the checkpoint of the run before.  Returns the number of such
+// IIR stages, 0 if the group does not qualify.
+inline int g_ckpt_iirs(const GStage* st, int n)
+{
+    int lead = 0;
+    bool window = false;
+    for (int j = 0; j < n; ++j) {
+        if (st[j].rt > 0) return 0;
+        if (g_is_window(st[j].kind)) window = true;
+        if (st[j].kind == G_IIR) {
+            if (window) return 0;
+            ++lead;
+        }
+    }
+    return window ? lead : 0;
+}
 
 // Work items that fill the device: 256 CUs x 4 SIMDs, one 256-thread
 // workgroup (four wavefronts) per SIMD slot.

@@ -331,6 +331,25 @@ __global__ __launch_bounds__(BLOCK_THREADS) void k_gmarch(const GParams p)
     while (lead < p.n && !g_is_window(p.st[lead].kind)) ++lead;
     const UDiv by_rw(RW);
 
+    if (p.ck_n > 0 && t0 > 0) {
+        // the leading IIRs resume from the first pass's state after frame t0 - 1
+        const double* ck = p.ckpt + (size_t)(t0 / p.tt - 1) * p.ck_n * P;
+        for (int e = threadIdx.x; e < CELLS; e += BLOCK_THREADS) {
+            int lx;
+            const int ly = by_rw.quot(e, lx);
+            const int gx = ox + lx, gy = oy + ly;
+            if (gx < 0 || gx >= p.W || gy < 0 || gy >= p.H) continue;
+            int k = 0;
+            for (int j = 0; j < lead; ++j) {
+                const GStage sj = p.st[j];
+                if (sj.kind != G_IIR) continue;
+                ((double*)(glds + sj.buf))[e] = ck[(size_t)k * P + (size_t)gy * p.W + gx];
+                ++k;
+            }
+        }
+        __syncthreads();
+    }
+
     for (int f = fs; f < t1; ++f) {
         const bool first = f == 0;
         const size_t fbase = (size_t)f * P;
@@ -441,7 +460,12 @@ __global__ __launch_bounds__(BLOCK_THREADS) void k_gmarch(const GParams p)
 // states (doubles) live in LDS, PX per thread and IIR stage (GStage::buf is
 // the stage's offset there, in doubles); registers indexed by a stage number
 // only known at run time would have gone to scratch memory.
-template <int PX, int D>
+//
+// With CKPT, the kernel is the first pass of a checkpointed group: it runs
+// the group's leading point and IIR stages only (p.n of them), stores no
+// output, and after the last frame of every frame run but the last writes
+// each IIR's state to p.ckpt[run][IIR][pixel].
+template <int PX, int D, bool CKPT>
 __global__ __launch_bounds__(BLOCK_THREADS) void k_gstream_t(const GParams p)
 {
     extern __shared__ double gstate[];
@@ -476,6 +500,8 @@ __global__ __launch_bounds__(BLOCK_THREADS) void k_gstream_t(const GParams p)
         for (int d = 0; d < D; ++d) {
             if (t + d >= p.T) break;
             const bool first = t + d == 0;
+            const bool save = CKPT && (t + d + 1) % p.tt == 0 && t + d + 1 < p.T;
+            int n_iir = 0;
             for (int j = 0; j < p.n; ++j) {
                 const GStage s = p.st[j];
                 if (s.kind == G_IIR) {
@@ -488,16 +514,24 @@ __global__ __launch_bounds__(BLOCK_THREADS) void k_gstream_t(const GParams p)
                         sp[k] = y;
                         v[d][k] = (float)y;
                     }
+                    if (save) {
+                        double* ck = (double*)p.ckpt + ((size_t)((t + d + 1) / p.tt - 1) * p.ck_n + n_iir) * P + i0;
+#pragma unroll
+                        for (int k = 0; k < PX; ++k) ck[k] = sp[k];
+                    }
+                    ++n_iir;
                 } else {
 #pragma unroll
                     for (int k = 0; k < PX; ++k) v[d][k] = gpoint(s, v[d][k]);
                 }
             }
-            const size_t gi = (size_t)(t + d) * P + i0;
-            if constexpr (PX == 4)
-                *(float4*)(p.out + gi) = make_float4(v[d][0], v[d][1], v[d][2], v[d][3]);
-            else
-                p.out[gi] = v[d][0];
+            if constexpr (!CKPT) {
+                const size_t gi = (size_t)(t + d) * P + i0;
+                if constexpr (PX == 4)
+                    *(float4*)(p.out + gi) = make_float4(v[d][0], v[d][1], v[d][2], v[d][3]);
+                else
+                    p.out[gi] = v[d][0];
+            }
         }
     }
 }
@@ -526,9 +560,42 @@ static hipError_t launch_tile(const GParams& gp, int lds, bool march, int nchunk
     return hipGetLastError();
 }
 
-int launch_generic(const fz_plan& p, const Segment& g, const void* in, void* out, void* stream)
+// Launch a group of point and IIR stages through k_gstream_t (the whole group,
+// or with CKPT the first pass of a checkpointed group).
+template <bool CKPT>
+static hipError_t launch_stream_t(GParams gp, const void* in, size_t P, hipStream_t s)
 {
-    if (g.engine == FZ_ENGINE_JIT) return launch_jit(p, g, in, out, stream);
+    const bool vec = P % 4 == 0 && ((uintptr_t)in % (gp.in_u8 ? 4 : 16)) == 0 &&
+                     (CKPT || ((uintptr_t)gp.out % 16) == 0);
+    const int px = vec ? 4 : 1;
+    int n_iir = 0;
+    for (int j = 0; j < gp.n; ++j)
+        if (gp.st[j].kind == G_IIR) gp.st[j].buf = (n_iir++) * BLOCK_THREADS * px;
+    const int lds = n_iir * BLOCK_THREADS * px * 8;  // doubles; a 4-pixel run with 16 IIRs: 128 KB
+    hipError_t e = hipSuccess;
+    if (lds > 65536) e = vec ? allow_lds(k_gstream_t<4, 8, CKPT>, lds) : allow_lds(k_gstream_t<1, 8, CKPT>, lds);
+    if (e != hipSuccess) return e;
+    const size_t threads = P / px;
+    const unsigned blocks = (unsigned)((threads + BLOCK_THREADS - 1) / BLOCK_THREADS);
+    if (vec)
+        k_gstream_t<4, 8, CKPT><<<dim3(blocks), dim3(BLOCK_THREADS), lds, s>>>(gp);
+    else
+        k_gstream_t<1, 8, CKPT><<<dim3(blocks), dim3(BLOCK_THREADS), lds, s>>>(gp);
+    return hipGetLastError();
+}
+
+size_t ckpt_bytes(const fz_plan& p, const Segment& g)
+{
+    if (!p.generic || !g.ckpt || g.tpb <= 0) return 0;
+    GStage st[G_MAX_STAGES];
+    g_stage_list(p.stages.data(), g.first, g.last, st);
+    const int n_iir = g_ckpt_iirs(st, g.last - g.first + 1);
+    const size_t runs = (size_t)(p.T + g.tpb - 1) / g.tpb;
+    return runs > 1 ? (runs - 1) * n_iir * (size_t)p.W * p.H * sizeof(double) : 0;
+}
+
+int launch_generic(const fz_plan& p, const Segment& g, const void* in, void* out, void* ckpt, void* stream)
+{
     hipStream_t s = (hipStream_t)stream;
     GParams gp{};
     gp.in = in;
@@ -556,38 +623,35 @@ int launch_generic(const fz_plan& p, const Segment& g, const void* in, void* out
     const bool temporal = g_temporal(gp.st, gp.n, &has_iir, &gp.ht);
     const size_t P = (size_t)p.W * p.H;
     if (g.engine == FZ_ENGINE_STREAM) {
-        if (temporal) {  // point and IIR stages: one thread per run of pixels, all frames
-            const bool vec = P % 4 == 0 && ((uintptr_t)in % (gp.in_u8 ? 4 : 16)) == 0 && ((uintptr_t)out % 16) == 0;
-            const int px = vec ? 4 : 1;
-            int n_iir = 0;
-            for (int j = 0; j < gp.n; ++j)
-                if (gp.st[j].kind == G_IIR) gp.st[j].buf = (n_iir++) * BLOCK_THREADS * px;
-            const int lds = n_iir * BLOCK_THREADS * px * 8;  // doubles; a 4-pixel run with 16 IIRs: 128 KB
-            if (lds > 65536) {
-                hipError_t e = vec ? allow_lds(k_gstream_t<4, 8>, lds) : allow_lds(k_gstream_t<1, 8>, lds);
-                if (e != hipSuccess) return e;
-            }
-            const size_t threads = P / px;
-            const unsigned blocks = (unsigned)((threads + BLOCK_THREADS - 1) / BLOCK_THREADS);
-            if (vec)
-                k_gstream_t<4, 8><<<dim3(blocks), dim3(BLOCK_THREADS), lds, s>>>(gp);
-            else
-                k_gstream_t<1, 8><<<dim3(blocks), dim3(BLOCK_THREADS), lds, s>>>(gp);
-            return hipGetLastError();
-        }
+        if (temporal) return launch_stream_t<false>(gp, in, P, s);  // point and IIR stages, all frames
         const size_t n = P * p.T;
         const size_t want = (n + BLOCK_THREADS - 1) / BLOCK_THREADS;
         const unsigned blocks = (unsigned)std::min<size_t>(want, 256 * 32);
         k_gstream<<<dim3(blocks), dim3(BLOCK_THREADS), 0, s>>>(gp);
         return hipGetLastError();
     }
+    if (g.engine == FZ_ENGINE_JIT && !temporal) return launch_jit(p, g, in, out, nullptr, stream);
     gp.tiles_x = (p.W + g.tile_w - 1) / g.tile_w;
     gp.tiles_y = (p.H + g.tile_h - 1) / g.tile_h;
     int nchunks = 1;
     if (temporal) {
         gp.tt = g.tpb;
-        if (gp.tt < 1 || (has_iir && gp.tt < p.T)) return hipErrorInvalidValue;
+        if (gp.tt < 1 || (has_iir && !g.ckpt && gp.tt < p.T)) return hipErrorInvalidValue;
         nchunks = (p.T + gp.tt - 1) / gp.tt;
+        if (g.ckpt && nchunks > 1) {
+            // first pass: the leading point and IIR stages over every pixel, checkpoints only
+            if (!ckpt) return hipErrorInvalidValue;
+            gp.ck_n = g_ckpt_iirs(gp.st, gp.n);
+            gp.ckpt = (const double*)ckpt;
+            GParams g1 = gp;
+            int lead = 0;
+            while (lead < gp.n && !g_is_window(gp.st[lead].kind)) ++lead;
+            g1.n = lead;
+            g1.out = nullptr;
+            const hipError_t e = launch_stream_t<true>(g1, in, P, s);
+            if (e != hipSuccess) return e;
+        }
+        if (g.engine == FZ_ENGINE_JIT) return launch_jit(p, g, in, out, ckpt, stream);
         const int floats = march_layout(gp.st, gp.n, (g.tile_w + 2 * gp.hx) * (g.tile_h + 2 * gp.hy));
         if ((floats + GEN_PAD) * 4 != g.lds_bytes) return hipErrorInvalidValue;
     }

@@ -12,7 +12,9 @@
 // stages applied, window stages from one LDS buffer into the other, the last
 // one straight to global memory, five neighbouring cells per thread inside the
 // frame, clamped reads on border tiles) and the same arithmetic in the same
-// order, so its output equals the tile kernel's to the bit.
+// order, so its output equals the tile kernel's to the bit.  Groups with a
+// temporal stage get the frame-marching kernel written out the same way
+// (rings of earlier frames per stencil, IIR states, checkpoint restore).
 #include <hip/hip_runtime.h>
 #include <hip/hiprtc.h>
 
@@ -54,8 +56,15 @@ static std::string point_stmt(const fz_stage& s)
     }
 }
 
+static std::string jit_march_source(const fz_plan& p, const Segment& g);
+
 std::string jit_source(const fz_plan& p, const Segment& g)
 {
+    {
+        GStage st[G_MAX_STAGES];
+        g_stage_list(p.stages.data(), g.first, g.last, st);
+        if (g_temporal(st, g.last - g.first + 1)) return jit_march_source(p, g);
+    }
     std::ostringstream o;
     const int TW = g.tile_w, TH = g.tile_h, HX = g.halo, HY = g.halo_y;
     const bool u8 = p.stages[g.first].in_dtype == FZ_U8;
@@ -188,6 +197,190 @@ std::string jit_source(const fz_plan& p, const Segment& g)
     return o.str();
 }
 
+// One point or IIR stage on `v` (cell: the expression of its box cell, for an
+// IIR's state).
+static std::string trail_stmt(const fz_stage& s, const GStage& gs, const std::string& cell)
+{
+    if (s.op != FZ_OP_IIR) return point_stmt(s);
+    const std::string a = "(double)" + flit(s.param[0]);
+    return "{ double* sp = (double*)(lds + " + std::to_string(gs.buf) + ") + (" + cell +
+           "); const double x = (double)v; const double y = fma(" + a + ", x, (1.0 - " + a +
+           ") * (first ? x : *sp)); *sp = y; v = (float)y; }";
+}
+
+// The frame-marching kernel of a group with a temporal stage, written out
+// (the same steps and arithmetic as k_gmarch, stage list as constants).
+static std::string jit_march_source(const fz_plan& p, const Segment& g)
+{
+    std::ostringstream o;
+    const int TW = g.tile_w, TH = g.tile_h, HX = g.halo, HY = g.halo_y;
+    const int n = g.last - g.first + 1;
+    GStage st[G_MAX_STAGES];
+    g_stage_list(p.stages.data(), g.first, g.last, st);
+    const int floats = march_layout(st, n, (TW + 2 * HX) * (TH + 2 * HY)) + GEN_PAD;
+    const int ck_n = g.ckpt ? g_ckpt_iirs(st, n) : 0;
+    const bool u8 = p.stages[g.first].in_dtype == FZ_U8;
+    o << "#define GQ 5\n"
+         "__device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }\n"
+         "extern \"C\" __global__ __launch_bounds__(256) void fz_jit(const "
+      << (u8 ? "unsigned char" : "float")
+      << "* __restrict__ in, float* __restrict__ out, int W, int H, int tiles_x, int tiles_y, int T, int tt, "
+         "int ht, const double* __restrict__ ckpt)\n{\n"
+      << "    constexpr int TW = " << TW << ", TH = " << TH << ", HX = " << HX << ", HY = " << HY
+      << ", RW = TW + 2 * HX, RH = TH + 2 * HY, CELLS = RW * RH;\n"
+      << "    __shared__ double lds_d[" << (floats + 1) / 2 << "];\n"
+      << "    float* lds = (float*)lds_d;\n"
+         "    const int nb = gridDim.x, q8 = nb >> 3, r8 = nb & 7, xcd = blockIdx.x & 7, slot = blockIdx.x >> 3;\n"
+         "    int b = (xcd < r8 ? xcd * (q8 + 1) : r8 * (q8 + 1) + (xcd - r8) * q8) + slot;\n"
+         "    const int tx = b % tiles_x;\n    b /= tiles_x;\n    const int ty = b % tiles_y;\n"
+         "    const int t0 = (b / tiles_y) * tt, t1 = min(T, t0 + tt), fs = max(0, t0 - ht);\n"
+         "    const int ox = tx * TW - HX, oy = ty * TH - HY;\n"
+         "    const size_t P = (size_t)W * H;\n"
+         "    const bool interior = ox >= 0 && oy >= 0 && ox + RW <= W && oy + RH <= H;\n";
+    int lead = 0;
+    while (lead < n && !g_is_window(st[lead].kind)) ++lead;
+    if (ck_n > 0) {
+        o << "    if (t0 > 0) {  // the leading IIRs resume from the first pass's state after frame t0 - 1\n"
+             "        const double* ck = ckpt + (size_t)(t0 / tt - 1) * "
+          << ck_n
+          << " * P;\n"
+             "        for (int e = threadIdx.x; e < CELLS; e += 256) {\n"
+             "            const int ly = e / RW, lx = e - ly * RW, gx = ox + lx, gy = oy + ly;\n"
+             "            if (gx < 0 || gx >= W || gy < 0 || gy >= H) continue;\n";
+        int k = 0;
+        for (int j = 0; j < lead; ++j)
+            if (st[j].kind == G_IIR)
+                o << "            ((double*)(lds + " << st[j].buf << "))[e] = ck[(size_t)" << k++
+                  << " * P + (size_t)gy * W + gx];\n";
+        o << "        }\n        __syncthreads();\n    }\n";
+    }
+    o << "    for (int f = fs; f < t1; ++f) {\n"
+         "        const bool first = f == 0;\n"
+         "        const size_t fbase = (size_t)f * P;\n"
+         "        {\n"
+         "            float* dst = lds + "
+      << st[lead].buf << " + (f % " << st[lead].slots
+      << ") * CELLS;\n"
+         "            for (int e = threadIdx.x; e < CELLS; e += 256) {\n"
+         "                const int ly = e / RW, lx = e - ly * RW, gx = ox + lx, gy = oy + ly;\n"
+         "                if (gx < 0 || gx >= W || gy < 0 || gy >= H) continue;\n"
+         "                float v = (float)in[fbase + (size_t)gy * W + gx];\n";
+    for (int j = 0; j < lead; ++j) o << "                " << trail_stmt(p.stages[g.first + j], st[j], "e") << "\n";
+    o << "                dst[e] = v;\n            }\n        }\n        __syncthreads();\n";
+    int i = lead, hx = HX, hy = HY, back = 0;
+    while (i < n) {
+        const GStage& s = st[i];
+        int j = i + 1;
+        while (j < n && !g_is_window(st[j].kind)) ++j;
+        const bool last = j == n;
+        back += s.rt;
+        const int ohx = hx - s.rx, ohy = hy - s.ry;
+        const bool stencil = s.kind == G_STENCIL;
+        const int nw = (2 * s.rx + 1) * (2 * s.ry + 1);
+        auto trail = [&](const std::string& cell, const char* ind) {
+            std::string r;
+            for (int q = i + 1; q < j; ++q) r += std::string(ind) + trail_stmt(p.stages[g.first + q], st[q], cell) + "\n";
+            return r;
+        };
+        o << "        {  // window stage " << i << "\n"
+          << "            constexpr int RX = " << s.rx << ", RY = " << s.ry << ", RT = " << s.rt << ", OHX = " << ohx
+          << ", OHY = " << ohy << ";\n"
+          << "            constexpr int OW = TW + 2 * OHX, OH = TH + 2 * OHY, BX = HX - OHX, BY = HY - OHY;\n"
+          << "            if ((fs == 0 || f >= fs + " << back << ")" << (last ? " && f >= t0" : "") << ") {\n";
+        if (stencil) {
+            o << "                constexpr float w[" << nw * (s.rt + 1) << "] = {";
+            for (int q = 0; q < nw * (s.rt + 1); ++q) o << (q ? ", " : "") << flit(p.gweights[p.gwoff[g.first + i] + q]);
+            o << "};\n";
+        }
+        if (!last) o << "                float* dst = lds + " << st[j].buf << " + (f % " << st[j].slots << ") * CELLS;\n";
+        o << "                if (interior) {\n"
+             "                    constexpr int NQ = (OW + GQ - 1) / GQ;\n"
+             "                    for (int e = threadIdx.x; e < NQ * OH; e += 256) {\n"
+             "                        const int cy = e / NQ, cx = (e - cy * NQ) * GQ;\n"
+             "                        const int lx = BX + cx, ly = BY + cy, base = ly * RW + lx;\n"
+             "                        float acc[GQ];\n"
+             "#pragma unroll\n"
+             "                        for (int c = 0; c < GQ; ++c) acc[c] = 0.0f;\n"
+             "#pragma unroll\n"
+             "                        for (int tau = 0; tau <= RT; ++tau) {\n"
+             "                            const float* src = lds + "
+          << s.buf << " + (max(f - tau, 0) % " << s.slots
+          << ") * CELLS;\n"
+             "#pragma unroll\n"
+             "                            for (int v = -RY; v <= RY; ++v) {\n"
+             "                                float x[GQ + 2 * RX];\n"
+             "#pragma unroll\n"
+             "                                for (int q = 0; q < GQ + 2 * RX; ++q) x[q] = src[base + v * RW - RX + q];\n";
+        if (stencil)
+            o << "#pragma unroll\n"
+                 "                                for (int u = -RX; u <= RX; ++u) {\n"
+                 "                                    const float wv = w[tau * " << nw << " + (v + RY) * (2 * RX + 1) + (u + RX)];\n"
+                 "#pragma unroll\n"
+                 "                                    for (int c = 0; c < GQ; ++c) acc[c] = fmaf(wv, x[c + u + RX], acc[c]);\n"
+                 "                                }\n";
+        else
+            o << "#pragma unroll\n"
+                 "                                for (int c = 0; c < GQ; ++c) {\n"
+                 "                                    float h = 0.0f;\n"
+                 "#pragma unroll\n"
+                 "                                    for (int u = -RX; u <= RX; ++u) h = h + x[c + u + RX];\n"
+                 "                                    acc[c] = acc[c] + h;\n"
+                 "                                }\n";
+        o << "                            }\n"
+             "                        }\n"
+             "                        const int nk = OW - cx < GQ ? OW - cx : GQ;\n"
+             "#pragma unroll\n"
+             "                        for (int c = 0; c < GQ; ++c) {\n"
+             "                            if (c >= nk) break;\n"
+             "                            float v = acc[c];\n"
+          << trail("base + c", "                            ");
+        if (last)
+            o << "                            out[fbase + (size_t)(oy + ly) * W + (ox + lx + c)] = v;\n";
+        else
+            o << "                            dst[base + c] = v;\n";
+        o << "                        }\n                    }\n"
+             "                } else {\n"
+             "                    for (int e = threadIdx.x; e < OW * OH; e += 256) {\n"
+             "                        const int cy = e / OW, cx = e - cy * OW;\n"
+             "                        const int lx = BX + cx, ly = BY + cy, gx = ox + lx, gy = oy + ly;\n"
+             "                        if (gx < 0 || gx >= W || gy < 0 || gy >= H) continue;\n"
+             "                        float acc = 0.0f;\n"
+             "#pragma unroll\n"
+             "                        for (int tau = 0; tau <= RT; ++tau) {\n"
+             "                            const float* src = lds + "
+          << s.buf << " + (max(f - tau, 0) % " << s.slots
+          << ") * CELLS;\n"
+             "#pragma unroll\n"
+             "                            for (int v = -RY; v <= RY; ++v) {\n"
+             "                                const int row = (clampi(gy + v, 0, H - 1) - oy) * RW - ox;\n";
+        if (stencil)
+            o << "#pragma unroll\n"
+                 "                                for (int u = -RX; u <= RX; ++u)\n"
+                 "                                    acc = fmaf(w[tau * " << nw << " + (v + RY) * (2 * RX + 1) + (u + RX)], "
+                 "src[row + clampi(gx + u, 0, W - 1)], acc);\n";
+        else
+            o << "                                float h = 0.0f;\n"
+                 "#pragma unroll\n"
+                 "                                for (int u = -RX; u <= RX; ++u) h = h + src[row + clampi(gx + u, 0, W - 1)];\n"
+                 "                                acc = acc + h;\n";
+        o << "                            }\n"
+             "                        }\n"
+             "                        float v = acc;\n"
+          << trail("ly * RW + lx", "                        ");
+        if (last)
+            o << "                        out[fbase + (size_t)gy * W + gx] = v;\n";
+        else
+            o << "                        dst[ly * RW + lx] = v;\n";
+        o << "                    }\n                }\n            }\n        }\n";
+        if (!last) o << "        __syncthreads();\n";
+        hx = ohx;
+        hy = ohy;
+        i = j;
+    }
+    o << "        __syncthreads();\n    }\n}\n";
+    return o.str();
+}
+
 namespace {
 struct Compiled {
     std::vector<char> code;
@@ -271,11 +464,26 @@ int jit_load(const fz_plan& p, const Segment& g)
     return (int)jit_function(p, g, &fn);
 }
 
-int launch_jit(const fz_plan& p, const Segment& g, const void* in, void* out, void* stream)
+int launch_jit(const fz_plan& p, const Segment& g, const void* in, void* out, const void* ckpt, void* stream)
 {
     hipFunction_t fn = nullptr;
     const hipError_t e = jit_function(p, g, &fn);
     if (e != hipSuccess) return (int)e;
+    GStage st[G_MAX_STAGES];
+    g_stage_list(p.stages.data(), g.first, g.last, st);
+    int ht = 0;
+    if (g_temporal(st, g.last - g.first + 1, nullptr, &ht)) {  // the frame-marching form
+        const int tiles_x = (p.W + g.tile_w - 1) / g.tile_w, tiles_y = (p.H + g.tile_h - 1) / g.tile_h;
+        const long long blocks = (long long)tiles_x * tiles_y * ((p.T + g.tpb - 1) / g.tpb);
+        if (blocks > 0x7fffffffLL || g.tpb < 1) return (int)hipErrorInvalidConfiguration;
+        int W = p.W, H = p.H, txs = tiles_x, tys = tiles_y, T = p.T, tt = g.tpb, hts = ht;
+        const void* pin = in;
+        float* pout = (float*)out;
+        const void* pck = ckpt;
+        void* args[] = {&pin, &pout, &W, &H, &txs, &tys, &T, &tt, &hts, &pck};
+        return (int)hipModuleLaunchKernel(fn, (unsigned)blocks, 1, 1, BLOCK_THREADS, 1, 1, 0, (hipStream_t)stream,
+                                          args, nullptr);
+    }
     const int tiles_x = (p.W + g.tile_w - 1) / g.tile_w, tiles_y = (p.H + g.tile_h - 1) / g.tile_h;
     const long long blocks = (long long)tiles_x * tiles_y * p.T;
     if (blocks > 0x7fffffffLL) return (int)hipErrorInvalidConfiguration;

@@ -24,12 +24,25 @@ static size_t stage_out_bytes(const fz_plan& p, int k)
 }
 
 // Three buffers as large as the largest stage output (the input of the groups
-// being timed, the output they write, the next stage's input) and a counter.
+// being timed, the output they write, the next stage's input), a counter, and
+// the IIR checkpoints of the largest candidate group.
+static size_t measure_ckpt_bytes(const fz_plan& p)
+{
+    size_t ck = 0;
+    for (int a = 0; a < p.n; ++a)
+        for (int b = a; b < p.n; ++b) {
+            ck = std::max(ck, ckpt_bytes(p, price_group(p, a, b, 0, 0, 0, FZ_ENGINE_AUTO)));
+            for (int t = 0; t < N_TILES; ++t)
+                ck = std::max(ck, ckpt_bytes(p, price_group(p, a, b, tile_w(t), tile_h(t), 0, FZ_ENGINE_TILE)));
+        }
+    return align256(ck);
+}
+
 size_t measure_workspace_bytes(const fz_plan& p)
 {
     size_t mx = 0;
     for (int k = 0; k < p.n; ++k) mx = std::max(mx, stage_out_bytes(p, k));
-    return 3 * align256(mx) + 256;
+    return 3 * align256(mx) + 256 + measure_ckpt_bytes(p);
 }
 
 // A plan of the same chain and size whose only group is g.
@@ -63,7 +76,7 @@ struct EventPair {
 
 // Median time in microseconds of `reps` runs of group g (after one untimed run).
 static fz_status time_group(const fz_plan& p, const Segment& g, const void* in, void* out, uint32_t* cnt, int reps,
-                            hipStream_t s, const EventPair& ev, double* us)
+                            hipStream_t s, const EventPair& ev, void* ck, size_t ck_bytes, double* us)
 {
     fz_plan sub;
     single_group(sub, p, g);
@@ -71,7 +84,7 @@ static fz_status time_group(const fz_plan& p, const Segment& g, const void* in, 
     for (int r = 0; r <= reps; ++r) {
         hipError_t e = hipEventRecord(ev.a, s);
         if (e != hipSuccess) return fail(FZ_E_HIP, std::string("measure: event record: ") + hipGetErrorString(e));
-        fz_status st = run_plan(sub, in, out, nullptr, cnt, 0u, nullptr, 0, s);
+        fz_status st = run_plan(sub, in, out, nullptr, cnt, 0u, ck, ck_bytes, s);
         if (st != FZ_OK) return st;
         e = hipEventRecord(ev.b, s);
         if (e == hipSuccess) e = hipEventSynchronize(ev.b);
@@ -93,9 +106,11 @@ fz_status plan_measure(fz_plan& p, const void* d_in, void* ws, size_t ws_bytes, 
         return fail(FZ_E_WORKSPACE, "fz_plan_measure: workspace needs " + std::to_string(need) + " bytes");
     hipStream_t s = (hipStream_t)stream;
     (void)hipGetLastError();  // drop an error latched by earlier, unrelated runtime calls
-    const size_t slot = (need - 256) / 3;
+    const size_t ckb = measure_ckpt_bytes(p);
+    const size_t slot = (need - 256 - ckb) / 3;
     char* buf[3] = {(char*)ws, (char*)ws + slot, (char*)ws + 2 * slot};
     uint32_t* cnt = (uint32_t*)((char*)ws + 3 * slot);
+    void* ck = ckb ? (void*)((char*)ws + 3 * slot + 256) : nullptr;
     EventPair ev;
     hipError_t e = hipEventCreate(&ev.a);
     if (e == hipSuccess) e = hipEventCreate(&ev.b);
@@ -124,7 +139,7 @@ fz_status plan_measure(fz_plan& p, const void* d_in, void* ws, size_t ws_bytes, 
                 if (std::find(seen.begin(), seen.end(), key) != seen.end()) continue;
                 seen.push_back(key);
                 double us = 0.0;
-                fz_status st = time_group(p, g, cur, buf[out_buf], cnt, reps, s, ev, &us);
+                fz_status st = time_group(p, g, cur, buf[out_buf], cnt, reps, s, ev, ck, ckb, &us);
                 if (st != FZ_OK) return st;
                 if (us < cost[(size_t)a * n + b]) {
                     cost[(size_t)a * n + b] = us;
@@ -139,7 +154,7 @@ fz_status plan_measure(fz_plan& p, const void* d_in, void* ws, size_t ws_bytes, 
             const Segment g1 = best[(size_t)a * n + a];
             fz_plan sub;
             single_group(sub, p, g1);
-            fz_status st = run_plan(sub, cur, buf[next_buf], nullptr, cnt, 0u, nullptr, 0, s);
+            fz_status st = run_plan(sub, cur, buf[next_buf], nullptr, cnt, 0u, ck, ckb, s);
             if (st != FZ_OK) return st;
             cur = buf[next_buf];
             cur_buf = next_buf;

@@ -160,8 +160,11 @@ void eq6_box(double beta, double dx, double dt, double* x, double* t)
 //    items fill the device instead: Eq. 6 with beta = W H T / G_FILL_ITEMS
 //    output pixels per item gives t; then the tile of best Eq. 3 utilisation
 //    for that t, discounted by the idle share of the device when the tile
-//    leaves fewer work items than fill it.  An IIR's work items march the
-//    whole clip (t = T).
+//    leaves fewer work items than fill it.  IIRs that all come before the
+//    first window stage (and no stencil looking back) are checkpointed: a
+//    first pass writes their state at every run boundary and the runs are the
+//    longest power of two (at least 8 frames) that leaves two fills of work
+//    items.  Any other IIR makes the work items march the whole clip (t = T).
 // Cost: compulsory bytes (input once, output once, the temporal halo re-read
 // once per frame run), times G_FILL_ITEMS / items when a marching group has
 // fewer work items than fill the device (its frames are a sequential chain
@@ -194,8 +197,9 @@ Segment price_generic(const fz_plan& p, int a, int b, int req_w, int req_h, int 
     s.halo_t = ht;
     s.tpb = 1;
     s.streaming = nwin == 0;
-    if (iir && req_tpb > 0 && req_tpb < p.T) {
-        s.refused = 2;  // an IIR needs every earlier frame: its work items march the whole clip
+    const int n_ck = g_ckpt_iirs(st, n);  // leading IIRs that can resume from checkpoints
+    if (iir && !n_ck && nwin > 0 && req_tpb > 0 && req_tpb < p.T) {
+        s.refused = 2;  // an IIR after a window stage needs every earlier frame: whole-clip work items
         return s;
     }
     const double P = (double)p.W * p.H;
@@ -206,56 +210,55 @@ Segment price_generic(const fz_plan& p, int a, int b, int req_w, int req_h, int 
             s.tpb = p.T;
             items = ceil(P / (4.0 * BLOCK_THREADS));
         }
-    } else if (req_engine == FZ_ENGINE_JIT && !temporal) {
-        // a generated kernel: the tile of best data utilisation among the generated tiles
-        s.engine = FZ_ENGINE_JIT;
-        double best_du = -1.0;
-        for (int t = 0; t < N_JIT_TILES; ++t) {
-            const int tw = JIT_TILES[t][0], th = JIT_TILES[t][1];
-            if (req_w > 0 && (tw != req_w || th != req_h)) continue;
-            const int lds = generic_lds_bytes(tw, th, hx, hy, nwin);
-            if (lds > p.lds_budget) continue;
-            const double du = (double)tw * th / ((double)(tw + 2 * hx) * (th + 2 * hy));
-            if (du > best_du) {
-                best_du = du;
-                s.tile = t;
-                s.tile_w = tw;
-                s.tile_h = th;
-                s.lds_bytes = lds;
-            }
-        }
-        if (s.tile < 0) return s;
     } else {
-        s.engine = FZ_ENGINE_TILE;
-        int tt = 1;
-        if (iir) {
-            tt = p.T;
-        } else if (temporal) {
+        // window groups: the compiled tiles of the tile kernels, or the generated kernels' tiles
+        const bool jit = req_engine == FZ_ENGINE_JIT;
+        s.engine = jit ? FZ_ENGINE_JIT : FZ_ENGINE_TILE;
+        const int ntiles = jit ? N_JIT_TILES : N_TILES;
+        int tt_fixed = 1;
+        if (iir && !n_ck) {
+            tt_fixed = p.T;
+        } else if (temporal && !n_ck) {
             if (req_tpb > 0) {
-                tt = std::min(req_tpb, p.T);
+                tt_fixed = std::min(req_tpb, p.T);
             } else {
                 double x, t;
                 eq6_box(P * p.T / G_FILL_ITEMS, 0.5 * (hx + hy), ht, &x, &t);
-                tt = (int)std::min<double>(std::max(1.0, std::floor(t + 0.5)), p.T);
+                tt_fixed = (int)std::min<double>(std::max(1.0, std::floor(t + 0.5)), p.T);
             }
         }
         double best_du = -1.0;
-        for (int t = 0; t < N_TILES; ++t) {
-            const int tw = tile_w(t), th = tile_h(t);
+        int best_tt = tt_fixed;
+        for (int t = 0; t < ntiles; ++t) {
+            const int tw = jit ? JIT_TILES[t][0] : tile_w(t), th = jit ? JIT_TILES[t][1] : tile_h(t);
             if (req_w > 0 && (tw != req_w || th != req_h)) continue;
             const int cells = (tw + 2 * hx) * (th + 2 * hy);
             const int lds = temporal ? (march_layout(st, n, cells) + GEN_PAD) * 4
                                      : generic_lds_bytes(tw, th, hx, hy, nwin);
             if (lds > p.lds_budget) continue;
-            double du = (double)tw * th / ((double)(tw + 2 * hx) * (th + 2 * hy));
+            const double tiles = ceil((double)p.W / tw) * ceil((double)p.H / th);
+            int tt = tt_fixed;
+            if (n_ck) {
+                // checkpointed IIRs: the longest power-of-two run (at least 8 frames) that still
+                // leaves two fills of work items; each run boundary costs a checkpoint
+                if (req_tpb > 0) {
+                    tt = std::min(req_tpb, p.T);
+                } else {
+                    tt = 8;
+                    while (tt * 2 <= p.T && tiles * ceil((double)p.T / (tt * 2)) >= 2.0 * G_FILL_ITEMS) tt *= 2;
+                    tt = std::min(tt, p.T);
+                }
+            }
+            double du = (double)tw * th / ((double)cells);
             if (temporal) {
                 du *= (double)tt / (tt + (iir ? 0 : ht));
                 // under-filled marching groups lose the idle share of the device
-                const double it = ceil((double)p.W / tw) * ceil((double)p.H / th) * ceil((double)p.T / tt);
+                const double it = tiles * ceil((double)p.T / tt);
                 if (it < G_FILL_ITEMS) du *= it / G_FILL_ITEMS;
             }
             if (du > best_du) {
                 best_du = du;
+                best_tt = tt;
                 s.tile = t;
                 s.tile_w = tw;
                 s.tile_h = th;
@@ -264,12 +267,16 @@ Segment price_generic(const fz_plan& p, int a, int b, int req_w, int req_h, int 
         }
         if (s.tile < 0) return s;
         if (temporal) {
-            s.tpb = tt;
-            items = ceil((double)p.W / s.tile_w) * ceil((double)p.H / s.tile_h) * ceil((double)p.T / tt);
+            s.tpb = best_tt;
+            items = ceil((double)p.W / s.tile_w) * ceil((double)p.H / s.tile_h) * ceil((double)p.T / s.tpb);
+            s.ckpt = n_ck > 0 && s.tpb < p.T;
         }
     }
     const double bin = dt_bytes(p.stages[a].in_dtype);
     s.bytes_per_px = bin + 4.0 + (ht > 0 && !s.streaming ? bin * ht / s.tpb : 0.0);
+    // checkpointed IIRs: a first pass reads the input once more and writes each IIR's
+    // double state at every run boundary, which the work items read back
+    if (s.ckpt) s.bytes_per_px += bin + 16.0 * n_ck / s.tpb;
     s.cost = s.bytes_per_px * P * p.T;
     if (temporal && items > 0.0 && items < G_FILL_ITEMS) s.cost *= G_FILL_ITEMS / items;
     return s;
@@ -715,7 +722,10 @@ fz_status fz_plan_set_segment_config(fz_plan* plan, int32_t i, int32_t engine, i
             if (!ok) return fail(FZ_E_UNSUPPORTED, "fz_plan_set_segment_config: not a generated-kernel tile");
         }
         const Segment& o = plan->segs[i];
-        Segment s = price_group(*plan, o.first, o.last, tile_w, tile_h, 0, FZ_ENGINE_JIT);
+        Segment s = price_group(*plan, o.first, o.last, tile_w, tile_h, frames_per_block, FZ_ENGINE_JIT);
+        if (s.refused)
+            return fail(FZ_E_UNSUPPORTED, "fz_plan_set_segment_config: the group holds an IIR after a window stage, "
+                                          "whose work items march every frame of the clip");
         if (!(s.cost < kInf)) return fail(FZ_E_LDS, "fz_plan_set_segment_config: configuration does not fit the budget");
         if (s.engine != FZ_ENGINE_JIT)
             return fail(FZ_E_UNSUPPORTED, "fz_plan_set_segment_config: no generated kernel for this group");

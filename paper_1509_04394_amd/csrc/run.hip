@@ -23,13 +23,22 @@ static size_t group_out_bytes(const fz_plan& p, const Segment& s)
     return (size_t)p.W * p.H * p.T * st.out_ch * dt_bytes(st.out_dtype);
 }
 
-// Two ping-pong slots, each as large as the largest intermediate.
-size_t workspace_bytes(const fz_plan& p)
+// Two ping-pong slots, each as large as the largest intermediate, then the
+// largest group's IIR checkpoints (generic groups run in frame runs shorter
+// than the clip).
+static size_t slots_bytes(const fz_plan& p)
 {
     size_t mx = 0;
     for (size_t i = 0; i + 1 < p.segs.size(); ++i) mx = std::max(mx, group_out_bytes(p, p.segs[i]));
     if (mx == 0) return 0;
     return (p.segs.size() > 2 ? 2 : 1) * align256(mx);
+}
+
+size_t workspace_bytes(const fz_plan& p)
+{
+    size_t ck = 0;
+    for (const Segment& g : p.segs) ck = std::max(ck, ckpt_bytes(p, g));
+    return slots_bytes(p) + align256(ck);
 }
 
 fz_status run_plan(const fz_plan& p, const void* d_in, void* d_out, fz_point* d_points, uint32_t* d_count,
@@ -38,7 +47,8 @@ fz_status run_plan(const fz_plan& p, const void* d_in, void* d_out, fz_point* d_
     (void)ws_bytes;
     (void)hipGetLastError();  // drop an error latched by earlier, unrelated runtime calls
     hipStream_t s = (hipStream_t)stream;
-    const size_t slot = p.segs.size() > 1 ? align256(workspace_bytes(p) / (p.segs.size() > 2 ? 2 : 1)) : 0;
+    const size_t slot = p.segs.size() > 1 ? align256(slots_bytes(p) / (p.segs.size() > 2 ? 2 : 1)) : 0;
+    void* ckpt = d_ws ? (void*)((char*)d_ws + slots_bytes(p)) : nullptr;
     if (d_count && p.has_nms) {
         hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, s, d_count);
         hipError_t e = hipGetLastError();
@@ -67,7 +77,7 @@ fz_status run_plan(const fz_plan& p, const void* d_in, void* d_out, fz_point* d_
         if (!group_has_nms) sp.count = nullptr;
         hipError_t e;
         if (p.generic) {
-            e = (hipError_t)launch_generic(p, g, sp.in, sp.out, s);
+            e = (hipError_t)launch_generic(p, g, sp.in, sp.out, ckpt, s);
         } else if (g.engine == FZ_ENGINE_ROW) {
             RowParams rp{};
             rp.sp = sp;

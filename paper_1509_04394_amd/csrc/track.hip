@@ -164,15 +164,13 @@ __device__ __forceinline__ bool cand_less(const Cand& a, const Cand& b)
     return a.pj < b.pj;
 }
 
-__device__ __forceinline__ void put_record(fz_track* out, uint32_t* count, uint32_t cap, int t, const DevTrack& tr,
-                                           int status)
+__device__ __forceinline__ void put_record(fz_track* out, uint32_t k, uint32_t cap, int t, const DevTrack& tr)
 {
-    const uint32_t k = atomicAdd(&count[0], 1u);
     if (k < cap) {
         fz_track r;
         r.t = (uint32_t)t;
         r.id = (uint32_t)tr.id;
-        r.status = status;
+        r.status = tr.status;
         r.pad = 0;
         r.x = tr.s[0];
         r.y = tr.s[1];
@@ -182,6 +180,21 @@ __device__ __forceinline__ void put_record(fz_track* out, uint32_t* count, uint3
     }
 }
 
+// Slots for the records of the lanes in `m` (one atomic per wavefront):
+// returns this lane's slot.
+__device__ __forceinline__ uint32_t reserve(uint32_t* count, uint64_t m, int lane)
+{
+    uint32_t base = 0;
+    if (lane == 0 && m) base = atomicAdd(&count[0], (uint32_t)__popcll(m));
+    base = __shfl(base, 0);
+    return base + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+}
+
+// One wavefront marches the frames.  Every lane owns the tracks lane,
+// lane + 64, ... of the current list: it predicts them and lists their gated
+// candidates in one pass (the track read once from the workspace), and later
+// updates them; compaction and new tracks use ballot prefix sums, and the
+// records' slots are reserved with one atomic per 64 lanes.
 __global__ __launch_bounds__(TRK_THREADS) void k_trk_run(const int2* bucket, const uint32_t* offs, int T,
                                                           fz_track_opts o, DevTrack* buf0, DevTrack* buf1,
                                                           uint32_t max_tracks, fz_track* out, uint32_t* count,
@@ -189,11 +202,11 @@ __global__ __launch_bounds__(TRK_THREADS) void k_trk_run(const int2* bucket, con
 {
     __shared__ int2 pin[TRK_MAX_POINTS];   // the frame's points as loaded
     __shared__ int2 pts[TRK_MAX_POINTS];   // sorted by (y, x)
-    __shared__ Cand cand[TRK_MAX_CANDS];
-    __shared__ int16_t order[TRK_MAX_CANDS];  // order[rank] = candidate index
+    __shared__ Cand cand[TRK_MAX_CANDS];   // as listed
+    __shared__ Cand cs[TRK_MAX_CANDS];     // in increasing (d2, id, point) order
     __shared__ uint8_t ptaken[TRK_MAX_POINTS];
     __shared__ int16_t tmatch[FZ_TRACK_MAX_TRACKS];  // point matched to each track, -1 none
-    __shared__ uint32_t s_nc, s_flags, s_alive, s_new;
+    __shared__ uint32_t s_nc, s_flags;
     const int lane = threadIdx.x;
     const KModel M(o.q, o.r);
     DevTrack* cur = buf0;
@@ -224,12 +237,16 @@ __global__ __launch_bounds__(TRK_THREADS) void k_trk_run(const int2* bucket, con
             }
             pts[rank] = a;
         }
-        // 2. predict every live track
+        __syncthreads();
+        // 2. predict every live track and list its gated candidate pairs
         for (uint32_t i = lane; i < ntr; i += TRK_THREADS) {
             DevTrack& tr = cur[i];
-            double sp[4], FP[16], Pp[16], HP[8], S[4];
-            mm<4, 4, 1>(M.F, tr.s, sp);
-            mm<4, 4, 4>(M.F, tr.P, FP);
+            double sp[4], P0[16], FP[16], Pp[16], HP[8], S[4], Si[4];
+            for (int e = 0; e < 4; ++e) sp[e] = tr.s[e];
+            for (int e = 0; e < 16; ++e) P0[e] = tr.P[e];
+            double s1[4];
+            mm<4, 4, 1>(M.F, sp, s1);
+            mm<4, 4, 4>(M.F, P0, FP);
             mm<4, 4, 4>(FP, M.Ft, Pp);
             for (int e = 0; e < 16; ++e) Pp[e] = Pp[e] + M.Q[e];
             mm<2, 4, 4>(M.H, Pp, HP);
@@ -237,55 +254,53 @@ __global__ __launch_bounds__(TRK_THREADS) void k_trk_run(const int2* bucket, con
             S[0] = S[0] + M.r;
             S[3] = S[3] + M.r;
             const double det = S[0] * S[3] - S[1] * S[2];
-            for (int e = 0; e < 4; ++e) tr.s[e] = sp[e];
+            Si[0] = S[3] / det;
+            Si[1] = -S[1] / det;
+            Si[2] = -S[2] / det;
+            Si[3] = S[0] / det;
+            for (int e = 0; e < 4; ++e) tr.s[e] = s1[e];
             for (int e = 0; e < 16; ++e) tr.P[e] = Pp[e];
-            tr.Si[0] = S[3] / det;
-            tr.Si[1] = -S[1] / det;
-            tr.Si[2] = -S[2] / det;
-            tr.Si[3] = S[0] / det;
-        }
-        __syncthreads();
-        // 3. gated candidate pairs
-        const uint32_t pairs = ntr * np;
-        for (uint32_t e = lane; e < pairs; e += TRK_THREADS) {
-            const uint32_t i = e / np, j = e - i * np;
-            const DevTrack& tr = cur[i];
-            double hs[2], nu[2];
-            mm<2, 4, 1>(M.H, tr.s, hs);
-            nu[0] = (double)pts[j].x - hs[0];
-            nu[1] = (double)pts[j].y - hs[1];
-            double d2 = 0.0;
-            for (int a = 0; a < 2; ++a)
-                for (int b = 0; b < 2; ++b) d2 = d2 + nu[a] * tr.Si[2 * a + b] * nu[b];
-            if (d2 <= o.gate) {
-                const uint32_t k = atomicAdd(&s_nc, 1u);
-                if (k < (uint32_t)TRK_MAX_CANDS) {
-                    Cand c;
-                    c.d2 = d2;
-                    c.id = tr.id;
-                    c.ti = (int16_t)i;
-                    c.pj = (int16_t)j;
-                    cand[k] = c;
-                } else {
-                    atomicOr(&s_flags, (uint32_t)FZ_TRACK_TOO_MANY_CANDIDATES);
+            for (int e = 0; e < 4; ++e) tr.Si[e] = Si[e];
+            tmatch[i] = -1;
+            double hs[2];
+            mm<2, 4, 1>(M.H, s1, hs);
+            const int32_t id = tr.id;
+            for (uint32_t j = 0; j < np; ++j) {
+                double nu[2];
+                nu[0] = (double)pts[j].x - hs[0];
+                nu[1] = (double)pts[j].y - hs[1];
+                double d2 = 0.0;
+                for (int a = 0; a < 2; ++a)
+                    for (int b = 0; b < 2; ++b) d2 = d2 + nu[a] * Si[2 * a + b] * nu[b];
+                if (d2 <= o.gate) {
+                    const uint32_t k = atomicAdd(&s_nc, 1u);
+                    if (k < (uint32_t)TRK_MAX_CANDS) {
+                        Cand c;
+                        c.d2 = d2;
+                        c.id = id;
+                        c.ti = (int16_t)i;
+                        c.pj = (int16_t)j;
+                        cand[k] = c;
+                    } else {
+                        atomicOr(&s_flags, (uint32_t)FZ_TRACK_TOO_MANY_CANDIDATES);
+                    }
                 }
             }
         }
         __syncthreads();
         const uint32_t nc = min(s_nc, (uint32_t)TRK_MAX_CANDS);
-        // 4. candidates in increasing (d2, id, point) order
+        // 3. candidates in increasing (d2, id, point) order (keys are distinct)
         for (uint32_t c = lane; c < nc; c += TRK_THREADS) {
             const Cand a = cand[c];
             uint32_t rank = 0;
             for (uint32_t k = 0; k < nc; ++k) rank += cand_less(cand[k], a) ? 1u : 0u;
-            order[rank] = (int16_t)c;
+            cs[rank] = a;
         }
-        for (uint32_t i = lane; i < ntr; i += TRK_THREADS) tmatch[i] = -1;
         __syncthreads();
-        // 5. greedy association by one lane
+        // 4. greedy association by one lane
         if (lane == 0) {
             for (uint32_t k = 0; k < nc; ++k) {
-                const Cand c = cand[order[k]];
+                const Cand c = cs[k];
                 if (tmatch[c.ti] < 0 && !ptaken[c.pj]) {
                     tmatch[c.ti] = c.pj;
                     ptaken[c.pj] = 1;
@@ -293,90 +308,79 @@ __global__ __launch_bounds__(TRK_THREADS) void k_trk_run(const int2* bucket, con
             }
         }
         __syncthreads();
-        // 6. update or count a miss
-        for (uint32_t i = lane; i < ntr; i += TRK_THREADS) {
-            DevTrack& tr = cur[i];
-            const int j = tmatch[i];
-            if (j >= 0) {
-                double hs[2], nu[2], PHt[8], K[8], Knu[4], KH[16], IKH[16], Pn[16];
-                mm<2, 4, 1>(M.H, tr.s, hs);
-                nu[0] = (double)pts[j].x - hs[0];
-                nu[1] = (double)pts[j].y - hs[1];
-                mm<4, 4, 2>(tr.P, M.Ht, PHt);
-                mm<4, 2, 2>(PHt, tr.Si, K);
-                mm<4, 2, 1>(K, nu, Knu);
-                for (int e = 0; e < 4; ++e) tr.s[e] = tr.s[e] + Knu[e];
-                mm<4, 2, 4>(K, M.H, KH);
-                for (int a = 0; a < 4; ++a)
-                    for (int b = 0; b < 4; ++b) IKH[4 * a + b] = (a == b ? 1.0 : 0.0) - KH[4 * a + b];
-                mm<4, 4, 4>(IKH, tr.P, Pn);
-                for (int e = 0; e < 16; ++e) tr.P[e] = Pn[e];
-                tr.miss = 0;
-                tr.status = 1;
-            } else {
-                tr.miss += 1;
-                tr.status = 0;
-            }
-        }
-        __syncthreads();
-        // 7. compaction in id order, then the new tracks (ids in point order)
-        if (lane == 0) {
-            s_alive = 0u;
-            s_new = 0u;
-        }
-        __syncthreads();
+        // 5. update or count a miss; survivors to the next list in id order, with their records
+        uint32_t n_alive = 0;
         for (uint32_t c0 = 0; c0 < ntr; c0 += TRK_THREADS) {
             const uint32_t i = c0 + lane;
-            const bool alive = i < ntr && cur[i].miss <= o.max_miss;
-            const uint64_t m = __ballot(alive);
-            const uint32_t before = __popcll(m & ((1ull << lane) - 1ull));
-            const uint32_t base = s_alive;
-            if (alive) {
-                const DevTrack tr = cur[i];
-                nxt[base + before] = tr;
-                put_record(out, count, cap, t, tr, tr.status);
+            DevTrack tr;
+            bool alive = false;
+            if (i < ntr) {
+                tr = cur[i];
+                const int j = tmatch[i];
+                if (j >= 0) {
+                    double hs[2], nu[2], PHt[8], K[8], Knu[4], KH[16], IKH[16], Pn[16];
+                    mm<2, 4, 1>(M.H, tr.s, hs);
+                    nu[0] = (double)pts[j].x - hs[0];
+                    nu[1] = (double)pts[j].y - hs[1];
+                    mm<4, 4, 2>(tr.P, M.Ht, PHt);
+                    mm<4, 2, 2>(PHt, tr.Si, K);
+                    mm<4, 2, 1>(K, nu, Knu);
+                    for (int e = 0; e < 4; ++e) tr.s[e] = tr.s[e] + Knu[e];
+                    mm<4, 2, 4>(K, M.H, KH);
+                    for (int a = 0; a < 4; ++a)
+                        for (int b = 0; b < 4; ++b) IKH[4 * a + b] = (a == b ? 1.0 : 0.0) - KH[4 * a + b];
+                    mm<4, 4, 4>(IKH, tr.P, Pn);
+                    for (int e = 0; e < 16; ++e) tr.P[e] = Pn[e];
+                    tr.miss = 0;
+                    tr.status = 1;
+                } else {
+                    tr.miss += 1;
+                    tr.status = 0;
+                }
+                alive = tr.miss <= o.max_miss;
             }
-            __syncthreads();
-            if (lane == 0) s_alive = base + (uint32_t)__popcll(m);
-            __syncthreads();
+            const uint64_t m = __ballot(alive);
+            const uint32_t slot = reserve(count, m, lane);
+            if (alive) {
+                nxt[n_alive + (uint32_t)__popcll(m & ((1ull << lane) - 1ull))] = tr;
+                put_record(out, slot, cap, t, tr);
+            }
+            n_alive += (uint32_t)__popcll(m);
         }
-        const uint32_t n_alive = s_alive;
+        // 6. every point left over starts a track (ids in point order)
+        uint32_t n_new = 0;
         for (uint32_t c0 = 0; c0 < np; c0 += TRK_THREADS) {
             const uint32_t j = c0 + lane;
             const bool fresh = j < np && !ptaken[j];
-            const uint64_t m = __ballot(fresh);
-            const uint32_t before = __popcll(m & ((1ull << lane) - 1ull));
-            const uint32_t base = s_new;
-            if (fresh) {
-                const uint32_t slot = n_alive + base + before;
-                if (slot < max_tracks) {
-                    DevTrack tr;
-                    tr.id = (int32_t)(next_id + base + before);
-                    tr.miss = 0;
-                    tr.status = 2;
-                    tr.pad = 0;
-                    tr.s[0] = (double)pts[j].x;
-                    tr.s[1] = (double)pts[j].y;
-                    tr.s[2] = 0.0;
-                    tr.s[3] = 0.0;
-                    for (int e = 0; e < 16; ++e) tr.P[e] = 0.0;
-                    tr.P[0] = o.r;
-                    tr.P[5] = o.r;
-                    tr.P[10] = o.v0;
-                    tr.P[15] = o.v0;
-                    for (int e = 0; e < 4; ++e) tr.Si[e] = 0.0;
-                    nxt[slot] = tr;
-                    put_record(out, count, cap, t, tr, 2);
-                } else {
-                    atomicOr(&s_flags, (uint32_t)FZ_TRACK_TOO_MANY_TRACKS);
-                }
+            const uint32_t before = (uint32_t)__popcll(__ballot(fresh) & ((1ull << lane) - 1ull));
+            const uint32_t pos = n_alive + n_new + before;
+            const bool keep = fresh && pos < max_tracks;
+            if (fresh && !keep) atomicOr(&s_flags, (uint32_t)FZ_TRACK_TOO_MANY_TRACKS);
+            const uint64_t m = __ballot(keep);
+            const uint32_t slot = reserve(count, m, lane);
+            if (keep) {
+                DevTrack tr;
+                tr.id = (int32_t)(next_id + n_new + before);
+                tr.miss = 0;
+                tr.status = 2;
+                tr.pad = 0;
+                tr.s[0] = (double)pts[j].x;
+                tr.s[1] = (double)pts[j].y;
+                tr.s[2] = 0.0;
+                tr.s[3] = 0.0;
+                for (int e = 0; e < 16; ++e) tr.P[e] = 0.0;
+                tr.P[0] = o.r;
+                tr.P[5] = o.r;
+                tr.P[10] = o.v0;
+                tr.P[15] = o.v0;
+                for (int e = 0; e < 4; ++e) tr.Si[e] = 0.0;
+                nxt[pos] = tr;
+                put_record(out, slot, cap, t, tr);
             }
-            __syncthreads();
-            if (lane == 0) s_new = base + (uint32_t)__popcll(m);
-            __syncthreads();
+            n_new += (uint32_t)__popcll(__ballot(fresh));
         }
-        next_id += s_new;
-        ntr = min(n_alive + s_new, max_tracks);
+        next_id += n_new;
+        ntr = min(n_alive + n_new, max_tracks);
         DevTrack* sw = cur;
         cur = nxt;
         nxt = sw;

@@ -114,3 +114,29 @@ def test_large_box_and_batch(dev):
         for (v, _), o in zip(xs, outs):
             ref, _ = run(CHAINS["well"], v, dev)
             assert np.array_equal(o.cpu().numpy()[0], ref), rep
+
+
+def test_generated_marching_kernels_equal_interpreted(dev):
+    """Groups with temporal stages (an IIR, stencils over several frames, an
+    IIR after a window stage) as generated frame-marching kernels: the same
+    bits as the interpreted marching kernel, for checkpointed and whole-clip
+    IIR groups and several frame runs, and within the oracle's bound."""
+    from tests.test_gpu_temporal import MIXED, PAPER5, SPATIO
+    vol = synth.video(133, 77, 17, seed=75)
+    for name, spec in (("paper5", PAPER5), ("spatio", SPATIO), ("mixed", MIXED)):
+        ref, _ = run(spec, vol, dev, partition=[])
+        g, plan = run(spec, vol, dev, partition=[], engine="jit")
+        (s,) = plan.segment_info()
+        say("marching", name, s.engine, s.tile_w, s.tile_h, s.frames_per_block)
+        assert s.engine == fz.FZ_ENGINE_JIT
+        assert np.array_equal(g, ref), name
+        if name != "mixed":  # runs shorter than the clip (checkpointed IIR, look-back rings)
+            T, H, W = vol.shape
+            for tpb in (1, 4, 16):
+                plan = fz.Plan(spec, W, H, T, partition=[])
+                plan.set_segment_config(0, engine="jit", tile=(32, 16), frames_per_block=tpb)
+                out, _, _ = plan.run(torch.from_numpy(vol).to(dev))
+                torch.cuda.synchronize()
+                assert np.array_equal(out.cpu().numpy()[0], ref), (name, tpb)
+        ref_o, bound = parity.generic_reference(oracle, spec, vol)
+        parity.assert_within_bound(g, ref_o, bound, f"jit marching {name}")

@@ -134,11 +134,17 @@ def test_tiles_and_frame_runs_same_bits(dev, tile):
                                                                             frames_per_block=tpb)})
         assert plan.segment_info()[0].frames_per_block == min(tpb, 17)
         assert np.array_equal(g, ref), (tile, tpb)
-    # an IIR group keeps the whole clip per work item whatever the tile
-    ref, _ = run_gpu(PAPER5, vol, dev, partition=[])
-    g, plan = run_gpu(PAPER5, vol, dev, partition=[], configs={0: dict(engine="tile", tile=tile)})
+    # IIRs that lead the group resume from checkpoints: every frame run gives the same bits
+    ref, _ = run_gpu(PAPER5, vol, dev, partition=[], configs={0: dict(engine="tile", tile=tile,
+                                                                      frames_per_block=17)})
+    for tpb in (1, 2, 5, 8, 16):
+        g, plan = run_gpu(PAPER5, vol, dev, partition=[], configs={0: dict(engine="tile", tile=tile,
+                                                                          frames_per_block=tpb)})
+        assert plan.segment_info()[0].frames_per_block == tpb
+        assert np.array_equal(g, ref), (tile, tpb)
+    # an IIR after a window stage keeps whole-clip work items
+    g, plan = run_gpu(MIXED, vol, dev, partition=[], configs={0: dict(engine="tile", tile=tile)})
     assert plan.segment_info()[0].frames_per_block == 17
-    assert np.array_equal(g, ref), tile
 
 
 @pytest.mark.parametrize("size", [(1, 1, 5), (3, 2, 4), (7, 5, 9), (200, 3, 6)], ids=str)

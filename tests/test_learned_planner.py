@@ -7,7 +7,7 @@ import numpy as np
 import pytest
 
 from oracle import mlp
-from paper_1509_04394_amd import fz
+from paper_1509_04394_amd import costmodel, fz
 
 F = fz.fz_cost_n_features()
 
@@ -91,3 +91,12 @@ def test_committed_weights_plan_random_chains_optimally():
         want, groups = P.best(c, n)
         assert plan.cost == pytest.approx(want, rel=1e-12)
         assert plan.segments == [b for (_, b) in groups]
+
+
+def test_fixed_held_out_cases_are_not_training_cases():
+    """The held-out fixed-chain workloads of the cost-model test are neither in
+    the fine-tuning grid nor in the original campaign's training split."""
+    held = set(costmodel.FIXED_HELD_OUT)
+    assert len(held) >= 6
+    assert not held & set(costmodel.fixed_campaign()["train"])
+    assert not held & set(costmodel.campaign()["train"])

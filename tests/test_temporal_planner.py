@@ -80,9 +80,16 @@ def test_engines_and_frame_runs():
     p = fz.Plan([("iir", 0.25), ("point", "abs", 0.0, 0.0)], 800, 600, T)
     (s,) = p.segment_info()
     assert s.engine == fz.FZ_ENGINE_STREAM and s.frames_per_block == T
+    # an IIR before the window stage is checkpointed: 8-frame runs here (64x32 tiles: 247 x 7 runs
+    # already leave fewer than two fills of work items at 16), the checkpoints priced per run
     p = fz.Plan([("iir", 0.25), ("box", 1, 1)], 800, 600, T, partition=[])
     (s,) = p.segment_info()
-    assert s.engine == fz.FZ_ENGINE_TILE and s.frames_per_block == T and s.halo_t == 0
+    assert s.engine == fz.FZ_ENGINE_TILE and s.frames_per_block == 8 and s.halo_t == 0
+    assert s.bytes_per_px == pytest.approx(1 + 4 + 1 + 16.0 / 8)
+    # an IIR after a window stage cannot resume from a checkpoint: whole-clip runs
+    p = fz.Plan([("box", 1, 1), ("iir", 0.25)], 800, 600, T, partition=[])
+    (s,) = p.segment_info()
+    assert s.engine == fz.FZ_ENGINE_TILE and s.frames_per_block == T
     # a stencil two frames back: the frame run follows Eq. 6 with beta = W H T / 1024
     p = fz.Plan([("stencil", 1, 1, W3T), ("box", 1, 1)], 800, 600, 1000, partition=[])
     (s,) = p.segment_info()
@@ -93,16 +100,23 @@ def test_engines_and_frame_runs():
     assert s.bytes_per_px == pytest.approx(1 + 4 + 2.0 / s.frames_per_block)
 
 
-def test_iir_frame_run_requests_are_refused():
+def test_iir_frame_run_requests():
+    """A frame run shorter than the clip is refused for a group whose IIR
+    follows a window stage (its state cannot be checkpointed), and kept for
+    one whose IIRs lead (checkpointed)."""
     with pytest.raises(fz.FzError) as e:
-        fz.Plan([("iir", 0.5), ("box", 1, 1)], 128, 64, 20, frames_per_block=4)
+        fz.Plan([("box", 1, 1), ("iir", 0.5)], 128, 64, 20, frames_per_block=4)
     assert e.value.code == fz.FZ_E_UNSUPPORTED
-    p = fz.Plan([("iir", 0.5), ("box", 1, 1)], 128, 64, 20, partition=[])
+    p = fz.Plan([("box", 1, 1), ("iir", 0.5)], 128, 64, 20, partition=[])
     with pytest.raises(fz.FzError) as e:
         p.set_segment_config(0, engine="tile", tile=(32, 32), frames_per_block=4)
     assert e.value.code == fz.FZ_E_UNSUPPORTED
     p.set_segment_config(0, engine="tile", tile=(32, 32), frames_per_block=20)
     assert p.segment_info()[0].frames_per_block == 20
+    p = fz.Plan([("iir", 0.5), ("box", 1, 1)], 128, 64, 20, frames_per_block=4)
+    assert p.segment_info()[0].frames_per_block == 4
+    # the checkpoints live in the workspace: (20 / 4 - 1) runs x 128 x 64 states of 8 bytes
+    assert p.workspace_bytes >= 4 * 128 * 64 * 8
 
 
 def test_weight_store_limits_group_size():
