@@ -18,7 +18,7 @@ from . import fz
 
 TILES = [(64, 16), (32, 32), (64, 32)]
 BANDS = [32, 44, 55, 67, 86, 100, 150]
-FRAME_RUNS = [8, 12, 16, 24]
+FRAME_RUNS = [1, 2, 4, 8, 16]
 ROW_SLOTS = 256 * 4 * 5  # wavefronts the device holds at once (5 per SIMD, the RGB row kernel)
 ROW_HALO, ROW_SPAN = 6, 128  # rows of halo per band side; columns per strip (64 lanes x 2)
 

@@ -79,6 +79,8 @@ Segment price_generic(const fz_plan& p, int a, int b, int req_w, int req_h, int 
 void eq6_box(double beta, double dx, double dt, double* x, double* t);
 int launch_generic(const fz_plan& p, const Segment& g, const void* in, void* out, void* ckpt, void* stream);  // hipError_t
 size_t ckpt_bytes(const fz_plan& p, const Segment& g);  // IIR checkpoints of group g (0 if none)
+// Frame-boundary exchange of group g (a frame-difference row group; 0 otherwise).
+size_t exchange_bytes(const fz_plan& p, const Segment& g);
 
 // Learned prices (cost.cpp)
 constexpr int COST_FEATURES = 20;

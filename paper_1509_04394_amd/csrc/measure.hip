@@ -26,16 +26,20 @@ static size_t stage_out_bytes(const fz_plan& p, int k)
 // Three buffers as large as the largest stage output (the input of the groups
 // being timed, the output they write, the next stage's input), a counter, and
 // the IIR checkpoints of the largest candidate group.
+static size_t group_ws(const fz_plan& p, const Segment& g) { return align256(ckpt_bytes(p, g)) + exchange_bytes(p, g); }
+
+// The largest single-group workspace (IIR checkpoints, frame-boundary
+// exchange) of any group the measurement may time.
 static size_t measure_ckpt_bytes(const fz_plan& p)
 {
     size_t ck = 0;
     for (int a = 0; a < p.n; ++a)
         for (int b = a; b < p.n; ++b) {
-            ck = std::max(ck, ckpt_bytes(p, price_group(p, a, b, 0, 0, 0, FZ_ENGINE_AUTO)));
+            ck = std::max(ck, group_ws(p, price_group(p, a, b, 0, 0, 0, FZ_ENGINE_AUTO)));
             for (int t = 0; t < N_TILES; ++t)
-                ck = std::max(ck, ckpt_bytes(p, price_group(p, a, b, tile_w(t), tile_h(t), 0, FZ_ENGINE_TILE)));
+                ck = std::max(ck, group_ws(p, price_group(p, a, b, tile_w(t), tile_h(t), 0, FZ_ENGINE_TILE)));
         }
-    return align256(ck);
+    return ck;
 }
 
 size_t measure_workspace_bytes(const fz_plan& p)

@@ -123,7 +123,11 @@ Segment price_group(const fz_plan& p, int a, int b, int req_w, int req_h, int re
     // Compulsory traffic (Eq. 2 per group): the group's input once, its output
     // once; a multi-frame group re-reads its temporal halo once per frame run.
     const double bin = op_bytes_in(p.stages[a].op), bout = op_bytes_out(p.stages[b].op);
-    const double temporal = s.halo_t > 0 ? bin * s.halo_t / (s.streaming ? 1.0 : (double)s.tpb) : 0.0;
+    // (the Harris row kernel's frame-difference groups exchange the frame
+    // before a run between items instead: no re-read)
+    const bool exchange = s.engine == FZ_ENGINE_ROW && !s.row_gen && chain_op(ch, B) == FZ_OP_FRAMEDIFF;
+    const double temporal =
+        s.halo_t > 0 && !exchange ? bin * s.halo_t / (s.streaming ? 1.0 : (double)s.tpb) : 0.0;
     s.bytes_per_px = bin + bout + temporal;
     s.cost = s.bytes_per_px * (double)p.W * p.H * p.T;
     return s;

@@ -22,8 +22,13 @@
 //     the last row it copies it into the slots of the rows below, one slot per
 //     iteration, once the consumer no longer needs the slot's old row;
 //   * the suppression mask feeds the frame difference through a per-wavefront
-//     LDS row of previous-frame mask bits; a work item then covers a run of
-//     frames, preceded by the frame before them (one frame of temporal halo).
+//     LDS row of previous-frame mask bits; a work item covers a run of frames.
+//     The difference at the first frame of a run needs the mask of the frame
+//     before it, which the item of the previous run computes anyway: the two
+//     items meet at their shared frame boundary (see row_exchange) instead of
+//     the later one computing that frame again.  Without the exchange buffers
+//     an item first recomputes the frame before its run (one frame of
+//     temporal halo).
 // The input rows are prefetched two iterations ahead.
 #pragma once
 
@@ -40,6 +45,13 @@ struct RowParams {
     int strip_step;  // 64K - 2*ROW_HX
     int band_h;
     int tt;          // frames per work item
+    // frame-boundary exchange (frame difference; null: recompute the frame
+    // before each run instead): per boundary between runs c-1 and c of one
+    // strip and band, two mask areas of band_h * K words (the earlier run's
+    // last frame, the later run's first frame) and one arrival counter,
+    // zeroed before the launch
+    uint64_t* xmask;
+    uint32_t* xcount;
 };
 
 // Value of the lane to the left (wave_shr:1) / right (wave_shl:1).  At a
@@ -155,7 +167,8 @@ struct RowCtx {
     int W, Hf, x0, lane, y0, y1, t;
     int row_bytes;            // bytes per input row
     int lane_in, lane_out;    // byte offset of this lane's first column in an input / output row
-    bool real;
+    bool real;                // frame t is one of the item's own frames (feature points)
+    bool store;               // its output is written now (not at a frame boundary exchange)
     uint32_t valid;           // bit k: column k of this lane is an output column of the strip
     int lo_in, hi_in, lo_g, hi_g, lo_s, hi_s, lo_b, hi_b;
     // iteration j computes a stage's row iff (unsigned)(j - j*) < n*: the rows
@@ -355,7 +368,7 @@ __device__ __forceinline__ void row_step(RowState<K, RGB>& st, const RowCtx& c, 
             *slot = (uint8_t)bits;
             outbits = bits ^ prev;
         }
-        if (c.real) {
+        if (c.store) {
             const __amdgpu_buffer_rsrc_t r = out_rsrc(c.out_frame, (uint32_t)(c.W * c.Hf));
             const int soff = rn * c.W;  // uniform row offset
 #pragma unroll
@@ -382,16 +395,104 @@ __device__ __forceinline__ void row_block(RowState<K, RGB>& st, const RowCtx& c,
     ((jb + U < n ? row_step<K, RGB, DIFF, EL, ER, U>(st, c, p, jb + U) : void()), ...);
 }
 
+// One side of a frame boundary between two runs of frames of the same strip
+// and band: the mask of the frame next to the boundary on this side (held in
+// the LDS row of previous-frame bits) is published as K ballot words per row;
+// the side that arrives second reads the other side's words and writes the
+// frame difference of the later run's first frame (out_frame): the exclusive
+// or of the two masks, the same bits the later item would have formed from a
+// recomputed frame.  Neither side waits for the other.
+//
+// Every access to the exchange words and the counter is a device-scope
+// atomic read-modify-write, which the device performs coherently across its
+// XCDs; the words are published with exchanges whose results are waited for
+// before the arrival is counted, and read (fetch-or 0) only after the count
+// has come back.  No fence is used: an agent-scope release or acquire fence
+// writes back or invalidates the XCD's whole L2, which cost the kernel a
+// quarter of its speed (the strips of neighbouring items share input rows
+// in L2).
+template <int K>
+__device__ __forceinline__ void row_exchange(const RowCtx& c, uint64_t* mine, uint64_t* other, uint32_t* cnt,
+                                             uint8_t* out_frame)
+{
+    constexpr int RPC = 64 / K;  // rows per chunk: one word per lane
+    const int nrow = c.y1 - c.y0;
+    uint64_t sink = 0;
+    for (int r0 = 0; r0 < nrow; r0 += RPC) {
+        const int nr = min(RPC, nrow - r0);
+        uint64_t w = 0;  // lane (r - r0) K + k: word k of row r
+        for (int r = 0; r < nr; ++r) {
+            const uint32_t b = c.prev[(r0 + r) * 64 + c.lane];
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const uint64_t m = __ballot((b >> k & 1u) != 0u);
+                if (c.lane == r * K + k) w = m;
+            }
+        }
+        if (c.lane < nr * K)
+            sink |= __hip_atomic_exchange(mine + r0 * K + c.lane, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    // the exchanges have returned (so they are performed) before the arrival
+    // is counted: the empty asm needs their results, and orders the memory
+    // operations around it
+    const uint32_t sl = (uint32_t)sink, sh = (uint32_t)(sink >> 32);
+    asm volatile("" ::"v"(sl), "v"(sh) : "memory");
+    uint32_t old = 0;
+    if (c.lane == 0) old = __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    old = __builtin_amdgcn_readfirstlane(__shfl(old, 0));
+    if (old == 0u) return;
+    const __amdgpu_buffer_rsrc_t rs = out_rsrc(out_frame, (uint32_t)(c.W * c.Hf));
+    for (int r0 = 0; r0 < nrow; r0 += RPC) {
+        const int nr = min(RPC, nrow - r0);
+        uint64_t w = 0;
+        if (c.lane < nr * K)
+            w = __hip_atomic_fetch_or(other + r0 * K + c.lane, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        for (int r = 0; r < nr; ++r) {
+            const uint32_t b = c.prev[(r0 + r) * 64 + c.lane];
+            uint32_t o = 0;
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const uint64_t m = __shfl(w, r * K + k);
+                o |= (uint32_t)(m >> c.lane & 1u) << k;
+            }
+            const uint32_t outbits = b ^ o;
+            const int soff = (c.y0 + r0 + r) * c.W;
+#pragma unroll
+            for (int k = 0; k < K; ++k)
+                __builtin_amdgcn_raw_buffer_store_b8((outbits >> k & 1u) ? (uint8_t)255 : (uint8_t)0, rs,
+                                                     (c.valid >> k & 1u) ? c.lane_out + k : DROP, soff, 0);
+        }
+    }
+}
+
+// Exchange areas of the boundary before run `chunk` (chunk >= 1).
+struct RowBoundary {
+    uint64_t* last;   // the earlier run's last frame
+    uint64_t* first;  // the later run's first frame
+    uint32_t* cnt;
+};
+template <int K>
+__device__ __forceinline__ RowBoundary row_boundary(const RowParams& rp, int strip, int band, int chunk)
+{
+    const size_t b = ((size_t)(chunk - 1) * rp.nbands + band) * rp.nstrips + strip;
+    const size_t words = (size_t)rp.band_h * K;
+    return RowBoundary{rp.xmask + 2 * b * words, rp.xmask + (2 * b + 1) * words, rp.xcount + b};
+}
+
 // All frames of one work item.
 template <int K, bool RGB, bool DIFF, bool EL, bool ER>
-__device__ __forceinline__ void row_frames(RowCtx& c, const SegParams& p, int ts, int t0, int t1)
+__device__ __forceinline__ void row_frames(RowCtx& c, const RowParams& rp, int strip, int band, int ts, int t0,
+                                           int t1)
 {
+    const SegParams& p = rp.sp;
     constexpr int C = RGB ? 3 : 1;
     const size_t plane = (size_t)p.W * p.H;
     const int n = c.y1 - c.y0 + 2 * ROW_HX;
+    const bool xch = DIFF && rp.xcount != nullptr;
     for (int t = ts; t < t1; ++t) {
         c.t = t;
         c.real = t >= t0;
+        c.store = c.real && !(xch && t == t0 && t0 > 0);
         c.in_frame = (const uint8_t*)p.in + (size_t)t * plane * C;
         c.out_frame = (uint8_t*)p.out + (size_t)t * plane;
         RowState<K, RGB> st;
@@ -401,6 +502,16 @@ __device__ __forceinline__ void row_frames(RowCtx& c, const SegParams& p, int ts
         load_raw<K, RGB>(c, r0 + 1, st.raw[1]);
         for (int jb = 0; jb < n; jb += ROW_UNROLL)
             row_block<K, RGB, DIFF, EL, ER>(st, c, p, jb, n, std::make_integer_sequence<int, ROW_UNROLL>{});
+        if constexpr (DIFF) {
+            if (xch && t == t0 && t0 > 0) {  // the boundary before the run: this side is its first frame
+                const RowBoundary x = row_boundary<K>(rp, strip, band, t0 / rp.tt);
+                row_exchange<K>(c, x.first, x.last, x.cnt, c.out_frame);
+            }
+            if (xch && t == t1 - 1 && t1 < p.T) {  // the boundary after the run: this side is its last frame
+                const RowBoundary x = row_boundary<K>(rp, strip, band, t1 / rp.tt);
+                row_exchange<K>(c, x.last, x.first, x.cnt, (uint8_t*)p.out + (size_t)t1 * plane);
+            }
+        }
     }
 }
 
@@ -412,8 +523,9 @@ struct RowItem {
 
 // One work item of one wavefront (all of it wavefront-uniform).
 template <int K, bool RGB, bool DIFF>
-__device__ __forceinline__ void row_item(const SegParams& p, const RowItem& it, uint8_t* prev_lds)
+__device__ __forceinline__ void row_item(const RowParams& rp, const RowItem& it, uint8_t* prev_lds)
 {
+    const SegParams& p = rp.sp;
     RowCtx c;
     c.W = p.W;
     c.Hf = p.H;
@@ -468,16 +580,16 @@ __device__ __forceinline__ void row_item(const SegParams& p, const RowItem& it, 
 
     const int t0 = it.chunk * it.tt;
     const int t1 = min(t0 + it.tt, p.T);
-    const int ts = (DIFF && t0 > 0) ? t0 - 1 : t0;
+    const int ts = (DIFF && t0 > 0 && rp.xcount == nullptr) ? t0 - 1 : t0;
     const bool el = it.strip == 0, er = it.strip == it.nstrips - 1;
     if (el && er)
-        row_frames<K, RGB, DIFF, true, true>(c, p, ts, t0, t1);
+        row_frames<K, RGB, DIFF, true, true>(c, rp, it.strip, it.band, ts, t0, t1);
     else if (el)
-        row_frames<K, RGB, DIFF, true, false>(c, p, ts, t0, t1);
+        row_frames<K, RGB, DIFF, true, false>(c, rp, it.strip, it.band, ts, t0, t1);
     else if (er)
-        row_frames<K, RGB, DIFF, false, true>(c, p, ts, t0, t1);
+        row_frames<K, RGB, DIFF, false, true>(c, rp, it.strip, it.band, ts, t0, t1);
     else
-        row_frames<K, RGB, DIFF, false, false>(c, p, ts, t0, t1);
+        row_frames<K, RGB, DIFF, false, false>(c, rp, it.strip, it.band, ts, t0, t1);
 }
 
 // Decompose a clip-local item index.  Strips vary fastest, then bands, then
@@ -509,7 +621,7 @@ __global__ __launch_bounds__(ROW_WAVES * 64) void k_rowfuse(RowParams rp)
     const int item = blockIdx.x * ROW_WAVES + wave;
     if (item >= rp.total) return;  // whole wavefront leaves; no barrier is used
     const RowItem it = row_decompose(item, rp.nstrips, rp.nbands, rp.nchunks, rp.band_h, rp.tt, rp.strip_step);
-    row_item<K, RGB, DIFF>(rp.sp, it, row_lds + wave * rp.band_h * 64);
+    row_item<K, RGB, DIFF>(rp, it, row_lds + wave * rp.band_h * 64);
 }
 
 // ---------------------------------------------------------------- batches
@@ -552,7 +664,8 @@ __global__ __launch_bounds__(ROW_WAVES * 64) void k_rowfuse_batch(BatchParams bp
         int ci = 0;
         while (ci + 1 < bp.n_clips && item >= bp.clip[ci + 1].item_begin) ++ci;
         const BatchClip& bc = bp.clip[ci];
-        SegParams sp{};
+        RowParams rp{};
+        SegParams& sp = rp.sp;
         sp.in = bc.in;
         sp.out = bc.out;
         sp.W = bc.W;
@@ -567,7 +680,8 @@ __global__ __launch_bounds__(ROW_WAVES * 64) void k_rowfuse_batch(BatchParams bp
         sp.cap = bc.cap;
         const RowItem it = row_decompose(item - bc.item_begin, bc.nstrips, bc.nbands, bc.nchunks, BATCH_BAND_H,
                                          BATCH_TT, 64 * K - 2 * ROW_HX);
-        row_item<K, RGB, DIFF>(sp, it, row_lds + wave * BATCH_BAND_H * 64);
+        rp.tt = BATCH_TT;  // no exchange buffers: each run recomputes the frame before it
+        row_item<K, RGB, DIFF>(rp, it, row_lds + wave * BATCH_BAND_H * 64);
     }
 }
 

@@ -12,11 +12,27 @@ __global__ void k_batch_reset(BatchParams bp)
     if (i < bp.n_clips && bp.clip[i].count != nullptr) *bp.clip[i].count = 0u;
 }
 
+// Zero n words (the frame-boundary arrival counters; a kernel, not a memset,
+// so that it is an ordinary kernel node when a run is captured into a graph).
+__global__ void k_zero_words(uint32_t* p, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0u;
+}
+
 template <int K, bool RGB, bool DIFF>
 static hipError_t go(const RowParams& rp, hipStream_t s)
 {
     const int blocks = (rp.total + ROW_WAVES - 1) / ROW_WAVES;
     const size_t lds = DIFF ? (size_t)ROW_WAVES * rp.band_h * 64 : 0;
+    if (DIFF && rp.xcount != nullptr) {
+        const int nb = row_boundaries(rp.nstrips, rp.nbands, rp.nchunks);
+        if (nb > 0) {
+            hipLaunchKernelGGL(k_zero_words, dim3((nb + 255) / 256), dim3(256), 0, s, rp.xcount, nb);
+            const hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return e;
+        }
+    }
     hipLaunchKernelGGL((k_rowfuse<K, RGB, DIFF>), dim3(blocks), dim3(ROW_WAVES * 64), lds, s, rp);
     return hipGetLastError();
 }

@@ -47,17 +47,38 @@ inline int row_strips_best(int W, bool rgb)
 
 inline int row_lds_bytes(int band_h) { return ROW_WAVES * band_h * 64; }
 
+// Frame boundaries between consecutive runs of one strip and band, and the
+// device bytes of their exchange (two areas of band_h * K mask words and one
+// counter each, 256-byte aligned), for a frame-difference row group.
+FZ_HD inline int row_boundaries(int nstrips, int nbands, int nchunks)
+{
+    return nchunks > 1 ? nstrips * nbands * (nchunks - 1) : 0;
+}
+inline size_t row_exchange_bytes(int nstrips, int nbands, int nchunks, int band_h, int K)
+{
+    const size_t nb = (size_t)row_boundaries(nstrips, nbands, nchunks);
+    const size_t words = ((2 * nb * band_h * K * 8) + 255) & ~(size_t)255;
+    return nb == 0 ? 0 : words + ((nb * 4 + 255) & ~(size_t)255);
+}
+
 // A frame-difference group keeps one byte of previous-frame mask bits per lane
 // and row in LDS: at most 256 rows per band keep that within 64 KB per
 // workgroup of ROW_WAVES wavefronts.
 constexpr int ROW_DIFF_MAX_BAND = 256;
 
 // Rows per band and frames per work item.  A work item marches band_h + 2*HX
-// rows per frame over tt frames (plus the frame before them when the group
-// ends in the frame difference); items run in rounds of `slots` wavefronts,
-// fewer when the frame difference's LDS rows (one workgroup of ROW_WAVES
-// wavefronts per SIMD slot) do not fit 160 KB per CU that many times.  Pick
-// the pair with the least (rounds x item length).  Explicit requests (> 0)
+// rows per frame over tt frames (a frame-difference group takes the frame
+// before them from the previous run's item, which costs about 0.45 of a
+// frame per item); `slots` wavefronts run at once, fewer when the frame
+// difference's LDS rows (one workgroup of ROW_WAVES wavefronts per SIMD slot)
+// do not fit 160 KB per CU that many times.  The cost of a pair is its total
+// work, items x (band_h + 2*HX) x (tt + exchange), times (1 + 1/r) for r =
+// items / (wavefronts at once): a launch of few rounds of long items loses
+// the tail of its last round, and on the 800x600x1000 RGB chain measured
+// times fall from ~1.27 ms at 0.95 rounds (55 rows x 16 frames) to ~1.11 ms
+// at 5-8 rounds (55-86 rows x 2 frames); and times slots / (wavefronts at
+// once) where LDS holds fewer wavefronts than the registers allow.
+// Explicit requests (> 0)
 // are kept as given, except that a frame run longer than the video is the
 // whole video and a band taller than the frame the whole frame; a request the
 // kernel cannot run (a band over ROW_DIFF_MAX_BAND rows on a frame-difference
@@ -86,8 +107,9 @@ inline RowShape row_shape(int H, int T, int nstrips, bool diff, int req_h, int r
             const long long items = (long long)nstrips * ((H + bh - 1) / bh) * ((T + t - 1) / t);
             long long fit = slots;
             if (diff) fit = std::min(fit, (long long)256 * ROW_WAVES * (163840 / row_lds_bytes(bh)));
-            const long long rounds = (items + fit - 1) / fit;
-            const double cost = (double)rounds * (bh + 2 * ROW_HX) * (t + (diff ? 1 : 0));
+            const double r = (double)items / (double)fit;
+            const double cost = (double)items * (bh + 2 * ROW_HX) * (t + (diff && t < T ? 0.45 : 0.0)) *
+                                (1.0 + 1.0 / r) * ((double)slots / (double)fit);
             if (best_cost < 0 || cost < best_cost) {
                 best_cost = cost;
                 best = RowShape{bh, t};

@@ -34,21 +34,36 @@ static size_t slots_bytes(const fz_plan& p)
     return (p.segs.size() > 2 ? 2 : 1) * align256(mx);
 }
 
+// Frame-boundary exchange of a frame-difference group of the Harris row
+// kernel (0 for every other group).
+size_t exchange_bytes(const fz_plan& p, const Segment& g)
+{
+    if (p.generic || g.engine != FZ_ENGINE_ROW || g.row_gen || g.clast != 8) return 0;
+    return row_exchange_bytes(g.nstrips, g.nbands, g.nchunks, g.tile_h, g.row_k);
+}
+
+// Layout: the intermediate slots, the IIR checkpoints, the row kernel's
+// frame-boundary exchange.
 size_t workspace_bytes(const fz_plan& p)
 {
-    size_t ck = 0;
-    for (const Segment& g : p.segs) ck = std::max(ck, ckpt_bytes(p, g));
-    return slots_bytes(p) + align256(ck);
+    size_t ck = 0, xb = 0;
+    for (const Segment& g : p.segs) {
+        ck = std::max(ck, ckpt_bytes(p, g));
+        xb = std::max(xb, exchange_bytes(p, g));
+    }
+    return slots_bytes(p) + align256(ck) + xb;
 }
 
 fz_status run_plan(const fz_plan& p, const void* d_in, void* d_out, fz_point* d_points, uint32_t* d_count,
                    uint32_t cap, void* d_ws, size_t ws_bytes, void* stream)
 {
-    (void)ws_bytes;
     (void)hipGetLastError();  // drop an error latched by earlier, unrelated runtime calls
     hipStream_t s = (hipStream_t)stream;
     const size_t slot = p.segs.size() > 1 ? align256(slots_bytes(p) / (p.segs.size() > 2 ? 2 : 1)) : 0;
     void* ckpt = d_ws ? (void*)((char*)d_ws + slots_bytes(p)) : nullptr;
+    size_t ck = 0;
+    for (const Segment& g : p.segs) ck = std::max(ck, ckpt_bytes(p, g));
+    char* xch = d_ws ? (char*)d_ws + slots_bytes(p) + align256(ck) : nullptr;
     if (d_count && p.has_nms) {
         hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, s, d_count);
         hipError_t e = hipGetLastError();
@@ -94,6 +109,14 @@ fz_status run_plan(const fz_plan& p, const void* d_in, void* d_out, fz_point* d_
                 e = fn(rp, s);
             } else {
                 rp.strip_step = 64 * g.row_k - 2 * ROW_HX;
+                const size_t xb = exchange_bytes(p, g);
+                if (xb > 0) {
+                    if (!xch || ws_bytes < workspace_bytes(p))
+                        return fail(FZ_E_WORKSPACE, "the frame-difference row group needs the exchange workspace");
+                    const size_t nb = (size_t)row_boundaries(g.nstrips, g.nbands, g.nchunks);
+                    rp.xmask = (uint64_t*)xch;
+                    rp.xcount = (uint32_t*)(xch + ((2 * nb * g.tile_h * g.row_k * 8 + 255) & ~(size_t)255));
+                }
                 e = launch_rowfuse(rp, g.row_k, g.cfirst == 0, g.clast == 8, s);
             }
         } else {

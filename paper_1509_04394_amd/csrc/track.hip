@@ -22,9 +22,11 @@
 // scatter into the workspace), then one wavefront marches the frames in
 // order: it sorts the frame's points by (y, x) (rank by counting), predicts
 // every live track, lists the gated candidate pairs, sorts them (rank by
-// counting), lets one lane take them greedily, updates the tracks, appends the
-// new ones and writes one record per live track.  Tracks live in the
-// workspace in two buffers (ping-pong on compaction), kept in id order.
+// counting), takes them greedily (in rounds of candidates first for both
+// their track and their point), updates the tracks, appends the new ones and
+// writes one record per live track.  The list is kept in id order: its first
+// 64 tracks in registers, the rest in the workspace in two buffers
+// (ping-pong on compaction).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -180,21 +182,18 @@ __device__ __forceinline__ void put_record(fz_track* out, uint32_t k, uint32_t c
     }
 }
 
-// Slots for the records of the lanes in `m` (one atomic per wavefront):
-// returns this lane's slot.
-__device__ __forceinline__ uint32_t reserve(uint32_t* count, uint64_t m, int lane)
-{
-    uint32_t base = 0;
-    if (lane == 0 && m) base = atomicAdd(&count[0], (uint32_t)__popcll(m));
-    base = __shfl(base, 0);
-    return base + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
-}
-
 // One wavefront marches the frames.  Every lane owns the tracks lane,
 // lane + 64, ... of the current list: it predicts them and lists their gated
-// candidates in one pass (the track read once from the workspace), and later
-// updates them; compaction and new tracks use ballot prefix sums, and the
-// records' slots are reserved with one atomic per 64 lanes.
+// candidates in one pass, and later updates them.  The first 64 tracks of the
+// list stay in the lanes' registers from frame to frame (passed through LDS
+// when the list is compacted); tracks past them live in the workspace.  The
+// greedy association is formed in rounds: every candidate that is the first
+// (in the (d2, id, point) order) of the remaining candidates of both its track
+// and its point is taken, and candidates of taken tracks and points leave;
+// for a strict total order this is the matching the one-by-one greedy pass
+// makes, in a few rounds instead of one step per candidate.  The next frame's
+// points are loaded while the current frame is processed; the record count
+// is kept in a register (one wavefront writes every record).
 __global__ __launch_bounds__(TRK_THREADS) void k_trk_run(const int2* bucket, const uint32_t* offs, int T,
                                                           fz_track_opts o, DevTrack* buf0, DevTrack* buf1,
                                                           uint32_t max_tracks, fz_track* out, uint32_t* count,
@@ -205,26 +204,46 @@ __global__ __launch_bounds__(TRK_THREADS) void k_trk_run(const int2* bucket, con
     __shared__ Cand cand[TRK_MAX_CANDS];   // as listed
     __shared__ Cand cs[TRK_MAX_CANDS];     // in increasing (d2, id, point) order
     __shared__ uint8_t ptaken[TRK_MAX_POINTS];
-    __shared__ int16_t tmatch[FZ_TRACK_MAX_TRACKS];  // point matched to each track, -1 none
+    __shared__ uint8_t calive[TRK_MAX_CANDS];          // candidate still open (association rounds)
+    __shared__ int16_t tmatch[FZ_TRACK_MAX_TRACKS];    // point matched to each track, -1 none
+    __shared__ uint32_t tbest[FZ_TRACK_MAX_TRACKS];    // first open candidate of each track (a round)
+    __shared__ uint32_t pbest[TRK_MAX_POINTS];         // first open candidate of each point (a round)
+    __shared__ DevTrack stage[TRK_THREADS];            // the next list's first 64 tracks
     __shared__ uint32_t s_nc, s_flags;
     const int lane = threadIdx.x;
     const KModel M(o.q, o.r);
     DevTrack* cur = buf0;
     DevTrack* nxt = buf1;
-    uint32_t ntr = 0, next_id = 0;
+    uint32_t ntr = 0, next_id = 0, nrec = 0;
+    DevTrack rt;  // track `lane` of the current list (lane < ntr)
     if (lane == 0) s_flags = 0u;
     if (max_tracks > (uint32_t)FZ_TRACK_MAX_TRACKS) max_tracks = FZ_TRACK_MAX_TRACKS;
+    const uint32_t total = offs[T];
+    uint32_t f_lo = offs[0], f_hi = T > 0 ? offs[1] : f_lo;
+    int pre_x = 0, pre_y = 0;  // point f_lo + lane (loaded a frame ahead)
+    if (f_lo + lane < total) {
+        const int2 q = bucket[f_lo + lane];
+        pre_x = q.x;
+        pre_y = q.y;
+    }
 
     for (int t = 0; t < T; ++t) {
-        uint32_t np = offs[t + 1] - offs[t];
+        uint32_t np = f_hi - f_lo;
         if (np > (uint32_t)TRK_MAX_POINTS) {
             if (lane == 0) s_flags |= FZ_TRACK_TOO_MANY_POINTS;
             np = TRK_MAX_POINTS;
         }
         // 1. the frame's points, sorted by (y, x) (keys are distinct)
         for (uint32_t j = lane; j < np; j += TRK_THREADS) {
-            pin[j] = bucket[offs[t] + j];
+            pin[j] = j < (uint32_t)TRK_THREADS ? make_int2(pre_x, pre_y) : bucket[f_lo + j];
             ptaken[j] = 0;
+        }
+        // the next frame's bounds and first points, in flight during this frame
+        const uint32_t n_lo = f_hi, n_hi = t + 2 <= T ? offs[t + 2] : f_hi;
+        if (n_lo + lane < total) {
+            const int2 q = bucket[n_lo + lane];
+            pre_x = q.x;
+            pre_y = q.y;
         }
         if (lane == 0) s_nc = 0u;
         __syncthreads();
@@ -240,13 +259,14 @@ __global__ __launch_bounds__(TRK_THREADS) void k_trk_run(const int2* bucket, con
         __syncthreads();
         // 2. predict every live track and list its gated candidate pairs
         for (uint32_t i = lane; i < ntr; i += TRK_THREADS) {
-            DevTrack& tr = cur[i];
-            double sp[4], P0[16], FP[16], Pp[16], HP[8], S[4], Si[4];
-            for (int e = 0; e < 4; ++e) sp[e] = tr.s[e];
-            for (int e = 0; e < 16; ++e) P0[e] = tr.P[e];
-            double s1[4];
-            mm<4, 4, 1>(M.F, sp, s1);
-            mm<4, 4, 4>(M.F, P0, FP);
+            DevTrack tr;
+            if (i < (uint32_t)TRK_THREADS)
+                tr = rt;
+            else
+                tr = cur[i];
+            double s1[4], FP[16], Pp[16], HP[8], S[4], Si[4];
+            mm<4, 4, 1>(M.F, tr.s, s1);
+            mm<4, 4, 4>(M.F, tr.P, FP);
             mm<4, 4, 4>(FP, M.Ft, Pp);
             for (int e = 0; e < 16; ++e) Pp[e] = Pp[e] + M.Q[e];
             mm<2, 4, 4>(M.H, Pp, HP);
@@ -261,6 +281,10 @@ __global__ __launch_bounds__(TRK_THREADS) void k_trk_run(const int2* bucket, con
             for (int e = 0; e < 4; ++e) tr.s[e] = s1[e];
             for (int e = 0; e < 16; ++e) tr.P[e] = Pp[e];
             for (int e = 0; e < 4; ++e) tr.Si[e] = Si[e];
+            if (i < (uint32_t)TRK_THREADS)
+                rt = tr;
+            else
+                cur[i] = tr;
             tmatch[i] = -1;
             double hs[2];
             mm<2, 4, 1>(M.H, s1, hs);
@@ -295,17 +319,38 @@ __global__ __launch_bounds__(TRK_THREADS) void k_trk_run(const int2* bucket, con
             uint32_t rank = 0;
             for (uint32_t k = 0; k < nc; ++k) rank += cand_less(cand[k], a) ? 1u : 0u;
             cs[rank] = a;
+            calive[rank] = 1;
         }
-        __syncthreads();
-        // 4. greedy association by one lane
-        if (lane == 0) {
-            for (uint32_t k = 0; k < nc; ++k) {
-                const Cand c = cs[k];
-                if (tmatch[c.ti] < 0 && !ptaken[c.pj]) {
-                    tmatch[c.ti] = c.pj;
-                    ptaken[c.pj] = 1;
+        // 4. greedy association in rounds of locally first candidates
+        for (;;) {
+            __syncthreads();
+            for (uint32_t c = lane; c < nc; c += TRK_THREADS)
+                if (calive[c]) {
+                    tbest[cs[c].ti] = 0xffffffffu;
+                    pbest[cs[c].pj] = 0xffffffffu;
                 }
-            }
+            __syncthreads();
+            for (uint32_t c = lane; c < nc; c += TRK_THREADS)
+                if (calive[c]) {
+                    atomicMin(&tbest[cs[c].ti], c);
+                    atomicMin(&pbest[cs[c].pj], c);
+                }
+            __syncthreads();
+            for (uint32_t c = lane; c < nc; c += TRK_THREADS)
+                if (calive[c] && tbest[cs[c].ti] == c && pbest[cs[c].pj] == c) {
+                    tmatch[cs[c].ti] = cs[c].pj;
+                    ptaken[cs[c].pj] = 1;
+                }
+            __syncthreads();
+            bool open = false;
+            for (uint32_t c = lane; c < nc; c += TRK_THREADS)
+                if (calive[c]) {
+                    if (tmatch[cs[c].ti] >= 0 || ptaken[cs[c].pj])
+                        calive[c] = 0;
+                    else
+                        open = true;
+                }
+            if (!__any(open)) break;
         }
         __syncthreads();
         // 5. update or count a miss; survivors to the next list in id order, with their records
@@ -315,7 +360,10 @@ __global__ __launch_bounds__(TRK_THREADS) void k_trk_run(const int2* bucket, con
             DevTrack tr;
             bool alive = false;
             if (i < ntr) {
-                tr = cur[i];
+                if (c0 == 0)
+                    tr = rt;
+                else
+                    tr = cur[i];
                 const int j = tmatch[i];
                 if (j >= 0) {
                     double hs[2], nu[2], PHt[8], K[8], Knu[4], KH[16], IKH[16], Pn[16];
@@ -340,12 +388,17 @@ __global__ __launch_bounds__(TRK_THREADS) void k_trk_run(const int2* bucket, con
                 alive = tr.miss <= o.max_miss;
             }
             const uint64_t m = __ballot(alive);
-            const uint32_t slot = reserve(count, m, lane);
+            const uint32_t before = (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
             if (alive) {
-                nxt[n_alive + (uint32_t)__popcll(m & ((1ull << lane) - 1ull))] = tr;
-                put_record(out, slot, cap, t, tr);
+                const uint32_t pos = n_alive + before;
+                if (pos < (uint32_t)TRK_THREADS)
+                    stage[pos] = tr;
+                else
+                    nxt[pos] = tr;
+                put_record(out, nrec + before, cap, t, tr);
             }
             n_alive += (uint32_t)__popcll(m);
+            nrec += (uint32_t)__popcll(m);
         }
         // 6. every point left over starts a track (ids in point order)
         uint32_t n_new = 0;
@@ -357,7 +410,6 @@ __global__ __launch_bounds__(TRK_THREADS) void k_trk_run(const int2* bucket, con
             const bool keep = fresh && pos < max_tracks;
             if (fresh && !keep) atomicOr(&s_flags, (uint32_t)FZ_TRACK_TOO_MANY_TRACKS);
             const uint64_t m = __ballot(keep);
-            const uint32_t slot = reserve(count, m, lane);
             if (keep) {
                 DevTrack tr;
                 tr.id = (int32_t)(next_id + n_new + before);
@@ -374,9 +426,13 @@ __global__ __launch_bounds__(TRK_THREADS) void k_trk_run(const int2* bucket, con
                 tr.P[10] = o.v0;
                 tr.P[15] = o.v0;
                 for (int e = 0; e < 4; ++e) tr.Si[e] = 0.0;
-                nxt[pos] = tr;
-                put_record(out, slot, cap, t, tr);
+                if (pos < (uint32_t)TRK_THREADS)
+                    stage[pos] = tr;
+                else
+                    nxt[pos] = tr;
+                put_record(out, nrec + (uint32_t)__popcll(m & ((1ull << lane) - 1ull)), cap, t, tr);
             }
+            nrec += (uint32_t)__popcll(m);
             n_new += (uint32_t)__popcll(__ballot(fresh));
         }
         next_id += n_new;
@@ -385,8 +441,15 @@ __global__ __launch_bounds__(TRK_THREADS) void k_trk_run(const int2* bucket, con
         cur = nxt;
         nxt = sw;
         __syncthreads();
+        if ((uint32_t)lane < ntr) rt = stage[lane];
+        f_lo = n_lo;
+        f_hi = n_hi;
+        __syncthreads();
     }
-    if (lane == 0) atomicOr(&count[1], s_flags);
+    if (lane == 0) {
+        count[0] = nrec;
+        atomicOr(&count[1], s_flags);
+    }
 }
 
 static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }

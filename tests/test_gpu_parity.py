@@ -309,6 +309,35 @@ def test_row_engine_equals_tile_engine(dev, shape):
             assert key(gp) == key(refp), (ops[-1], band_h, tpb)
 
 
+def test_row_frame_boundary_exchange(dev):
+    """Frame-difference row groups: the item of a run takes the mask of the
+    frame before it from the previous run's item (whichever of the two ends
+    second writes that frame's difference).  Runs of 1 .. T frames, a run
+    length that does not divide T, and repeated runs on one workspace (the
+    arrival counters are cleared by each launch) give the tile engine's
+    bytes and points."""
+    W, H, T = 300, 40, 23
+    rgb = synth.video(W, H, T, seed=91, rgb=True)
+    key = lambda p: sorted(map(tuple, p.tolist()))
+    ref, refp, _ = run_gpu(fz.RGB_HARRIS_CHAIN, rgb, dev, engine="tile")
+    x = torch.from_numpy(rgb).to(dev)
+    for band_h, tpb in [(8, 1), (13, 2), (40, 5), (21, 22), (40, 23)]:
+        plan = fz.Plan(fz.RGB_HARRIS_CHAIN, W, H, T, partition=[], engine="row", band_h=band_h,
+                       frames_per_block=tpb)
+        s = plan.segment_info()[0]
+        assert s.engine == fz.FZ_ENGINE_ROW and s.frames_per_block == tpb
+        out, pts, cnt, ws = plan.alloc(dev, point_capacity=1 << 16)
+        if tpb < T:
+            assert plan.workspace_bytes > 0
+        for rep in range(2):
+            say("row exchange", band_h, tpb, rep)
+            out.zero_()
+            plan.run(x, out, pts, cnt, ws)
+            torch.cuda.synchronize()
+            assert np.array_equal(out.cpu().numpy(), ref), (band_h, tpb, rep)
+            assert key(fz.points_to_numpy(pts, cnt)) == key(refp), (band_h, tpb, rep)
+
+
 def test_row_engine_vs_oracle(dev):
     ops = fz.RGB_HARRIS_CHAIN
     rgb = synth.video(300, 120, 7, seed=40, rgb=True)
