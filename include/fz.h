@@ -155,8 +155,10 @@ typedef struct fz_plan_opts {
  * as constants, point and IIR stages inline -- compiled for gfx950 with hipRTC
  * when the plan is made (a compile error fails fz_plan_chain), loaded on each
  * device at its first run and cached for the process; tiles 16x16, 32x16,
- * 32x32, 64x16, 64x32.  Its output equals TILE's to the bit.  Point-only
- * groups of a JIT plan run as in AUTO. */
+ * 32x32, 64x16, 64x32; a work item marches frames_per_block frames (up to 4
+ * by default for a group without temporal stages).  Its output equals TILE's
+ * in value (the sign of a zero sum aside).  Point-only groups of a JIT plan
+ * run as in AUTO. */
 enum { FZ_ENGINE_AUTO = 0, FZ_ENGINE_TILE = 1, FZ_ENGINE_ROW = 2, FZ_ENGINE_STREAM = 3, FZ_ENGINE_JIT = 4 };
 
 typedef struct fz_plan fz_plan;  /* opaque, host memory */

@@ -153,6 +153,9 @@ inline bool g_temporal(const GStage* st, int n, bool* has_iir = nullptr, int* ht
 
 // Output tiles of the generated (hipRTC) kernels, x by y.
 constexpr int N_JIT_TILES = 5;
+// Work items a generated kernel without temporal stages keeps when it takes
+// several frames per item (two rounds of four 256-thread workgroups per CU).
+constexpr int JIT_FILL_ITEMS = 2048;
 extern const int JIT_TILES[N_JIT_TILES][2];
 
 // A group whose IIR stages all come before its first window stage, and whose

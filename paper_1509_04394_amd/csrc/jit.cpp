@@ -10,11 +10,13 @@
 // text for the life of the process.  The generated kernel keeps the tile
 // kernel's structure (input box loaded once into LDS with the leading point
 // stages applied, window stages from one LDS buffer into the other, the last
-// one straight to global memory, five neighbouring cells per thread inside the
-// frame, clamped reads on border tiles) and the same arithmetic in the same
-// order, so its output equals the tile kernel's to the bit.  Groups with a
-// temporal stage get the frame-marching kernel written out the same way
-// (rings of earlier frames per stencil, IIR states, checkpoint restore).
+// one straight to global memory) and each output's arithmetic in the same
+// order, so its output equals the tile kernel's in value (the sign of a zero
+// sum aside); the work per thread differs: a block of neighbouring cells
+// (five across, up to two down) per thread, and aligned four-cell loads of
+// the input box.  Groups with a temporal stage get the frame-marching kernel
+// written out the same way (rings of earlier frames per stencil, IIR states,
+// checkpoint restore).
 #include <hip/hip_runtime.h>
 #include <hip/hiprtc.h>
 
@@ -56,147 +58,6 @@ static std::string point_stmt(const fz_stage& s)
     }
 }
 
-static std::string jit_march_source(const fz_plan& p, const Segment& g);
-
-std::string jit_source(const fz_plan& p, const Segment& g)
-{
-    {
-        GStage st[G_MAX_STAGES];
-        g_stage_list(p.stages.data(), g.first, g.last, st);
-        if (g_temporal(st, g.last - g.first + 1)) return jit_march_source(p, g);
-    }
-    std::ostringstream o;
-    const int TW = g.tile_w, TH = g.tile_h, HX = g.halo, HY = g.halo_y;
-    const bool u8 = p.stages[g.first].in_dtype == FZ_U8;
-    o << "#define GQ 5\n"
-         "__device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }\n"
-         "extern \"C\" __global__ __launch_bounds__(256) void fz_jit(const "
-      << (u8 ? "unsigned char" : "float")
-      << "* __restrict__ in, float* __restrict__ out, int W, int H, int tiles_x, int tiles_y)\n{\n"
-      << "    constexpr int TW = " << TW << ", TH = " << TH << ", HX = " << HX << ", HY = " << HY
-      << ", RW = TW + 2 * HX, RH = TH + 2 * HY;\n";
-    int nwin = 0;
-    for (int j = g.first; j <= g.last; ++j) nwin += p.stages[j].op != FZ_OP_POINT;
-    o << "    __shared__ float lds[" << generic_lds_bytes(TW, TH, HX, HY, nwin) / 4 << "];\n"
-      << "    float* bufs[2] = {lds, lds + RW * RH};\n"
-         // blocks dealt to XCDs round-robin: contiguous runs of tiles per XCD
-         "    const int nb = gridDim.x, q8 = nb >> 3, r8 = nb & 7, xcd = blockIdx.x & 7, slot = blockIdx.x >> 3;\n"
-         "    int b = (xcd < r8 ? xcd * (q8 + 1) : r8 * (q8 + 1) + (xcd - r8) * q8) + slot;\n"
-         "    const int tx = b % tiles_x;\n    b /= tiles_x;\n    const int ty = b % tiles_y;\n"
-         "    const int t = b / tiles_y;\n"
-         "    const int ox = tx * TW - HX, oy = ty * TH - HY;\n"
-         "    const size_t fbase = (size_t)t * W * H;\n"
-         "    const bool interior = ox >= 0 && oy >= 0 && ox + RW <= W && oy + RH <= H;\n";
-    // load with the leading point stages
-    int j = g.first;
-    o << "    for (int e = threadIdx.x; e < RW * RH; e += 256) {\n"
-         "        const int ly = e / RW, lx = e - ly * RW;\n"
-         "        const int gx = ox + lx, gy = oy + ly;\n"
-         "        if (gx < 0 || gx >= W || gy < 0 || gy >= H) continue;\n"
-         "        float v = (float)in[fbase + (size_t)gy * W + gx];\n";
-    for (; j <= g.last && p.stages[j].op == FZ_OP_POINT; ++j) o << "        " << point_stmt(p.stages[j]) << "\n";
-    o << "        bufs[0][e] = v;\n    }\n    __syncthreads();\n";
-    int hx = HX, hy = HY, step = 0;
-    while (j <= g.last) {
-        const fz_stage& s = p.stages[j];
-        int k = j + 1;
-        while (k <= g.last && p.stages[k].op == FZ_OP_POINT) ++k;
-        const bool last = k > g.last;
-        const bool stencil = s.op == FZ_OP_STENCIL;
-        const int ohx = hx - s.rx, ohy = hy - s.ry;
-        std::string trail;
-        for (int q = j + 1; q < k; ++q) trail += "                " + point_stmt(p.stages[q]) + "\n";
-        o << "    {  // window stage " << (j - g.first) << (stencil ? ": stencil " : ": window sum ") << 2 * s.rx + 1
-          << "x" << 2 * s.ry + 1 << "\n"
-          << "        constexpr int RX = " << s.rx << ", RY = " << s.ry << ", OHX = " << ohx << ", OHY = " << ohy
-          << ";\n        constexpr int OW = TW + 2 * OHX, OH = TH + 2 * OHY, BX = HX - OHX, BY = HY - OHY;\n"
-          << "        const float* src = bufs[" << (step & 1) << "];\n"
-          << "        float* dst = bufs[" << ((step + 1) & 1) << "];\n";
-        if (stencil) {
-            o << "        constexpr float w[" << (2 * s.rx + 1) * (2 * s.ry + 1) << "] = {";
-            const int off = p.gwoff[j];
-            for (int q = 0; q < (2 * s.rx + 1) * (2 * s.ry + 1); ++q)
-                o << (q ? ", " : "") << flit(p.gweights[off + q]);
-            o << "};\n";
-        }
-        // interior: GQ cells per thread, rows read once into registers
-        o << "        if (interior) {\n"
-             "            constexpr int NQ = (OW + GQ - 1) / GQ;\n"
-             "            for (int e = threadIdx.x; e < NQ * OH; e += 256) {\n"
-             "                const int cy = e / NQ, cx = (e - cy * NQ) * GQ;\n"
-             "                const int lx = BX + cx, ly = BY + cy, base = ly * RW + lx;\n"
-             "                float acc[GQ];\n"
-             "#pragma unroll\n"
-             "                for (int c = 0; c < GQ; ++c) acc[c] = 0.0f;\n"
-             "#pragma unroll\n"
-             "                for (int v = -RY; v <= RY; ++v) {\n"
-             "                    float x[GQ + 2 * RX];\n"
-             "#pragma unroll\n"
-             "                    for (int q = 0; q < GQ + 2 * RX; ++q) x[q] = src[base + v * RW - RX + q];\n";
-        if (stencil)
-            o << "#pragma unroll\n"
-                 "                    for (int u = -RX; u <= RX; ++u) {\n"
-                 "                        const float wv = w[(v + RY) * (2 * RX + 1) + (u + RX)];\n"
-                 "#pragma unroll\n"
-                 "                        for (int c = 0; c < GQ; ++c) acc[c] = fmaf(wv, x[c + u + RX], acc[c]);\n"
-                 "                    }\n";
-        else
-            o << "#pragma unroll\n"
-                 "                    for (int c = 0; c < GQ; ++c) {\n"
-                 "                        float h = 0.0f;\n"
-                 "#pragma unroll\n"
-                 "                        for (int u = -RX; u <= RX; ++u) h = h + x[c + u + RX];\n"
-                 "                        acc[c] = acc[c] + h;\n"
-                 "                    }\n";
-        o << "                }\n"
-             "                const int nk = OW - cx < GQ ? OW - cx : GQ;\n"
-             "#pragma unroll\n"
-             "                for (int c = 0; c < GQ; ++c) {\n"
-             "                    if (c >= nk) break;\n"
-             "                    float v = acc[c];\n"
-          << trail;
-        if (last)
-            o << "                    out[fbase + (size_t)(oy + ly) * W + (ox + lx + c)] = v;\n";
-        else
-            o << "                    dst[base + c] = v;\n";
-        o << "                }\n            }\n"
-             "        } else {\n"
-             "            for (int e = threadIdx.x; e < OW * OH; e += 256) {\n"
-             "                const int cy = e / OW, cx = e - cy * OW;\n"
-             "                const int lx = BX + cx, ly = BY + cy, gx = ox + lx, gy = oy + ly;\n"
-             "                if (gx < 0 || gx >= W || gy < 0 || gy >= H) continue;\n"
-             "                float acc = 0.0f;\n"
-             "#pragma unroll\n"
-             "                for (int v = -RY; v <= RY; ++v) {\n"
-             "                    const int row = (clampi(gy + v, 0, H - 1) - oy) * RW - ox;\n";
-        if (stencil)
-            o << "#pragma unroll\n"
-                 "                    for (int u = -RX; u <= RX; ++u)\n"
-                 "                        acc = fmaf(w[(v + RY) * (2 * RX + 1) + (u + RX)], "
-                 "src[row + clampi(gx + u, 0, W - 1)], acc);\n";
-        else
-            o << "                    float h = 0.0f;\n"
-                 "#pragma unroll\n"
-                 "                    for (int u = -RX; u <= RX; ++u) h = h + src[row + clampi(gx + u, 0, W - 1)];\n"
-                 "                    acc = acc + h;\n";
-        o << "                }\n"
-             "                float v = acc;\n"
-          << trail;
-        if (last)
-            o << "                out[fbase + (size_t)gy * W + gx] = v;\n";
-        else
-            o << "                dst[ly * RW + lx] = v;\n";
-        o << "            }\n        }\n    }\n";
-        if (!last) o << "    __syncthreads();\n";
-        hx = ohx;
-        hy = ohy;
-        ++step;
-        j = k;
-    }
-    o << "}\n";
-    return o.str();
-}
-
 // One point or IIR stage on `v` (cell: the expression of its box cell, for an
 // IIR's state).
 static std::string trail_stmt(const fz_stage& s, const GStage& gs, const std::string& cell)
@@ -208,9 +69,47 @@ static std::string trail_stmt(const fz_stage& s, const GStage& gs, const std::st
            ") * (first ? x : *sp)); *sp = y; v = (float)y; }";
 }
 
-// The frame-marching kernel of a group with a temporal stage, written out
-// (the same steps and arithmetic as k_gmarch, stage list as constants).
-static std::string jit_march_source(const fz_plan& p, const Segment& g)
+// Rows of outputs per thread of a window stage: each thread computes a block
+// of GQ x gr cells (gr <= 2), so the input rows it reads and (for a window
+// sum) the row sums it forms serve gr output rows.  Chosen by a count of wave
+// instructions: wave passes (ceil(items / 64)) times an estimate of the
+// instructions per item.
+static int pick_rows(const GStage& s, int ow, int oh, int trail_ops, bool last, int GQ)
+{
+    const int nq = (ow + GQ - 1) / GQ;
+    int best = 1;
+    long best_cost = -1;
+    for (int gr = 1; gr <= 2 && gr <= oh; ++gr) {  // four rows: ~30 more registers, a wave fewer per SIMD
+        const int items = nq * ((oh + gr - 1) / gr);
+        const int rows_in = gr + 2 * s.ry;
+        long per = 14 + (long)GQ * gr * (1 + trail_ops + (last ? 1 : 0));
+        if (s.kind == G_STENCIL)
+            per += (long)GQ * gr * (2 * s.rx + 1) * (2 * s.ry + 1) * (s.rt + 1);
+        else
+            per += (long)(s.rt + 1) * (rows_in * GQ * 2 * s.rx + (long)gr * GQ * 2 * s.ry);
+        if (last) per += 4L * gr;
+        const long cost = (long)((items + 63) / 64) * per;
+        if (best_cost < 0 || cost < best_cost) {
+            best_cost = cost;
+            best = gr;
+        }
+    }
+    return best;
+}
+
+// The group's kernel.  One form serves every generic window group: a work
+// item is an output tile and a run of tt frames (tt = 1 and no temporal halo
+// for a group without temporal stages).  Borders: a tile whose box leaves the
+// frame loads its out-of-frame cells with clamped reads (the replicate border
+// of the group's input) and, after every window stage but the last, copies
+// each out-of-frame cell of that stage's output from the frame cell it
+// clamps to (the replicate border of that stage's output); so every stage
+// runs the unclamped path everywhere, and its in-frame results are exactly
+// those of clamped reads.  The last stage stores its in-frame cells only.
+// The input box of a tile that lies inside the frame across (every tile but
+// the left and right border ones) is read four cells per load, aligned, with
+// its rows clamped; others cell by cell with both coordinates clamped.
+std::string jit_source(const fz_plan& p, const Segment& g)
 {
     std::ostringstream o;
     const int TW = g.tile_w, TH = g.tile_h, HX = g.halo, HY = g.halo_y;
@@ -220,8 +119,8 @@ static std::string jit_march_source(const fz_plan& p, const Segment& g)
     const int floats = march_layout(st, n, (TW + 2 * HX) * (TH + 2 * HY)) + GEN_PAD;
     const int ck_n = g.ckpt ? g_ckpt_iirs(st, n) : 0;
     const bool u8 = p.stages[g.first].in_dtype == FZ_U8;
-    o << "#define GQ 5\n"
-         "__device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }\n"
+    const int S = (4 - HX % 4) % 4;  // tiles are a multiple of 4 wide: ox = tx TW - HX = S (mod 4)
+    o << "__device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }\n"
          "extern \"C\" __global__ __launch_bounds__(256) void fz_jit(const "
       << (u8 ? "unsigned char" : "float")
       << "* __restrict__ in, float* __restrict__ out, int W, int H, int tiles_x, int tiles_y, int T, int tt, "
@@ -230,13 +129,18 @@ static std::string jit_march_source(const fz_plan& p, const Segment& g)
       << ", RW = TW + 2 * HX, RH = TH + 2 * HY, CELLS = RW * RH;\n"
       << "    __shared__ double lds_d[" << (floats + 1) / 2 << "];\n"
       << "    float* lds = (float*)lds_d;\n"
+         // blocks dealt to XCDs round-robin: contiguous runs of tiles per XCD
          "    const int nb = gridDim.x, q8 = nb >> 3, r8 = nb & 7, xcd = blockIdx.x & 7, slot = blockIdx.x >> 3;\n"
          "    int b = (xcd < r8 ? xcd * (q8 + 1) : r8 * (q8 + 1) + (xcd - r8) * q8) + slot;\n"
          "    const int tx = b % tiles_x;\n    b /= tiles_x;\n    const int ty = b % tiles_y;\n"
          "    const int t0 = (b / tiles_y) * tt, t1 = min(T, t0 + tt), fs = max(0, t0 - ht);\n"
          "    const int ox = tx * TW - HX, oy = ty * TH - HY;\n"
          "    const size_t P = (size_t)W * H;\n"
-         "    const bool interior = ox >= 0 && oy >= 0 && ox + RW <= W && oy + RH <= H;\n";
+         "    const bool interior = ox >= 0 && oy >= 0 && ox + RW <= W && oy + RH <= H;\n"
+         "    const bool xin = ox >= 0 && ox + RW <= W && (W & 3) == 0 && ((size_t)in & "
+      << (u8 ? 3 : 15)
+      << ") == 0;\n"
+         "    const bool vec_out = interior && (W & 3) == 0 && ((size_t)out & 15) == 0;\n";
     int lead = 0;
     while (lead < n && !g_is_window(st[lead].kind)) ++lead;
     if (ck_n > 0) {
@@ -245,28 +149,102 @@ static std::string jit_march_source(const fz_plan& p, const Segment& g)
           << ck_n
           << " * P;\n"
              "        for (int e = threadIdx.x; e < CELLS; e += 256) {\n"
-             "            const int ly = e / RW, lx = e - ly * RW, gx = ox + lx, gy = oy + ly;\n"
-             "            if (gx < 0 || gx >= W || gy < 0 || gy >= H) continue;\n";
+             "            const int ly = e / RW, lx = e - ly * RW;\n"
+             "            const size_t gi = (size_t)clampi(oy + ly, 0, H - 1) * W + clampi(ox + lx, 0, W - 1);\n";
         int k = 0;
         for (int j = 0; j < lead; ++j)
-            if (st[j].kind == G_IIR)
-                o << "            ((double*)(lds + " << st[j].buf << "))[e] = ck[(size_t)" << k++
-                  << " * P + (size_t)gy * W + gx];\n";
+            if (st[j].kind == G_IIR) o << "            ((double*)(lds + " << st[j].buf << "))[e] = ck[(size_t)" << k++ << " * P + gi];\n";
         o << "        }\n        __syncthreads();\n    }\n";
     }
-    o << "    for (int f = fs; f < t1; ++f) {\n"
+    std::string lead_stmts;
+    for (int j = 0; j < lead; ++j) lead_stmts += "                            " + trail_stmt(p.stages[g.first + j], st[j], "e") + "\n";
+    // The input box of a frame is loaded into registers (pf) one frame ahead:
+    // the loads of frame f + 1 are issued right after frame f's box is in LDS
+    // and are in flight while frame f's window stages run.  pf holds raw
+    // words: four u8 cells or one f32 cell each.
+    const char* vt = u8 ? "unsigned int" : "float4";
+    auto issue = [&](const std::string& frame) {
+        std::ostringstream q;
+        q << "        {  // loads of frame " << frame << "'s box\n"
+          << "            const size_t gb = (size_t)(" << frame << ") * P;\n"
+          << "            if (xin) {\n"
+             "#pragma unroll\n"
+             "                for (int k = 0; k < NLV; ++k) {\n"
+             "                    const int it = threadIdx.x + 256 * k;\n"
+             "                    if (it < NV) {\n"
+             "                        const int ly = it / ND, kd = it - ly * ND;\n"
+             "                        const "
+          << vt << " w = *(const " << vt
+          << "*)(in + gb + (size_t)clampi(oy + ly, 0, H - 1) * W + a0 + 4 * kd);\n";
+        if (u8)
+            q << "                        pf[k] = w;\n";
+        else
+            q << "                        pf[4 * k] = __float_as_uint(w.x);\n"
+                 "                        pf[4 * k + 1] = __float_as_uint(w.y);\n"
+                 "                        pf[4 * k + 2] = __float_as_uint(w.z);\n"
+                 "                        pf[4 * k + 3] = __float_as_uint(w.w);\n";
+        q << "                    }\n"
+             "                }\n"
+             "            } else {\n"
+             "#pragma unroll\n"
+             "                for (int k = 0; k < NLS; ++k) {\n"
+             "                    const int e = threadIdx.x + 256 * k;\n"
+             "                    if (e < CELLS) {\n"
+             "                        const int ly = e / RW, lx = e - ly * RW;\n"
+             "                        const size_t gi = gb + (size_t)clampi(oy + ly, 0, H - 1) * W + clampi(ox + lx, 0, W - 1);\n";
+        if (u8)
+            q << "                        const unsigned int bv = in[gi];\n"
+                 "                        pf[k >> 2] = (k & 3) == 0 ? bv : pf[k >> 2] | bv << (8 * (k & 3));\n";
+        else
+            q << "                        pf[k] = __float_as_uint(in[gi]);\n";
+        q << "                    }\n"
+             "                }\n"
+             "            }\n"
+             "        }\n";
+        return q.str();
+    };
+    const char* vx[4] = {"(float)(pf[k] & 255u)", "(float)((pf[k] >> 8) & 255u)", "(float)((pf[k] >> 16) & 255u)",
+                         "(float)(pf[k] >> 24)"};
+    o << "    constexpr int S = " << S
+      << ", ND = (RW + S + 3) / 4, NV = RH * ND, NLV = (NV + 255) / 256, NLS = (CELLS + 255) / 256;\n"
+      << "    constexpr int NPF = " << (u8 ? "NLV > (NLS + 3) / 4 ? NLV : (NLS + 3) / 4" : "4 * NLV > NLS ? 4 * NLV : NLS")
+      << ";\n"
+         "    const int a0 = ox - S;\n"
+         "    unsigned int pf[NPF];\n"
+         "    if (fs < t1)\n"
+      << issue("fs")
+      << "    for (int f = fs; f < t1; ++f) {\n"
          "        const bool first = f == 0;\n"
          "        const size_t fbase = (size_t)f * P;\n"
-         "        {\n"
-         "            float* dst = lds + "
-      << st[lead].buf << " + (f % " << st[lead].slots
-      << ") * CELLS;\n"
-         "            for (int e = threadIdx.x; e < CELLS; e += 256) {\n"
-         "                const int ly = e / RW, lx = e - ly * RW, gx = ox + lx, gy = oy + ly;\n"
-         "                if (gx < 0 || gx >= W || gy < 0 || gy >= H) continue;\n"
-         "                float v = (float)in[fbase + (size_t)gy * W + gx];\n";
-    for (int j = 0; j < lead; ++j) o << "                " << trail_stmt(p.stages[g.first + j], st[j], "e") << "\n";
-    o << "                dst[e] = v;\n            }\n        }\n        __syncthreads();\n";
+         "        float* dst = lds + "
+      << st[lead].buf << " + (f % " << st[lead].slots << ") * CELLS;\n"
+      << "        if (xin) {\n"
+         "#pragma unroll\n"
+         "            for (int k = 0; k < NLV; ++k) {\n"
+         "                const int it = threadIdx.x + 256 * k;\n"
+         "                if (it < NV) {\n"
+         "                    const int ly = it / ND, kd = it - ly * ND;\n";
+    for (int q = 0; q < 4; ++q) {
+        o << "                    if (" << (q < S ? "kd > 0 && " : "") << "4 * kd + " << q - S << " < RW) {\n"
+          << "                        const int e = ly * RW + 4 * kd + " << q - S << ";\n"
+          << "                        float v = " << (u8 ? std::string(vx[q]) : "__uint_as_float(pf[4 * k + " + std::to_string(q) + "])")
+          << ";\n"
+          << lead_stmts << "                        dst[e] = v;\n                    }\n";
+    }
+    o << "                }\n"
+         "            }\n"
+         "        } else {\n"
+         "#pragma unroll\n"
+         "            for (int k = 0; k < NLS; ++k) {\n"
+         "                const int e = threadIdx.x + 256 * k;\n"
+         "                if (e < CELLS) {\n"
+         "                    float v = "
+      << (u8 ? "(float)((pf[k >> 2] >> (8 * (k & 3))) & 255u)" : "__uint_as_float(pf[k])") << ";\n"
+      << lead_stmts
+      << "                    dst[e] = v;\n                }\n            }\n        }\n"
+         "        __syncthreads();\n"
+         "        if (f + 1 < t1)\n"
+      << issue("f + 1");
     int i = lead, hx = HX, hy = HY, back = 0;
     while (i < n) {
         const GStage& s = st[i];
@@ -277,102 +255,137 @@ static std::string jit_march_source(const fz_plan& p, const Segment& g)
         const int ohx = hx - s.rx, ohy = hy - s.ry;
         const bool stencil = s.kind == G_STENCIL;
         const int nw = (2 * s.rx + 1) * (2 * s.ry + 1);
-        auto trail = [&](const std::string& cell, const char* ind) {
-            std::string r;
-            for (int q = i + 1; q < j; ++q) r += std::string(ind) + trail_stmt(p.stages[g.first + q], st[q], cell) + "\n";
-            return r;
-        };
-        o << "        {  // window stage " << i << "\n"
+        int trail_ops = 0;
+        std::string trail;
+        for (int q = i + 1; q < j; ++q) {
+            trail += "                            " + trail_stmt(p.stages[g.first + q], st[q], "base + r * RW + c") + "\n";
+            trail_ops += st[q].kind == G_IIR ? 8 : 2;
+        }
+        // cells across per thread: five (fewer LDS reads per output), four in
+        // the last stage, whose rows then go out as aligned 16-byte stores
+        const int gq = last ? 4 : 5;
+        const int gr = pick_rows(s, TW + 2 * ohx, TH + 2 * ohy, trail_ops, last, gq);
+        o << "        {  // window stage " << i << (stencil ? ": stencil " : ": window sum ") << 2 * s.rx + 1 << "x"
+          << 2 * s.ry + 1 << (s.rt ? " over " + std::to_string(s.rt + 1) + " frames" : std::string()) << "\n"
           << "            constexpr int RX = " << s.rx << ", RY = " << s.ry << ", RT = " << s.rt << ", OHX = " << ohx
-          << ", OHY = " << ohy << ";\n"
-          << "            constexpr int OW = TW + 2 * OHX, OH = TH + 2 * OHY, BX = HX - OHX, BY = HY - OHY;\n"
-          << "            if ((fs == 0 || f >= fs + " << back << ")" << (last ? " && f >= t0" : "") << ") {\n";
+          << ", OHY = " << ohy << ", GR = " << gr << ", GQ = " << gq << ";\n"
+          << "            constexpr int OW = TW + 2 * OHX, OH = TH + 2 * OHY, BX = HX - OHX, BY = HY - OHY;\n";
+        if (!last) o << "            float* dst = lds + " << st[j].buf << " + (f % " << st[j].slots << ") * CELLS;\n";
+        o << "            if ((fs == 0 || f >= fs + " << back << ")" << (last ? " && f >= t0" : "") << ") {\n";
         if (stencil) {
             o << "                constexpr float w[" << nw * (s.rt + 1) << "] = {";
             for (int q = 0; q < nw * (s.rt + 1); ++q) o << (q ? ", " : "") << flit(p.gweights[p.gwoff[g.first + i] + q]);
             o << "};\n";
         }
-        if (!last) o << "                float* dst = lds + " << st[j].buf << " + (f % " << st[j].slots << ") * CELLS;\n";
-        o << "                if (interior) {\n"
-             "                    constexpr int NQ = (OW + GQ - 1) / GQ;\n"
-             "                    for (int e = threadIdx.x; e < NQ * OH; e += 256) {\n"
-             "                        const int cy = e / NQ, cx = (e - cy * NQ) * GQ;\n"
-             "                        const int lx = BX + cx, ly = BY + cy, base = ly * RW + lx;\n"
-             "                        float acc[GQ];\n"
+        // a block of GQ x GR cells per thread; the last row block is moved up
+        // to end at the region's last row (no reads past the buffer) and skips
+        // the rows the block above it owns
+        o << "                constexpr int NQ = (OW + GQ - 1) / GQ, NR = (OH + GR - 1) / GR;\n"
+             "                for (int e = threadIdx.x; e < NQ * NR; e += 256) {\n"
+             "                    const int ry = e / NQ, cx = (e - ry * NQ) * GQ;\n"
+             "                    const int cy = min(ry * GR, OH - GR), skip = ry * GR - cy;\n"
+             "                    const int lx = BX + cx, ly = BY + cy, base = ly * RW + lx;\n"
+             "                    float acc[GR][GQ];\n"
              "#pragma unroll\n"
-             "                        for (int c = 0; c < GQ; ++c) acc[c] = 0.0f;\n"
+             "                    for (int r = 0; r < GR; ++r)\n"
              "#pragma unroll\n"
-             "                        for (int tau = 0; tau <= RT; ++tau) {\n"
-             "                            const float* src = lds + "
+             "                        for (int c = 0; c < GQ; ++c) acc[r][c] = "
+          << (stencil ? "0.0f" : "-0.0f")
+          << ";\n"
+             "#pragma unroll\n"
+             "                    for (int tau = 0; tau <= RT; ++tau) {\n"
+             "                        const float* src = lds + "
           << s.buf << " + (max(f - tau, 0) % " << s.slots
           << ") * CELLS;\n"
              "#pragma unroll\n"
-             "                            for (int v = -RY; v <= RY; ++v) {\n"
-             "                                float x[GQ + 2 * RX];\n"
+             "                        for (int v = -RY; v < GR + RY; ++v) {\n"
+             "                            float x[GQ + 2 * RX];\n"
              "#pragma unroll\n"
-             "                                for (int q = 0; q < GQ + 2 * RX; ++q) x[q] = src[base + v * RW - RX + q];\n";
+             "                            for (int q = 0; q < GQ + 2 * RX; ++q) x[q] = src[base + v * RW - RX + q];\n";
         if (stencil)
             o << "#pragma unroll\n"
+                 "                            for (int r = 0; r < GR; ++r) {\n"
+                 "                                if (v - r < -RY || v - r > RY) continue;\n"
+                 "#pragma unroll\n"
                  "                                for (int u = -RX; u <= RX; ++u) {\n"
-                 "                                    const float wv = w[tau * " << nw << " + (v + RY) * (2 * RX + 1) + (u + RX)];\n"
+                 "                                    const float wv = w[tau * " << nw << " + (v - r + RY) * (2 * RX + 1) + (u + RX)];\n"
                  "#pragma unroll\n"
-                 "                                    for (int c = 0; c < GQ; ++c) acc[c] = fmaf(wv, x[c + u + RX], acc[c]);\n"
-                 "                                }\n";
+                 "                                    for (int c = 0; c < GQ; ++c) acc[r][c] = fmaf(wv, x[c + u + RX], acc[r][c]);\n"
+                 "                                }\n"
+                 "                            }\n";
         else
-            o << "#pragma unroll\n"
-                 "                                for (int c = 0; c < GQ; ++c) {\n"
-                 "                                    float h = 0.0f;\n"
+            o << "                            float h[GQ];\n"
                  "#pragma unroll\n"
-                 "                                    for (int u = -RX; u <= RX; ++u) h = h + x[c + u + RX];\n"
-                 "                                    acc[c] = acc[c] + h;\n"
-                 "                                }\n";
-        o << "                            }\n"
-             "                        }\n"
-             "                        const int nk = OW - cx < GQ ? OW - cx : GQ;\n"
+                 "                            for (int c = 0; c < GQ; ++c) {\n"
+                 "                                h[c] = x[c];\n"
+                 "#pragma unroll\n"
+                 "                                for (int u = 1; u <= 2 * RX; ++u) h[c] = h[c] + x[c + u];\n"
+                 "                            }\n"
+                 "#pragma unroll\n"
+                 "                            for (int r = 0; r < GR; ++r) {\n"
+                 "                                if (v - r < -RY || v - r > RY) continue;\n"
+                 "#pragma unroll\n"
+                 "                                for (int c = 0; c < GQ; ++c) acc[r][c] = acc[r][c] + h[c];\n"
+                 "                            }\n";
+        o << "                        }\n"
+             "                    }\n"
+             "                    const int nk = OW - cx < GQ ? OW - cx : GQ;\n"
              "#pragma unroll\n"
+             "                    for (int r = 0; r < GR; ++r) {\n"
+             "                        if (r < skip) continue;\n";
+        if (last)
+            o << "                        const int gy = oy + ly + r, gx0 = ox + lx;\n"
+                 "                        const bool row_in = gy >= 0 && gy < H;\n"
+                 "                        float* orow = out + fbase + (size_t)gy * W + gx0;\n";
+        if (last)
+            o << "                        if (vec_out) {  // a tile inside the frame: GQ = 4 cells, 16-byte aligned\n"
+                 "                            float vv[GQ];\n"
+                 "#pragma unroll\n"
+                 "                            for (int c = 0; c < GQ; ++c) {\n"
+                 "                                float v = acc[r][c];\n"
+              << trail
+              << "                                vv[c] = v;\n"
+                 "                            }\n"
+                 "                            *(float4*)orow = make_float4(vv[0], vv[1], vv[2], vv[3]);\n"
+                 "                            continue;\n"
+                 "                        }\n";
+        o << "#pragma unroll\n"
              "                        for (int c = 0; c < GQ; ++c) {\n"
              "                            if (c >= nk) break;\n"
-             "                            float v = acc[c];\n"
-          << trail("base + c", "                            ");
+             "                            float v = acc[r][c];\n"
+          << trail;
         if (last)
-            o << "                            out[fbase + (size_t)(oy + ly) * W + (ox + lx + c)] = v;\n";
+            o << "                            if (interior || (row_in && gx0 + c >= 0 && gx0 + c < W)) orow[c] = v;\n";
         else
-            o << "                            dst[base + c] = v;\n";
-        o << "                        }\n                    }\n"
-             "                } else {\n"
-             "                    for (int e = threadIdx.x; e < OW * OH; e += 256) {\n"
-             "                        const int cy = e / OW, cx = e - cy * OW;\n"
-             "                        const int lx = BX + cx, ly = BY + cy, gx = ox + lx, gy = oy + ly;\n"
-             "                        if (gx < 0 || gx >= W || gy < 0 || gy >= H) continue;\n"
-             "                        float acc = 0.0f;\n"
-             "#pragma unroll\n"
-             "                        for (int tau = 0; tau <= RT; ++tau) {\n"
-             "                            const float* src = lds + "
-          << s.buf << " + (max(f - tau, 0) % " << s.slots
-          << ") * CELLS;\n"
-             "#pragma unroll\n"
-             "                            for (int v = -RY; v <= RY; ++v) {\n"
-             "                                const int row = (clampi(gy + v, 0, H - 1) - oy) * RW - ox;\n";
-        if (stencil)
-            o << "#pragma unroll\n"
-                 "                                for (int u = -RX; u <= RX; ++u)\n"
-                 "                                    acc = fmaf(w[tau * " << nw << " + (v + RY) * (2 * RX + 1) + (u + RX)], "
-                 "src[row + clampi(gx + u, 0, W - 1)], acc);\n";
-        else
-            o << "                                float h = 0.0f;\n"
-                 "#pragma unroll\n"
-                 "                                for (int u = -RX; u <= RX; ++u) h = h + src[row + clampi(gx + u, 0, W - 1)];\n"
-                 "                                acc = acc + h;\n";
-        o << "                            }\n"
-             "                        }\n"
-             "                        float v = acc;\n"
-          << trail("ly * RW + lx", "                        ");
-        if (last)
-            o << "                        out[fbase + (size_t)gy * W + gx] = v;\n";
-        else
-            o << "                        dst[ly * RW + lx] = v;\n";
-        o << "                    }\n                }\n            }\n        }\n";
-        if (!last) o << "        __syncthreads();\n";
+            o << "                            dst[base + r * RW + c] = v;\n";
+        o << "                        }\n                    }\n                }\n            }\n";
+        if (!last) {
+            // replicate border of this stage's output for the next stage: only
+            // the out-of-frame cells are visited -- whole rows above and below
+            // the frame, then the columns left and right of it on frame rows
+            o << "            __syncthreads();\n"
+                 "            if (!interior) {\n"
+                 "                const int y0 = clampi(-oy - BY, 0, OH), y1 = clampi(H - oy - BY, y0, OH);\n"
+                 "                const int x0 = clampi(-ox - BX, 0, OW), x1 = clampi(W - ox - BX, x0, OW);\n"
+                 "                const int na = (OH - (y1 - y0)) * OW, ncol = x0 + OW - x1, nall = na + (y1 - y0) * ncol;\n"
+                 "                for (int e = threadIdx.x; e < nall; e += 256) {\n"
+                 "                    int cy, cx;\n"
+                 "                    if (e < na) {\n"
+                 "                        const int r = e / OW;\n"
+                 "                        cx = e - r * OW;\n"
+                 "                        cy = r < y0 ? r : r - y0 + y1;\n"
+                 "                    } else {\n"
+                 "                        const int r = (e - na) / ncol, k = e - na - r * ncol;\n"
+                 "                        cy = y0 + r;\n"
+                 "                        cx = k < x0 ? k : k - x0 + x1;\n"
+                 "                    }\n"
+                 "                    const int lx = BX + cx, ly = BY + cy;\n"
+                 "                    dst[ly * RW + lx] = dst[(clampi(oy + ly, 0, H - 1) - oy) * RW + (clampi(ox + lx, 0, W - 1) - ox)];\n"
+                 "                }\n"
+                 "                __syncthreads();\n"
+                 "            }\n";
+        }
+        o << "        }\n";
         hx = ohx;
         hy = ohy;
         i = j;
@@ -472,25 +485,17 @@ int launch_jit(const fz_plan& p, const Segment& g, const void* in, void* out, co
     GStage st[G_MAX_STAGES];
     g_stage_list(p.stages.data(), g.first, g.last, st);
     int ht = 0;
-    if (g_temporal(st, g.last - g.first + 1, nullptr, &ht)) {  // the frame-marching form
-        const int tiles_x = (p.W + g.tile_w - 1) / g.tile_w, tiles_y = (p.H + g.tile_h - 1) / g.tile_h;
-        const long long blocks = (long long)tiles_x * tiles_y * ((p.T + g.tpb - 1) / g.tpb);
-        if (blocks > 0x7fffffffLL || g.tpb < 1) return (int)hipErrorInvalidConfiguration;
-        int W = p.W, H = p.H, txs = tiles_x, tys = tiles_y, T = p.T, tt = g.tpb, hts = ht;
-        const void* pin = in;
-        float* pout = (float*)out;
-        const void* pck = ckpt;
-        void* args[] = {&pin, &pout, &W, &H, &txs, &tys, &T, &tt, &hts, &pck};
-        return (int)hipModuleLaunchKernel(fn, (unsigned)blocks, 1, 1, BLOCK_THREADS, 1, 1, 0, (hipStream_t)stream,
-                                          args, nullptr);
-    }
+    (void)g_temporal(st, g.last - g.first + 1, nullptr, &ht);
+    const int tt = g.tpb;  // frames per work item (temporal or not)
+    if (tt < 1) return (int)hipErrorInvalidConfiguration;
     const int tiles_x = (p.W + g.tile_w - 1) / g.tile_w, tiles_y = (p.H + g.tile_h - 1) / g.tile_h;
-    const long long blocks = (long long)tiles_x * tiles_y * p.T;
+    const long long blocks = (long long)tiles_x * tiles_y * ((p.T + tt - 1) / tt);
     if (blocks > 0x7fffffffLL) return (int)hipErrorInvalidConfiguration;
-    int W = p.W, H = p.H, txs = tiles_x, tys = tiles_y;
+    int W = p.W, H = p.H, txs = tiles_x, tys = tiles_y, T = p.T, tts = tt, hts = ht;
     const void* pin = in;
     float* pout = (float*)out;
-    void* args[] = {&pin, &pout, &W, &H, &txs, &tys};
+    const void* pck = ckpt;
+    void* args[] = {&pin, &pout, &W, &H, &txs, &tys, &T, &tts, &hts, &pck};
     return (int)hipModuleLaunchKernel(fn, (unsigned)blocks, 1, 1, BLOCK_THREADS, 1, 1, 0, (hipStream_t)stream, args,
                                       nullptr);
 }

@@ -274,6 +274,17 @@ Segment price_generic(const fz_plan& p, int a, int b, int req_w, int req_h, int 
             s.tpb = best_tt;
             items = ceil((double)p.W / s.tile_w) * ceil((double)p.H / s.tile_h) * ceil((double)p.T / s.tpb);
             s.ckpt = n_ck > 0 && s.tpb < p.T;
+        } else if (jit) {
+            // a generated kernel marches a few frames per work item (its set-up
+            // and the last frame's drain amortised): up to four, while at
+            // least JIT_FILL_ITEMS work items remain
+            const double tiles = ceil((double)p.W / s.tile_w) * ceil((double)p.H / s.tile_h);
+            if (req_tpb > 0) {
+                s.tpb = std::min(req_tpb, p.T);
+            } else {
+                s.tpb = 4;
+                while (s.tpb > 1 && tiles * ceil((double)p.T / s.tpb) < JIT_FILL_ITEMS) s.tpb /= 2;
+            }
         }
     }
     const double bin = dt_bytes(p.stages[a].in_dtype);

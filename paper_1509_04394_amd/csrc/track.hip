@@ -21,10 +21,10 @@
 // Launches: the points are bucketed by frame (a histogram, one scan, a
 // scatter into the workspace), then one wavefront marches the frames in
 // order: it sorts the frame's points by (y, x) (rank by counting), predicts
-// every live track, lists the gated candidate pairs, sorts them (rank by
-// counting), takes them greedily (in rounds of candidates first for both
-// their track and their point), updates the tracks, appends the new ones and
-// writes one record per live track.  The list is kept in id order: its first
+// every live track, lists the gated candidate pairs and takes them greedily
+// in rounds of candidates that come first for both their track and their
+// point (no sort of the candidates), updates the tracks, appends the new
+// ones and writes one record per live track.  The list is kept in id order: its first
 // 64 tracks in registers, the rest in the workspace in two buffers
 // (ping-pong on compaction).
 #include <hip/hip_runtime.h>
@@ -159,11 +159,17 @@ struct Cand {
     int16_t ti, pj;
 };
 
-__device__ __forceinline__ bool cand_less(const Cand& a, const Cand& b)
+// Association order: increasing d2, then track id, then point index.  The
+// first part of the key maps d2 (a zero of either sign made +0) to an
+// unsigned integer of the same order; the second is (id, point).
+__device__ __forceinline__ unsigned long long d2_key(double d2)
 {
-    if (a.d2 != b.d2) return a.d2 < b.d2;
-    if (a.id != b.id) return a.id < b.id;
-    return a.pj < b.pj;
+    const unsigned long long b = (unsigned long long)__double_as_longlong(d2 + 0.0);
+    return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
+}
+__device__ __forceinline__ unsigned long long idpj_key(const Cand& c)
+{
+    return (unsigned long long)(uint32_t)c.id << 16 | (uint16_t)c.pj;
 }
 
 __device__ __forceinline__ void put_record(fz_track* out, uint32_t k, uint32_t cap, int t, const DevTrack& tr)
@@ -201,14 +207,20 @@ __global__ __launch_bounds__(TRK_THREADS) void k_trk_run(const int2* bucket, con
 {
     __shared__ int2 pin[TRK_MAX_POINTS];   // the frame's points as loaded
     __shared__ int2 pts[TRK_MAX_POINTS];   // sorted by (y, x)
-    __shared__ Cand cand[TRK_MAX_CANDS];   // as listed
-    __shared__ Cand cs[TRK_MAX_CANDS];     // in increasing (d2, id, point) order
+    // the gated candidates of the frame; after the association, the same
+    // memory holds the next list's first 64 tracks
+    __shared__ union {
+        Cand cand[TRK_MAX_CANDS];
+        DevTrack stage[TRK_THREADS];
+    } cu;
     __shared__ uint8_t ptaken[TRK_MAX_POINTS];
     __shared__ uint8_t calive[TRK_MAX_CANDS];          // candidate still open (association rounds)
     __shared__ int16_t tmatch[FZ_TRACK_MAX_TRACKS];    // point matched to each track, -1 none
-    __shared__ uint32_t tbest[FZ_TRACK_MAX_TRACKS];    // first open candidate of each track (a round)
-    __shared__ uint32_t pbest[TRK_MAX_POINTS];         // first open candidate of each point (a round)
-    __shared__ DevTrack stage[TRK_THREADS];            // the next list's first 64 tracks
+    // first open candidate of each track and point in a round: d2 key, then (id, point) key
+    __shared__ unsigned long long tb_d[FZ_TRACK_MAX_TRACKS], tb_k[FZ_TRACK_MAX_TRACKS];
+    __shared__ unsigned long long pb_d[TRK_MAX_POINTS], pb_k[TRK_MAX_POINTS];
+    Cand* const cand = cu.cand;
+    DevTrack* const stage = cu.stage;
     __shared__ uint32_t s_nc, s_flags;
     const int lane = threadIdx.x;
     const KModel M(o.q, o.r);
@@ -313,39 +325,51 @@ __global__ __launch_bounds__(TRK_THREADS) void k_trk_run(const int2* bucket, con
         }
         __syncthreads();
         const uint32_t nc = min(s_nc, (uint32_t)TRK_MAX_CANDS);
-        // 3. candidates in increasing (d2, id, point) order (keys are distinct)
-        for (uint32_t c = lane; c < nc; c += TRK_THREADS) {
-            const Cand a = cand[c];
-            uint32_t rank = 0;
-            for (uint32_t k = 0; k < nc; ++k) rank += cand_less(cand[k], a) ? 1u : 0u;
-            cs[rank] = a;
-            calive[rank] = 1;
-        }
-        // 4. greedy association in rounds of locally first candidates
+        // 3. greedy association in rounds: an open candidate that comes first
+        // (in the (d2, id, point) order) among the open candidates of both its
+        // track and its point is taken; then every candidate of a taken track
+        // or point closes
+        for (uint32_t c = lane; c < nc; c += TRK_THREADS) calive[c] = 1;
         for (;;) {
             __syncthreads();
             for (uint32_t c = lane; c < nc; c += TRK_THREADS)
                 if (calive[c]) {
-                    tbest[cs[c].ti] = 0xffffffffu;
-                    pbest[cs[c].pj] = 0xffffffffu;
+                    const Cand a = cand[c];
+                    tb_d[a.ti] = tb_k[a.ti] = ~0ull;
+                    pb_d[a.pj] = pb_k[a.pj] = ~0ull;
                 }
             __syncthreads();
             for (uint32_t c = lane; c < nc; c += TRK_THREADS)
                 if (calive[c]) {
-                    atomicMin(&tbest[cs[c].ti], c);
-                    atomicMin(&pbest[cs[c].pj], c);
+                    const Cand a = cand[c];
+                    const unsigned long long d = d2_key(a.d2);
+                    atomicMin(&tb_d[a.ti], d);
+                    atomicMin(&pb_d[a.pj], d);
                 }
             __syncthreads();
             for (uint32_t c = lane; c < nc; c += TRK_THREADS)
-                if (calive[c] && tbest[cs[c].ti] == c && pbest[cs[c].pj] == c) {
-                    tmatch[cs[c].ti] = cs[c].pj;
-                    ptaken[cs[c].pj] = 1;
+                if (calive[c]) {
+                    const Cand a = cand[c];
+                    const unsigned long long d = d2_key(a.d2), k = idpj_key(a);
+                    if (d == tb_d[a.ti]) atomicMin(&tb_k[a.ti], k);
+                    if (d == pb_d[a.pj]) atomicMin(&pb_k[a.pj], k);
+                }
+            __syncthreads();
+            for (uint32_t c = lane; c < nc; c += TRK_THREADS)
+                if (calive[c]) {
+                    const Cand a = cand[c];
+                    const unsigned long long d = d2_key(a.d2), k = idpj_key(a);
+                    if (d == tb_d[a.ti] && k == tb_k[a.ti] && d == pb_d[a.pj] && k == pb_k[a.pj]) {
+                        tmatch[a.ti] = a.pj;
+                        ptaken[a.pj] = 1;
+                    }
                 }
             __syncthreads();
             bool open = false;
             for (uint32_t c = lane; c < nc; c += TRK_THREADS)
                 if (calive[c]) {
-                    if (tmatch[cs[c].ti] >= 0 || ptaken[cs[c].pj])
+                    const Cand a = cand[c];
+                    if (tmatch[a.ti] >= 0 || ptaken[a.pj])
                         calive[c] = 0;
                     else
                         open = true;

@@ -3,7 +3,7 @@ with its stage list, radii, box sizes and weights as constants and compiled
 with hipRTC) against the generic tile kernel and the oracle.
 
 The generated kernel evaluates the same operations in the same order as the
-tile kernel, so the outputs must be equal to the bit for every chain, tile,
+tile kernel, so the outputs must be equal (in value) for every chain, tile,
 partition and frame size; against the FP64 oracle they lie within the FP32
 error bound of tests/parity.py."""
 import numpy as np
@@ -48,10 +48,15 @@ CHAINS = {
 }
 
 
+@pytest.mark.parametrize("width", [203, 204], ids=["w203", "w204"])
 @pytest.mark.parametrize("name", sorted(CHAINS))
-def test_generated_equals_tile_kernel_and_oracle(dev, name):
+def test_generated_equals_tile_kernel_and_oracle(dev, name, width):
+    """Width 203: every tile loads its box cell by cell; width 204 (a
+    multiple of four): tiles inside the frame across load four cells at a
+    time, u8 in the first group and f32 in the later groups of the unfused
+    partition."""
     spec = CHAINS[name]
-    vol = synth.video(203, 117, 5, seed=71)
+    vol = synth.video(width, 117, 5, seed=71)
     for part in ("optimal", "unfused"):
         ref, _ = run(spec, vol, dev, partition=part)
         g, plan = run(spec, vol, dev, partition=part, engine="jit")
@@ -76,6 +81,26 @@ def test_every_generated_tile_same_bits(dev, tile):
     assert np.array_equal(out.cpu().numpy()[0], ref), tile
 
 
+def test_frames_per_work_item(dev):
+    """A group without temporal stages marching several frames per work item
+    (the input box of the next frame loaded while the current one is
+    computed): any run length, including one that does not divide the clip
+    and one longer than it, gives the tile kernel's values."""
+    spec = CHAINS["well"]
+    vol = synth.video(204, 70, 7, seed=77)
+    ref, _ = run(spec, vol, dev, partition=[])
+    T, H, W = vol.shape
+    plan = fz.Plan(spec, W, H, T, partition=[], engine="jit")
+    assert plan.segment_info()[0].frames_per_block >= 1
+    for tpb in (1, 2, 3, 4, 7, 9):
+        plan = fz.Plan(spec, W, H, T, partition=[])
+        plan.set_segment_config(0, engine="jit", tile=(64, 32), frames_per_block=tpb)
+        assert plan.segment_info()[0].frames_per_block == min(tpb, T)
+        out, _, _ = plan.run(torch.from_numpy(vol).to(dev))
+        torch.cuda.synchronize()
+        assert np.array_equal(out.cpu().numpy()[0], ref), tpb
+
+
 @pytest.mark.parametrize("size", [(1, 1, 2), (7, 5, 3), (200, 3, 2), (65, 33, 2)], ids=str)
 def test_tiny_and_ragged_frames(dev, size):
     W, H, T = size
@@ -84,6 +109,24 @@ def test_tiny_and_ragged_frames(dev, size):
         ref, _ = run(spec, vol, dev)
         g, _ = run(spec, vol, dev, engine="jit")
         assert np.array_equal(g, ref), size
+
+
+def test_unaligned_input_pointer(dev):
+    """An input tensor whose data starts one byte past an aligned address
+    (a view into a larger buffer): the four-cell loads are not used for it,
+    and the output equals that of an aligned copy."""
+    spec = CHAINS["well"]
+    vol = synth.video(208, 64, 3, seed=76)
+    ref, _ = run(spec, vol, dev)
+    T, H, W = vol.shape
+    big = torch.zeros(T * H * W + 16, dtype=torch.uint8, device=dev)
+    x = big[1:1 + T * H * W].view(T, H, W)
+    x.copy_(torch.from_numpy(vol).to(dev))
+    assert x.data_ptr() % 4 == 1
+    plan = fz.Plan(spec, W, H, T, engine="jit")
+    out, _, _ = plan.run(x)
+    torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy()[0], ref)
 
 
 def test_large_box_and_batch(dev):
@@ -122,7 +165,11 @@ def test_generated_marching_kernels_equal_interpreted(dev):
     bits as the interpreted marching kernel, for checkpointed and whole-clip
     IIR groups and several frame runs, and within the oracle's bound."""
     from tests.test_gpu_temporal import MIXED, PAPER5, SPATIO
-    vol = synth.video(133, 77, 17, seed=75)
+    for width in (133, 136):
+        marching_case(dev, MIXED, PAPER5, SPATIO, synth.video(width, 77, 17, seed=75))
+
+
+def marching_case(dev, MIXED, PAPER5, SPATIO, vol):
     for name, spec in (("paper5", PAPER5), ("spatio", SPATIO), ("mixed", MIXED)):
         ref, _ = run(spec, vol, dev, partition=[])
         g, plan = run(spec, vol, dev, partition=[], engine="jit")
