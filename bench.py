@@ -331,7 +331,8 @@ def autotune_leg(ops, W, H, T, x, steps, warmup, dev, stream, planner_ms):
     the headline is, beside the planner-sized headline."""
     from paper_1509_04394_amd import autotune, fz
     plan = fz.Plan(ops, W, H, T)
-    report = autotune.autotune(plan, x, reps=3)
+    stats = {}
+    autotune.autotune(plan, x, reps=3, stats=stats)
     bufs = plan.alloc(dev)
     ms, _, _ = time_plan(plan, x, bufs, steps, warmup, stream)
     del bufs
@@ -339,7 +340,7 @@ def autotune_leg(ops, W, H, T, x, steps, warmup, dev, stream, planner_ms):
     log(f"autotuned: {ms:.4f} ms/step ({[(g.tile_w, g.tile_h, g.frames_per_block) for g in s]})")
     return {"ms_per_step": round(ms, 4), "mpx_s": round(W * H * T / (ms * 1e-3) / 1e6, 1),
             "groups": [[g.first, g.last, g.engine, g.tile_w, g.tile_h, g.frames_per_block] for g in s],
-            "configs_tried": sum(1 for _ in report), "planner_ms_per_step": round(planner_ms, 4),
+            "configs_tried": stats.get("tried", 0), "planner_ms_per_step": round(planner_ms, 4),
             "speedup_over_planner": round(planner_ms / ms, 3)}
 
 

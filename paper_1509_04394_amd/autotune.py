@@ -84,10 +84,11 @@ def _time(plan, x, reps):
     return float(np.median([a.elapsed_time(b) for a, b in ev]))
 
 
-def autotune(plan: "fz.Plan", x, reps=5, log=None):
+def autotune(plan: "fz.Plan", x, reps=5, log=None, stats=None):
     """Tune every group of `plan` (a fz.Plan) on input tensor x in place; returns
     [(group, best config, best ms, default ms)].  A configuration is kept only
-    when it beats the planner's by more than 1% (timing noise)."""
+    when it beats the planner's by more than 1% (timing noise).  stats (a
+    dict), if given, receives the number of configurations timed ("tried")."""
     import torch
     ops, W, H, T = plan.ops, plan.W, plan.H, plan.T
     # inputs of each group: run the plan's own prefix
@@ -113,6 +114,8 @@ def autotune(plan: "fz.Plan", x, reps=5, log=None):
             except fz.FzError:
                 continue
             ms = _time(trial, ins[i], reps)
+            if stats is not None:
+                stats["tried"] = stats.get("tried", 0) + 1
             if log:
                 log(f"[autotune] group {s.first}..{s.last} {cfg}: {ms:.3f} ms")
             if ms < best[1] * (0.99 if best[0] is None else 1.0):

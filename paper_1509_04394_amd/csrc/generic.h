@@ -157,6 +157,9 @@ constexpr int N_JIT_TILES = 5;
 // several frames per item (two rounds of four 256-thread workgroups per CU).
 constexpr int JIT_FILL_ITEMS = 2048;
 extern const int JIT_TILES[N_JIT_TILES][2];
+// LDS row pitch (cells) of a generated kernel's buffers for stages st[0..n)
+// on TW x TH tiles with halos HX, HY (at least TW + 2 HX).
+int jit_pitch(const GStage* st, int n, int TW, int TH, int HX, int HY);
 
 // A group whose IIR stages all come before its first window stage, and whose
 // stencils do not look back, can run in frame runs shorter than the clip: a

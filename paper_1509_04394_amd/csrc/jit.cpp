@@ -31,6 +31,7 @@
 
 #include "fz_internal.h"
 #include "generic.h"
+#include "jit_layout.h"
 
 namespace fz {
 
@@ -69,34 +70,6 @@ static std::string trail_stmt(const fz_stage& s, const GStage& gs, const std::st
            ") * (first ? x : *sp)); *sp = y; v = (float)y; }";
 }
 
-// Rows of outputs per thread of a window stage: each thread computes a block
-// of GQ x gr cells (gr <= 2), so the input rows it reads and (for a window
-// sum) the row sums it forms serve gr output rows.  Chosen by a count of wave
-// instructions: wave passes (ceil(items / 64)) times an estimate of the
-// instructions per item.
-static int pick_rows(const GStage& s, int ow, int oh, int trail_ops, bool last, int GQ)
-{
-    const int nq = (ow + GQ - 1) / GQ;
-    int best = 1;
-    long best_cost = -1;
-    for (int gr = 1; gr <= 2 && gr <= oh; ++gr) {  // four rows: ~30 more registers, a wave fewer per SIMD
-        const int items = nq * ((oh + gr - 1) / gr);
-        const int rows_in = gr + 2 * s.ry;
-        long per = 14 + (long)GQ * gr * (1 + trail_ops + (last ? 1 : 0));
-        if (s.kind == G_STENCIL)
-            per += (long)GQ * gr * (2 * s.rx + 1) * (2 * s.ry + 1) * (s.rt + 1);
-        else
-            per += (long)(s.rt + 1) * (rows_in * GQ * 2 * s.rx + (long)gr * GQ * 2 * s.ry);
-        if (last) per += 4L * gr;
-        const long cost = (long)((items + 63) / 64) * per;
-        if (best_cost < 0 || cost < best_cost) {
-            best_cost = cost;
-            best = gr;
-        }
-    }
-    return best;
-}
-
 // The group's kernel.  One form serves every generic window group: a work
 // item is an output tile and a run of tt frames (tt = 1 and no temporal halo
 // for a group without temporal stages).  Borders: a tile whose box leaves the
@@ -116,7 +89,8 @@ std::string jit_source(const fz_plan& p, const Segment& g)
     const int n = g.last - g.first + 1;
     GStage st[G_MAX_STAGES];
     g_stage_list(p.stages.data(), g.first, g.last, st);
-    const int floats = march_layout(st, n, (TW + 2 * HX) * (TH + 2 * HY)) + GEN_PAD;
+    const int LP = jit_pitch(st, n, TW, TH, HX, HY);
+    const int floats = march_layout(st, n, LP * (TH + 2 * HY)) + GEN_PAD;
     const int ck_n = g.ckpt ? g_ckpt_iirs(st, n) : 0;
     const bool u8 = p.stages[g.first].in_dtype == FZ_U8;
     const int S = (4 - HX % 4) % 4;  // tiles are a multiple of 4 wide: ox = tx TW - HX = S (mod 4)
@@ -126,7 +100,8 @@ std::string jit_source(const fz_plan& p, const Segment& g)
       << "* __restrict__ in, float* __restrict__ out, int W, int H, int tiles_x, int tiles_y, int T, int tt, "
          "int ht, const double* __restrict__ ckpt)\n{\n"
       << "    constexpr int TW = " << TW << ", TH = " << TH << ", HX = " << HX << ", HY = " << HY
-      << ", RW = TW + 2 * HX, RH = TH + 2 * HY, CELLS = RW * RH;\n"
+      << ", RW = TW + 2 * HX, RH = TH + 2 * HY, LP = " << LP
+      << ", CELLS = LP * RH, BOX = RW * RH;  // LP: LDS row pitch\n"
       << "    __shared__ double lds_d[" << (floats + 1) / 2 << "];\n"
       << "    float* lds = (float*)lds_d;\n"
          // blocks dealt to XCDs round-robin: contiguous runs of tiles per XCD
@@ -148,12 +123,13 @@ std::string jit_source(const fz_plan& p, const Segment& g)
              "        const double* ck = ckpt + (size_t)(t0 / tt - 1) * "
           << ck_n
           << " * P;\n"
-             "        for (int e = threadIdx.x; e < CELLS; e += 256) {\n"
+             "        for (int e = threadIdx.x; e < BOX; e += 256) {\n"
              "            const int ly = e / RW, lx = e - ly * RW;\n"
              "            const size_t gi = (size_t)clampi(oy + ly, 0, H - 1) * W + clampi(ox + lx, 0, W - 1);\n";
         int k = 0;
         for (int j = 0; j < lead; ++j)
-            if (st[j].kind == G_IIR) o << "            ((double*)(lds + " << st[j].buf << "))[e] = ck[(size_t)" << k++ << " * P + gi];\n";
+            if (st[j].kind == G_IIR)
+                o << "            ((double*)(lds + " << st[j].buf << "))[ly * LP + lx] = ck[(size_t)" << k++ << " * P + gi];\n";
         o << "        }\n        __syncthreads();\n    }\n";
     }
     std::string lead_stmts;
@@ -189,7 +165,7 @@ std::string jit_source(const fz_plan& p, const Segment& g)
              "#pragma unroll\n"
              "                for (int k = 0; k < NLS; ++k) {\n"
              "                    const int e = threadIdx.x + 256 * k;\n"
-             "                    if (e < CELLS) {\n"
+             "                    if (e < BOX) {\n"
              "                        const int ly = e / RW, lx = e - ly * RW;\n"
              "                        const size_t gi = gb + (size_t)clampi(oy + ly, 0, H - 1) * W + clampi(ox + lx, 0, W - 1);\n";
         if (u8)
@@ -206,7 +182,7 @@ std::string jit_source(const fz_plan& p, const Segment& g)
     const char* vx[4] = {"(float)(pf[k] & 255u)", "(float)((pf[k] >> 8) & 255u)", "(float)((pf[k] >> 16) & 255u)",
                          "(float)(pf[k] >> 24)"};
     o << "    constexpr int S = " << S
-      << ", ND = (RW + S + 3) / 4, NV = RH * ND, NLV = (NV + 255) / 256, NLS = (CELLS + 255) / 256;\n"
+      << ", ND = (RW + S + 3) / 4, NV = RH * ND, NLV = (NV + 255) / 256, NLS = (BOX + 255) / 256;\n"
       << "    constexpr int NPF = " << (u8 ? "NLV > (NLS + 3) / 4 ? NLV : (NLS + 3) / 4" : "4 * NLV > NLS ? 4 * NLV : NLS")
       << ";\n"
          "    const int a0 = ox - S;\n"
@@ -226,7 +202,7 @@ std::string jit_source(const fz_plan& p, const Segment& g)
          "                    const int ly = it / ND, kd = it - ly * ND;\n";
     for (int q = 0; q < 4; ++q) {
         o << "                    if (" << (q < S ? "kd > 0 && " : "") << "4 * kd + " << q - S << " < RW) {\n"
-          << "                        const int e = ly * RW + 4 * kd + " << q - S << ";\n"
+          << "                        const int e = ly * LP + 4 * kd + " << q - S << ";\n"
           << "                        float v = " << (u8 ? std::string(vx[q]) : "__uint_as_float(pf[4 * k + " + std::to_string(q) + "])")
           << ";\n"
           << lead_stmts << "                        dst[e] = v;\n                    }\n";
@@ -236,8 +212,9 @@ std::string jit_source(const fz_plan& p, const Segment& g)
          "        } else {\n"
          "#pragma unroll\n"
          "            for (int k = 0; k < NLS; ++k) {\n"
-         "                const int e = threadIdx.x + 256 * k;\n"
-         "                if (e < CELLS) {\n"
+         "                const int eb = threadIdx.x + 256 * k;\n"
+         "                if (eb < BOX) {\n"
+         "                    const int ey = eb / RW, e = ey * LP + (eb - ey * RW);\n"
          "                    float v = "
       << (u8 ? "(float)((pf[k >> 2] >> (8 * (k & 3))) & 255u)" : "__uint_as_float(pf[k])") << ";\n"
       << lead_stmts
@@ -245,26 +222,17 @@ std::string jit_source(const fz_plan& p, const Segment& g)
          "        __syncthreads();\n"
          "        if (f + 1 < t1)\n"
       << issue("f + 1");
-    int i = lead, hx = HX, hy = HY, back = 0;
-    while (i < n) {
+    int back = 0;
+    for (const WinStep& ws : win_steps(st, n, TW, TH, HX, HY)) {
+        const int i = ws.i, j = ws.j, ohx = ws.ohx, ohy = ws.ohy, gq = ws.gq, gr = ws.gr;
+        const bool last = ws.last;
         const GStage& s = st[i];
-        int j = i + 1;
-        while (j < n && !g_is_window(st[j].kind)) ++j;
-        const bool last = j == n;
         back += s.rt;
-        const int ohx = hx - s.rx, ohy = hy - s.ry;
         const bool stencil = s.kind == G_STENCIL;
         const int nw = (2 * s.rx + 1) * (2 * s.ry + 1);
-        int trail_ops = 0;
         std::string trail;
-        for (int q = i + 1; q < j; ++q) {
-            trail += "                            " + trail_stmt(p.stages[g.first + q], st[q], "base + r * RW + c") + "\n";
-            trail_ops += st[q].kind == G_IIR ? 8 : 2;
-        }
-        // cells across per thread: five (fewer LDS reads per output), four in
-        // the last stage, whose rows then go out as aligned 16-byte stores
-        const int gq = last ? 4 : 5;
-        const int gr = pick_rows(s, TW + 2 * ohx, TH + 2 * ohy, trail_ops, last, gq);
+        for (int q = i + 1; q < j; ++q)
+            trail += "                            " + trail_stmt(p.stages[g.first + q], st[q], "base + r * LP + c") + "\n";
         o << "        {  // window stage " << i << (stencil ? ": stencil " : ": window sum ") << 2 * s.rx + 1 << "x"
           << 2 * s.ry + 1 << (s.rt ? " over " + std::to_string(s.rt + 1) + " frames" : std::string()) << "\n"
           << "            constexpr int RX = " << s.rx << ", RY = " << s.ry << ", RT = " << s.rt << ", OHX = " << ohx
@@ -284,7 +252,7 @@ std::string jit_source(const fz_plan& p, const Segment& g)
              "                for (int e = threadIdx.x; e < NQ * NR; e += 256) {\n"
              "                    const int ry = e / NQ, cx = (e - ry * NQ) * GQ;\n"
              "                    const int cy = min(ry * GR, OH - GR), skip = ry * GR - cy;\n"
-             "                    const int lx = BX + cx, ly = BY + cy, base = ly * RW + lx;\n"
+             "                    const int lx = BX + cx, ly = BY + cy, base = ly * LP + lx;\n"
              "                    float acc[GR][GQ];\n"
              "#pragma unroll\n"
              "                    for (int r = 0; r < GR; ++r)\n"
@@ -301,7 +269,7 @@ std::string jit_source(const fz_plan& p, const Segment& g)
              "                        for (int v = -RY; v < GR + RY; ++v) {\n"
              "                            float x[GQ + 2 * RX];\n"
              "#pragma unroll\n"
-             "                            for (int q = 0; q < GQ + 2 * RX; ++q) x[q] = src[base + v * RW - RX + q];\n";
+             "                            for (int q = 0; q < GQ + 2 * RX; ++q) x[q] = src[base + v * LP - RX + q];\n";
         if (stencil)
             o << "#pragma unroll\n"
                  "                            for (int r = 0; r < GR; ++r) {\n"
@@ -357,7 +325,7 @@ std::string jit_source(const fz_plan& p, const Segment& g)
         if (last)
             o << "                            if (interior || (row_in && gx0 + c >= 0 && gx0 + c < W)) orow[c] = v;\n";
         else
-            o << "                            dst[base + r * RW + c] = v;\n";
+            o << "                            dst[base + r * LP + c] = v;\n";
         o << "                        }\n                    }\n                }\n            }\n";
         if (!last) {
             // replicate border of this stage's output for the next stage: only
@@ -380,15 +348,12 @@ std::string jit_source(const fz_plan& p, const Segment& g)
                  "                        cx = k < x0 ? k : k - x0 + x1;\n"
                  "                    }\n"
                  "                    const int lx = BX + cx, ly = BY + cy;\n"
-                 "                    dst[ly * RW + lx] = dst[(clampi(oy + ly, 0, H - 1) - oy) * RW + (clampi(ox + lx, 0, W - 1) - ox)];\n"
+                 "                    dst[ly * LP + lx] = dst[(clampi(oy + ly, 0, H - 1) - oy) * LP + (clampi(ox + lx, 0, W - 1) - ox)];\n"
                  "                }\n"
                  "                __syncthreads();\n"
                  "            }\n";
         }
         o << "        }\n";
-        hx = ohx;
-        hy = ohy;
-        i = j;
     }
     o << "        __syncthreads();\n    }\n}\n";
     return o.str();

@@ -237,8 +237,10 @@ Segment price_generic(const fz_plan& p, int a, int b, int req_w, int req_h, int 
             const int tw = jit ? JIT_TILES[t][0] : tile_w(t), th = jit ? JIT_TILES[t][1] : tile_h(t);
             if (req_w > 0 && (tw != req_w || th != req_h)) continue;
             const int cells = (tw + 2 * hx) * (th + 2 * hy);
-            const int lds = temporal ? (march_layout(st, n, cells) + GEN_PAD) * 4
-                                     : generic_lds_bytes(tw, th, hx, hy, nwin);
+            // a generated kernel: the marching layout (either kind of group) at its LDS row pitch
+            const int lds = jit ? (march_layout(st, n, jit_pitch(st, n, tw, th, hx, hy) * (th + 2 * hy)) + GEN_PAD) * 4
+                            : temporal ? (march_layout(st, n, cells) + GEN_PAD) * 4
+                                       : generic_lds_bytes(tw, th, hx, hy, nwin);
             if (lds > p.lds_budget) continue;
             const double tiles = ceil((double)p.W / tw) * ceil((double)p.H / th);
             int tt = tt_fixed;

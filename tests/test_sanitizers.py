@@ -1,5 +1,6 @@
 """The host code under AddressSanitizer and UndefinedBehaviorSanitizer (CPU
-only): the planner and cost-model host code (`planner.cpp`, `cost.cpp`, with
+only): the planner and cost-model host code (`planner.cpp`, `cost.cpp`,
+`jit_layout.cpp`, with
 host stand-ins for the device-side functions) driven over every fixed
 sub-chain, random generic chains (temporal stages included), configuration
 overrides, the partition model and learned planning; and the oracle's C code
@@ -55,7 +56,8 @@ def write_chains(path, seeds):
 def test_planner_under_sanitizers(tmp_path):
     exe = str(tmp_path / "planner_driver")
     srcs = [os.path.join(HERE, "sanitize", "planner_driver.cpp"), os.path.join(HERE, "sanitize", "device_stubs.cpp"),
-            os.path.join(CSRC, "planner.cpp"), os.path.join(CSRC, "cost.cpp")]
+            os.path.join(CSRC, "planner.cpp"), os.path.join(CSRC, "cost.cpp"),
+            os.path.join(CSRC, "jit_layout.cpp")]
     subprocess.check_call(["g++", "-std=c++17", *SAN, f"-I{os.path.join(ROOT, 'include')}", f"-I{CSRC}", *srcs,
                            "-o", exe])
     chains = str(tmp_path / "chains.txt")
