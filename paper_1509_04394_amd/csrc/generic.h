@@ -158,8 +158,12 @@ constexpr int N_JIT_TILES = 5;
 constexpr int JIT_FILL_ITEMS = 2048;
 extern const int JIT_TILES[N_JIT_TILES][2];
 // LDS row pitch (cells) of a generated kernel's buffers for stages st[0..n)
-// on TW x TH tiles with halos HX, HY (at least TW + 2 HX).
+// on TW x TH tiles with halos HX, HY (at least TW + 2 HX rounded up to the
+// box's four-cell groups, so a row of IIR states by group fits).
 int jit_pitch(const GStage* st, int n, int TW, int TH, int HX, int HY);
+// A generated kernel's LDS layout (march_layout's, with the IIRs before the
+// first window stage in registers instead): sets buf / slots, returns floats.
+int jit_layout(GStage* st, int n, int cells);
 
 // A group whose IIR stages all come before its first window stage, and whose
 // stencils do not look back, can run in frame runs shorter than the clip: a

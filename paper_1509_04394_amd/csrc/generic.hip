@@ -456,29 +456,38 @@ __global__ __launch_bounds__(BLOCK_THREADS) void k_gmarch(const GParams p)
 
 // A group of point and IIR stages only: each thread owns PX neighbouring
 // pixels and marches through every frame in order; D frames are loaded before
-// any is processed, so D loads per thread are in flight at once.  The IIR
-// states (doubles) live in LDS, PX per thread and IIR stage (GStage::buf is
-// the stage's offset there, in doubles); registers indexed by a stage number
-// only known at run time would have gone to scratch memory.
+// any is processed, so D loads per thread are in flight at once.  With ONE
+// (the group has a single IIR) its states are PX registers; otherwise the
+// IIR states (doubles) live in LDS, PX per thread and IIR stage (GStage::buf
+// is the stage's offset there, in doubles): registers indexed by a stage
+// number only known at run time would have gone to scratch memory.
 //
 // With CKPT, the kernel is the first pass of a checkpointed group: it runs
 // the group's leading point and IIR stages only (p.n of them), stores no
 // output, and after the last frame of every frame run but the last writes
 // each IIR's state to p.ckpt[run][IIR][pixel].
-template <int PX, int D, bool CKPT>
+template <int PX, int D, bool CKPT, bool ONE, bool RAW = false>
 __global__ __launch_bounds__(BLOCK_THREADS) void k_gstream_t(const GParams p)
 {
     extern __shared__ double gstate[];
+    double rstate[PX];  // ONE: the IIR's states
+#pragma unroll
+    for (int k = 0; k < PX; ++k) rstate[k] = 0.0;
     const size_t P = (size_t)p.W * p.H;
     const size_t i0 = ((size_t)blockIdx.x * BLOCK_THREADS + threadIdx.x) * PX;
     if (i0 >= P) return;  // no barrier below
     for (int t = 0; t < p.T; t += D) {
-        float v[D][PX];
+        // RAW (u8 input, four pixels): the D frames' bytes stay packed, one
+        // register per frame, so many frames can be in flight
+        float v[RAW ? 1 : D][PX];
+        uint32_t raw[RAW ? D : 1];
 #pragma unroll
         for (int d = 0; d < D; ++d) {
             if (t + d >= p.T) break;
             const size_t gi = (size_t)(t + d) * P + i0;
-            if constexpr (PX == 4) {
+            if constexpr (RAW) {
+                raw[d] = *(const uint32_t*)((const uint8_t*)p.in + gi);
+            } else if constexpr (PX == 4) {
                 if (p.in_u8) {
                     const uchar4 q = *(const uchar4*)((const uint8_t*)p.in + gi);
                     v[d][0] = q.x;
@@ -499,38 +508,45 @@ __global__ __launch_bounds__(BLOCK_THREADS) void k_gstream_t(const GParams p)
 #pragma unroll
         for (int d = 0; d < D; ++d) {
             if (t + d >= p.T) break;
+            float w[PX];
+#pragma unroll
+            for (int k = 0; k < PX; ++k) w[k] = RAW ? (float)((raw[RAW ? d : 0] >> (8 * k)) & 255u) : v[RAW ? 0 : d][k];
             const bool first = t + d == 0;
             const bool save = CKPT && (t + d + 1) % p.tt == 0 && t + d + 1 < p.T;
             int n_iir = 0;
             for (int j = 0; j < p.n; ++j) {
                 const GStage s = p.st[j];
                 if (s.kind == G_IIR) {
-                    double* sp = gstate + s.buf + threadIdx.x * PX;
+                    double* sp = ONE ? rstate : gstate + s.buf + threadIdx.x * PX;
                     const double a = (double)s.a;
 #pragma unroll
                     for (int k = 0; k < PX; ++k) {
-                        const double x = (double)v[d][k];
-                        const double y = fma(a, x, (1.0 - a) * (first ? x : sp[k]));
-                        sp[k] = y;
-                        v[d][k] = (float)y;
+                        const double x = (double)w[k];
+                        const double prev = ONE ? rstate[k] : sp[k];
+                        const double y = fma(a, x, (1.0 - a) * (first ? x : prev));
+                        if (ONE)
+                            rstate[k] = y;
+                        else
+                            sp[k] = y;
+                        w[k] = (float)y;
                     }
                     if (save) {
                         double* ck = (double*)p.ckpt + ((size_t)((t + d + 1) / p.tt - 1) * p.ck_n + n_iir) * P + i0;
 #pragma unroll
-                        for (int k = 0; k < PX; ++k) ck[k] = sp[k];
+                        for (int k = 0; k < PX; ++k) ck[k] = ONE ? rstate[k] : sp[k];
                     }
                     ++n_iir;
                 } else {
 #pragma unroll
-                    for (int k = 0; k < PX; ++k) v[d][k] = gpoint(s, v[d][k]);
+                    for (int k = 0; k < PX; ++k) w[k] = gpoint(s, w[k]);
                 }
             }
             if constexpr (!CKPT) {
                 const size_t gi = (size_t)(t + d) * P + i0;
                 if constexpr (PX == 4)
-                    *(float4*)(p.out + gi) = make_float4(v[d][0], v[d][1], v[d][2], v[d][3]);
+                    *(float4*)(p.out + gi) = make_float4(w[0], w[1], w[2], w[3]);
                 else
-                    p.out[gi] = v[d][0];
+                    p.out[gi] = w[0];
             }
         }
     }
@@ -565,22 +581,36 @@ static hipError_t launch_tile(const GParams& gp, int lds, bool march, int nchunk
 template <bool CKPT>
 static hipError_t launch_stream_t(GParams gp, const void* in, size_t P, hipStream_t s)
 {
+    int n_iir = 0;
+    for (int j = 0; j < gp.n; ++j) n_iir += gp.st[j].kind == G_IIR ? 1 : 0;
+    const bool one = n_iir == 1;
+    // four pixels per thread where aligned; with one IIR on u8 input (its
+    // states in registers, the input bytes kept packed) 32 frames are loaded
+    // ahead: every thread marches all frames in order, so the kernel lives on
+    // the bytes in flight, and a pixel per thread (64-byte pieces of frames
+    // far apart) read at a fraction of the bandwidth
     const bool vec = P % 4 == 0 && ((uintptr_t)in % (gp.in_u8 ? 4 : 16)) == 0 &&
                      (CKPT || ((uintptr_t)gp.out % 16) == 0);
     const int px = vec ? 4 : 1;
-    int n_iir = 0;
+    n_iir = 0;
     for (int j = 0; j < gp.n; ++j)
         if (gp.st[j].kind == G_IIR) gp.st[j].buf = (n_iir++) * BLOCK_THREADS * px;
-    const int lds = n_iir * BLOCK_THREADS * px * 8;  // doubles; a 4-pixel run with 16 IIRs: 128 KB
+    const int lds = one ? 0 : n_iir * BLOCK_THREADS * px * 8;  // doubles; a 4-pixel run with 16 IIRs: 128 KB
     hipError_t e = hipSuccess;
-    if (lds > 65536) e = vec ? allow_lds(k_gstream_t<4, 8, CKPT>, lds) : allow_lds(k_gstream_t<1, 8, CKPT>, lds);
+    if (lds > 65536) e = vec ? allow_lds(k_gstream_t<4, 8, CKPT, false>, lds) : allow_lds(k_gstream_t<1, 8, CKPT, false>, lds);
     if (e != hipSuccess) return e;
     const size_t threads = P / px;
     const unsigned blocks = (unsigned)((threads + BLOCK_THREADS - 1) / BLOCK_THREADS);
-    if (vec)
-        k_gstream_t<4, 8, CKPT><<<dim3(blocks), dim3(BLOCK_THREADS), lds, s>>>(gp);
+    if (vec && one && gp.in_u8)
+        k_gstream_t<4, 32, CKPT, true, true><<<dim3(blocks), dim3(BLOCK_THREADS), lds, s>>>(gp);
+    else if (vec && one)
+        k_gstream_t<4, 8, CKPT, true><<<dim3(blocks), dim3(BLOCK_THREADS), lds, s>>>(gp);
+    else if (vec)
+        k_gstream_t<4, 8, CKPT, false><<<dim3(blocks), dim3(BLOCK_THREADS), lds, s>>>(gp);
+    else if (one)
+        k_gstream_t<1, 8, CKPT, true><<<dim3(blocks), dim3(BLOCK_THREADS), lds, s>>>(gp);
     else
-        k_gstream_t<1, 8, CKPT><<<dim3(blocks), dim3(BLOCK_THREADS), lds, s>>>(gp);
+        k_gstream_t<1, 8, CKPT, false><<<dim3(blocks), dim3(BLOCK_THREADS), lds, s>>>(gp);
     return hipGetLastError();
 }
 

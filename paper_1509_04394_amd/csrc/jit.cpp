@@ -90,7 +90,7 @@ std::string jit_source(const fz_plan& p, const Segment& g)
     GStage st[G_MAX_STAGES];
     g_stage_list(p.stages.data(), g.first, g.last, st);
     const int LP = jit_pitch(st, n, TW, TH, HX, HY);
-    const int floats = march_layout(st, n, LP * (TH + 2 * HY)) + GEN_PAD;
+    const int floats = jit_layout(st, n, LP * (TH + 2 * HY)) + GEN_PAD;
     const int ck_n = g.ckpt ? g_ckpt_iirs(st, n) : 0;
     const bool u8 = p.stages[g.first].in_dtype == FZ_U8;
     const int S = (4 - HX % 4) % 4;  // tiles are a multiple of 4 wide: ox = tx TW - HX = S (mod 4)
@@ -102,6 +102,7 @@ std::string jit_source(const fz_plan& p, const Segment& g)
       << "    constexpr int TW = " << TW << ", TH = " << TH << ", HX = " << HX << ", HY = " << HY
       << ", RW = TW + 2 * HX, RH = TH + 2 * HY, LP = " << LP
       << ", CELLS = LP * RH, BOX = RW * RH;  // LP: LDS row pitch\n"
+      << "    constexpr int S = " << S << ", ND = (RW + S + 3) / 4, NV = RH * ND;  // four-cell groups of the box\n"
       << "    __shared__ double lds_d[" << (floats + 1) / 2 << "];\n"
       << "    float* lds = (float*)lds_d;\n"
          // blocks dealt to XCDs round-robin: contiguous runs of tiles per XCD
@@ -118,40 +119,65 @@ std::string jit_source(const fz_plan& p, const Segment& g)
          "    const bool vec_out = interior && (W & 3) == 0 && ((size_t)out & 15) == 0;\n";
     int lead = 0;
     while (lead < n && !g_is_window(st[lead].kind)) ++lead;
+    // The input box is handled in four-cell groups (row ly, group kd: cells
+    // lx = 4 kd + q - S, q = 0..3), group it = ly ND + kd by thread it mod
+    // 256, the same threads every frame: groups of a tile inside the frame
+    // across are loaded with one aligned load, others cell by cell with
+    // clamped coordinates.  A leading IIR's double states are the thread's
+    // registers ist<j>[k][q] (k: its k-th group), restored from the
+    // checkpoint of the run before.
+    o << "    constexpr int NLV = (NV + 255) / 256, NPF = " << (u8 ? "NLV" : "4 * NLV") << ";\n"
+         "    const int a0 = ox - S;\n"
+         "    unsigned int pf[NPF];  // the next box: four u8 cells or one f32 cell per word\n";
+    int n_lead_iir = 0;
+    for (int j = 0; j < lead; ++j)
+        if (st[j].kind == G_IIR) o << "    double ist" << n_lead_iir++ << "[NLV][4];\n";
     if (ck_n > 0) {
         o << "    if (t0 > 0) {  // the leading IIRs resume from the first pass's state after frame t0 - 1\n"
              "        const double* ck = ckpt + (size_t)(t0 / tt - 1) * "
           << ck_n
           << " * P;\n"
-             "        for (int e = threadIdx.x; e < BOX; e += 256) {\n"
-             "            const int ly = e / RW, lx = e - ly * RW;\n"
-             "            const size_t gi = (size_t)clampi(oy + ly, 0, H - 1) * W + clampi(ox + lx, 0, W - 1);\n";
-        int k = 0;
-        for (int j = 0; j < lead; ++j)
-            if (st[j].kind == G_IIR)
-                o << "            ((double*)(lds + " << st[j].buf << "))[ly * LP + lx] = ck[(size_t)" << k++ << " * P + gi];\n";
-        o << "        }\n        __syncthreads();\n    }\n";
+             "#pragma unroll\n"
+             "        for (int k = 0; k < NLV; ++k) {\n"
+             "            const int it = threadIdx.x + 256 * k;\n"
+             "            if (it < NV) {\n"
+             "                const int ly = it / ND, kd = it - ly * ND;\n"
+             "#pragma unroll\n"
+             "                for (int q = 0; q < 4; ++q) {\n"
+             "                    const int lx = 4 * kd + q - S;\n"
+             "                    if (lx < 0 || lx >= RW) continue;\n"
+             "                    const size_t gi = (size_t)clampi(oy + ly, 0, H - 1) * W + clampi(ox + lx, 0, W - 1);\n";
+        for (int k = 0; k < n_lead_iir; ++k) o << "                    ist" << k << "[k][q] = ck[(size_t)" << k << " * P + gi];\n";
+        o << "                }\n            }\n        }\n    }\n";
     }
     std::string lead_stmts;
-    for (int j = 0; j < lead; ++j) lead_stmts += "                            " + trail_stmt(p.stages[g.first + j], st[j], "e") + "\n";
-    // The input box of a frame is loaded into registers (pf) one frame ahead:
-    // the loads of frame f + 1 are issued right after frame f's box is in LDS
-    // and are in flight while frame f's window stages run.  pf holds raw
-    // words: four u8 cells or one f32 cell each.
+    {
+        int k = 0;
+        for (int j = 0; j < lead; ++j) {
+            const fz_stage& fs = p.stages[g.first + j];
+            if (st[j].kind == G_IIR) {
+                const std::string a = "(double)" + flit(fs.param[0]), r = "ist" + std::to_string(k++) + "[k][Q]";
+                lead_stmts += "                        { const double x = (double)v; const double y = fma(" + a + ", x, (1.0 - " +
+                              a + ") * (first ? x : " + r + ")); " + r + " = y; v = (float)y; }\n";
+            } else {
+                lead_stmts += "                        " + point_stmt(fs) + "\n";
+            }
+        }
+    }
     const char* vt = u8 ? "unsigned int" : "float4";
     auto issue = [&](const std::string& frame) {
         std::ostringstream q;
         q << "        {  // loads of frame " << frame << "'s box\n"
           << "            const size_t gb = (size_t)(" << frame << ") * P;\n"
-          << "            if (xin) {\n"
              "#pragma unroll\n"
-             "                for (int k = 0; k < NLV; ++k) {\n"
-             "                    const int it = threadIdx.x + 256 * k;\n"
-             "                    if (it < NV) {\n"
-             "                        const int ly = it / ND, kd = it - ly * ND;\n"
+             "            for (int k = 0; k < NLV; ++k) {\n"
+             "                const int it = threadIdx.x + 256 * k;\n"
+             "                if (it < NV) {\n"
+             "                    const int ly = it / ND, kd = it - ly * ND;\n"
+             "                    const size_t rb = gb + (size_t)clampi(oy + ly, 0, H - 1) * W;\n"
+             "                    if (xin) {\n"
              "                        const "
-          << vt << " w = *(const " << vt
-          << "*)(in + gb + (size_t)clampi(oy + ly, 0, H - 1) * W + a0 + 4 * kd);\n";
+          << vt << " w = *(const " << vt << "*)(in + rb + a0 + 4 * kd);\n";
         if (u8)
             q << "                        pf[k] = w;\n";
         else
@@ -159,20 +185,19 @@ std::string jit_source(const fz_plan& p, const Segment& g)
                  "                        pf[4 * k + 1] = __float_as_uint(w.y);\n"
                  "                        pf[4 * k + 2] = __float_as_uint(w.z);\n"
                  "                        pf[4 * k + 3] = __float_as_uint(w.w);\n";
-        q << "                    }\n"
-             "                }\n"
-             "            } else {\n"
-             "#pragma unroll\n"
-             "                for (int k = 0; k < NLS; ++k) {\n"
-             "                    const int e = threadIdx.x + 256 * k;\n"
-             "                    if (e < BOX) {\n"
-             "                        const int ly = e / RW, lx = e - ly * RW;\n"
-             "                        const size_t gi = gb + (size_t)clampi(oy + ly, 0, H - 1) * W + clampi(ox + lx, 0, W - 1);\n";
+        q << "                    } else {\n";
         if (u8)
-            q << "                        const unsigned int bv = in[gi];\n"
-                 "                        pf[k >> 2] = (k & 3) == 0 ? bv : pf[k >> 2] | bv << (8 * (k & 3));\n";
+            q << "                        unsigned int w = 0;\n";
+        q << "#pragma unroll\n"
+             "                        for (int q = 0; q < 4; ++q) {\n"
+             "                            const int lx = 4 * kd + q - S;\n"
+             "                            if (lx < 0 || lx >= RW) continue;\n";
+        if (u8)
+            q << "                            w |= (unsigned int)in[rb + clampi(ox + lx, 0, W - 1)] << (8 * q);\n";
         else
-            q << "                        pf[k] = __float_as_uint(in[gi]);\n";
+            q << "                            pf[4 * k + q] = __float_as_uint(in[rb + clampi(ox + lx, 0, W - 1)]);\n";
+        q << "                        }\n";
+        if (u8) q << "                        pf[k] = w;\n";
         q << "                    }\n"
              "                }\n"
              "            }\n"
@@ -181,44 +206,28 @@ std::string jit_source(const fz_plan& p, const Segment& g)
     };
     const char* vx[4] = {"(float)(pf[k] & 255u)", "(float)((pf[k] >> 8) & 255u)", "(float)((pf[k] >> 16) & 255u)",
                          "(float)(pf[k] >> 24)"};
-    o << "    constexpr int S = " << S
-      << ", ND = (RW + S + 3) / 4, NV = RH * ND, NLV = (NV + 255) / 256, NLS = (BOX + 255) / 256;\n"
-      << "    constexpr int NPF = " << (u8 ? "NLV > (NLS + 3) / 4 ? NLV : (NLS + 3) / 4" : "4 * NLV > NLS ? 4 * NLV : NLS")
-      << ";\n"
-         "    const int a0 = ox - S;\n"
-         "    unsigned int pf[NPF];\n"
-         "    if (fs < t1)\n"
+    o << "    if (fs < t1)\n"
       << issue("fs")
       << "    for (int f = fs; f < t1; ++f) {\n"
          "        const bool first = f == 0;\n"
          "        const size_t fbase = (size_t)f * P;\n"
          "        float* dst = lds + "
       << st[lead].buf << " + (f % " << st[lead].slots << ") * CELLS;\n"
-      << "        if (xin) {\n"
-         "#pragma unroll\n"
-         "            for (int k = 0; k < NLV; ++k) {\n"
-         "                const int it = threadIdx.x + 256 * k;\n"
-         "                if (it < NV) {\n"
-         "                    const int ly = it / ND, kd = it - ly * ND;\n";
+      << "#pragma unroll\n"
+         "        for (int k = 0; k < NLV; ++k) {\n"
+         "            const int it = threadIdx.x + 256 * k;\n"
+         "            if (it < NV) {\n"
+         "                const int ly = it / ND, kd = it - ly * ND;\n";
     for (int q = 0; q < 4; ++q) {
-        o << "                    if (" << (q < S ? "kd > 0 && " : "") << "4 * kd + " << q - S << " < RW) {\n"
-          << "                        const int e = ly * LP + 4 * kd + " << q - S << ";\n"
-          << "                        float v = " << (u8 ? std::string(vx[q]) : "__uint_as_float(pf[4 * k + " + std::to_string(q) + "])")
+        std::string ls = lead_stmts;
+        for (size_t pos; (pos = ls.find("[k][Q]")) != std::string::npos;) ls.replace(pos, 6, "[k][" + std::to_string(q) + "]");
+        o << "                if (" << (q < S ? "kd > 0 && " : "") << "4 * kd + " << q - S << " < RW) {\n"
+          << "                    float v = " << (u8 ? std::string(vx[q]) : "__uint_as_float(pf[4 * k + " + std::to_string(q) + "])")
           << ";\n"
-          << lead_stmts << "                        dst[e] = v;\n                    }\n";
+          << ls << "                    dst[ly * LP + 4 * kd + " << q - S << "] = v;\n                }\n";
     }
-    o << "                }\n"
-         "            }\n"
-         "        } else {\n"
-         "#pragma unroll\n"
-         "            for (int k = 0; k < NLS; ++k) {\n"
-         "                const int eb = threadIdx.x + 256 * k;\n"
-         "                if (eb < BOX) {\n"
-         "                    const int ey = eb / RW, e = ey * LP + (eb - ey * RW);\n"
-         "                    float v = "
-      << (u8 ? "(float)((pf[k >> 2] >> (8 * (k & 3))) & 255u)" : "__uint_as_float(pf[k])") << ";\n"
-      << lead_stmts
-      << "                    dst[e] = v;\n                }\n            }\n        }\n"
+    o << "            }\n"
+         "        }\n"
          "        __syncthreads();\n"
          "        if (f + 1 < t1)\n"
       << issue("f + 1");

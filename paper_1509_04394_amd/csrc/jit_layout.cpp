@@ -64,7 +64,7 @@ std::vector<WinStep> win_steps(const GStage* st, int n, int TW, int TH, int HX, 
 }
 
 // LDS row pitch of a group's buffers (cells per box row, at least the box
-// width).  A window stage's thread reads and writes its cell block at
+// width rounded up to whole four-cell groups).  A window stage's thread reads and writes its cell block at
 // (row, column) = (BY + cy, BX + cx) plus offsets common to every lane, so
 // the bank conflicts of each of its LDS instructions are those of the lanes'
 // cy * pitch + cx over 32 banks of 4 bytes, per 32 lanes; the pitch with the
@@ -76,7 +76,8 @@ std::vector<WinStep> win_steps(const GStage* st, int n, int TW, int TH, int HX, 
 // 72 and 71 us.)
 int jit_pitch(const GStage* st, int n, int TW, int TH, int HX, int HY)
 {
-    const int RW = TW + 2 * HX, lp0 = RW;
+    // at least the four-cell groups' width (leading IIR states are indexed by group)
+    const int RW = TW + 2 * HX, S = (4 - HX % 4) % 4, lp0 = std::max(RW, (RW + S + 3) / 4 * 4);
     const std::vector<WinStep> w = win_steps(st, n, TW, TH, HX, HY);
     int best = lp0;
     long best_cost = -1;
@@ -107,6 +108,40 @@ int jit_pitch(const GStage* st, int n, int TW, int TH, int HX, int HY)
         }
     }
     return best;
+}
+
+// LDS layout of a generated kernel: march_layout's, except that the IIRs
+// before the first window stage keep their states in registers and take no
+// LDS (their buf is -1).  Returns the floats used (the caller adds GEN_PAD).
+int jit_layout(GStage* st, int n, int cells)
+{
+    int off = 0, shared[2] = {-1, -1}, alt = 0;
+    bool seen_window = false;
+    for (int j = 0; j < n; ++j) {
+        GStage& s = st[j];
+        s.buf = -1;
+        s.slots = 0;
+        if (g_is_window(s.kind)) {
+            seen_window = true;
+            s.slots = s.rt + 1;
+            if (s.rt == 0) {
+                if (shared[alt] < 0) {
+                    shared[alt] = off;
+                    off += cells;
+                }
+                s.buf = shared[alt];
+                alt ^= 1;
+            } else {
+                s.buf = off;
+                off += s.slots * cells;
+            }
+        } else if (s.kind == G_IIR && seen_window) {
+            off += off & 1;  // 8-byte alignment of the double state
+            s.buf = off;
+            off += 2 * cells;
+        }
+    }
+    return off;
 }
 
 }  // namespace fz

@@ -19,4 +19,5 @@ struct WinStep {
 
 std::vector<WinStep> win_steps(const GStage* st, int n, int TW, int TH, int HX, int HY);
 
+
 }  // namespace fz

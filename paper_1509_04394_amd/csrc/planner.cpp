@@ -238,7 +238,7 @@ Segment price_generic(const fz_plan& p, int a, int b, int req_w, int req_h, int 
             if (req_w > 0 && (tw != req_w || th != req_h)) continue;
             const int cells = (tw + 2 * hx) * (th + 2 * hy);
             // a generated kernel: the marching layout (either kind of group) at its LDS row pitch
-            const int lds = jit ? (march_layout(st, n, jit_pitch(st, n, tw, th, hx, hy) * (th + 2 * hy)) + GEN_PAD) * 4
+            const int lds = jit ? (jit_layout(st, n, jit_pitch(st, n, tw, th, hx, hy) * (th + 2 * hy)) + GEN_PAD) * 4
                             : temporal ? (march_layout(st, n, cells) + GEN_PAD) * 4
                                        : generic_lds_bytes(tw, th, hx, hy, nwin);
             if (lds > p.lds_budget) continue;
