@@ -242,7 +242,11 @@ fz_status fz_plan_group_cost(const fz_plan* plan, int32_t a, int32_t b, double* 
  * contiguous-group model is a shortest path over cut positions.  n in [1, 64]. */
 fz_status fz_partition_min(const double* cost, int32_t n, int32_t* seg_last, int32_t* n_seg, double* total);
 
-/* Device workspace the run needs for intermediates between groups. */
+/* Device workspace a run needs: the intermediates between groups, the IIR
+ * checkpoints of a group whose leading IIRs resume at frame runs, and the
+ * frame-boundary exchange of a frame-difference group on the Harris row
+ * kernel (two areas of 8 * K bytes per band row and one counter per boundary
+ * between runs of one strip and band; cleared by the run itself). */
 size_t fz_workspace_bytes(const fz_plan* plan);
 
 /* Measured prices (Sec. VI-A: the price of a candidate fused kernel is its
@@ -287,7 +291,9 @@ fz_status fz_run_chain(const fz_plan* plan, const void* d_in, void* d_out, fz_po
  * in fz_run_chain).  The call itself allocates nothing.
  *   - Limit: plans whose fz_workspace_bytes() exceeds FZ_STATIC_WORKSPACE_BYTES
  *     (64 MiB) are refused with FZ_E_WORKSPACE before anything is launched or
- *     any device is touched; a fully fused plan needs no workspace at all.
+ *     any device is touched (the fused 800x600x1000 RGB chain at its planned
+ *     2-frame runs needs 67 MB of exchange words: plan it with longer runs,
+ *     fz_plan_set_segment_config, to run it here).
  *   - Each GPU the library runs on holds its own 64 MiB array from the first
  *     call on that device (which looks its address up) until the process ends.
  *   - Every call on one GPU shares that GPU's array and leaves its contents

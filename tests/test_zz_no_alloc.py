@@ -23,9 +23,9 @@ def say(*a):
     print("[no-alloc]", *a, flush=True)
 
 
-def run_both(ops, vol, partition, dev):
+def run_both(ops, vol, partition, dev, **kw):
     W, H, T = vol.shape[2], vol.shape[1], vol.shape[0]
-    plan = fz.Plan(ops, W, H, T, partition=partition)
+    plan = fz.Plan(ops, W, H, T, partition=partition, **kw)
     assert 0 < plan.workspace_bytes <= fz.FZ_STATIC_WORKSPACE_BYTES
     x = torch.from_numpy(vol).to(dev)
     ref, rp, rc = plan.run(x)
@@ -63,6 +63,17 @@ def test_static_workspace_generic_chain(dev):
     for W, H, T in [(200, 120, 5), (90, 70, 3)]:
         say("generic unfused", W, H, T)
         run_both(spec, synth.video(W, H, T, seed=43), "unfused", dev)
+
+
+def test_static_workspace_fused_row_exchange(dev):
+    """The fused Harris chain on the row kernel with 2-frame runs: its work
+    items meet at run boundaries through the exchange words and counters in
+    the workspace (here the library's static array), big clip then small."""
+    for W, H, T, band in [(300, 40, 23, 13), (200, 24, 9, 8)]:
+        say("fused row exchange", W, H, T)
+        plan = run_both(fz.RGB_HARRIS_CHAIN, synth.video(W, H, T, seed=44 + W, rgb=True), [], dev,
+                        engine="row", band_h=band, frames_per_block=2)
+        assert plan.segment_info()[0].engine == fz.FZ_ENGINE_ROW
 
 
 def test_static_workspace_refuses_oversized_plans(dev):
