@@ -226,8 +226,11 @@ Segment price_generic(const fz_plan& p, int a, int b, int req_w, int req_h, int 
             if (req_tpb > 0) {
                 tt_fixed = std::min(req_tpb, p.T);
             } else {
+                // Eq. 6 for a box of the work one item does when the items fill the device
+                // once (four times for a generated kernel: on the 800x600x1000 look-back chain
+                // its 16-frame runs took 2.41 ms against 2.51 at the single fill's 44)
                 double x, t;
-                eq6_box(P * p.T / G_FILL_ITEMS, 0.5 * (hx + hy), ht, &x, &t);
+                eq6_box(P * p.T / (G_FILL_ITEMS * (jit ? 4.0 : 1.0)), 0.5 * (hx + hy), ht, &x, &t);
                 tt_fixed = (int)std::min<double>(std::max(1.0, std::floor(t + 0.5)), p.T);
             }
         }
@@ -246,12 +249,15 @@ Segment price_generic(const fz_plan& p, int a, int b, int req_w, int req_h, int 
             int tt = tt_fixed;
             if (n_ck) {
                 // checkpointed IIRs: the longest power-of-two run (at least 8 frames) that still
-                // leaves two fills of work items; each run boundary costs a checkpoint
+                // leaves two fills of work items (eight for a generated kernel: on the paper's
+                // five-kernel chain at 800x600x1000 its 16-frame runs took 1.49 ms against 1.60 at
+                // 64); each run boundary costs a checkpoint
                 if (req_tpb > 0) {
                     tt = std::min(req_tpb, p.T);
                 } else {
+                    const double fills = jit ? 8.0 : 2.0;
                     tt = 8;
-                    while (tt * 2 <= p.T && tiles * ceil((double)p.T / (tt * 2)) >= 2.0 * G_FILL_ITEMS) tt *= 2;
+                    while (tt * 2 <= p.T && tiles * ceil((double)p.T / (tt * 2)) >= fills * G_FILL_ITEMS) tt *= 2;
                     tt = std::min(tt, p.T);
                 }
             }
