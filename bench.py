@@ -70,8 +70,8 @@ KERNEL_OPS = dict(MIN_OPS, gauss5=11, boxsum5=18)
 # Valid only for the kernel sources and the launch geometry (columns per strip,
 # band rows, frames per work item) they were taken with: the key holds both.
 COUNTER_TRAFFIC = {
-    ("rgb800", "ed9bc057f0e37bfd", (128, 55, 16)): {"fetch_bytes": 2.488e9, "write_bytes": 0.590e9,
-                                                    "source": "profiles/rowfuse_rgb800_counters.md"},
+    ("rgb800", "1317c82aa13af6db", (128, 75, 2)): {"fetch_bytes": 2.029e9, "write_bytes": 0.660e9,
+                                                   "source": "profiles/rowfuse_rgb800_counters.md"},
 }
 KERNEL_SOURCES = ["rowfuse.h", "stage_math.h"]
 DRIVER_TIMEOUT_S = 600
