@@ -123,6 +123,30 @@ def test_batch_more_clips_than_one_launch(dev):
     check_oracle(ops, items)
 
 
+def test_batch_clip_by_clip_with_run_exchange(dev):
+    """A fused plan with one clip too narrow for the row kernel runs clip by
+    clip inside the graph: the wide clips' fused row groups meet at their
+    frame-run boundaries through the exchange words in the batch workspace,
+    whose counters a kernel node clears on every replay."""
+    ops = fz.HARRIS_CHAIN
+    sizes = [(200, 48, 9), (96, 40, 5), (160, 33, 12)]
+    items = make_clips(ops, sizes, dev, False, seed0=950)
+    refs = single_runs(items)
+    plan = fz.Plan(ops, 200, 48, 9)
+    assert len(plan.segments) == 1
+    clips = [fz.make_clip(it["x"], it["out"], it["pts"], it["cnt"], plan=plan) for it in items]
+    ws = None
+    for rep in range(3):
+        for it in items:
+            it["out"].fill_(7)
+            it["cnt"].fill_(12345)
+        torch.cuda.synchronize()
+        ws = fz.run_batch(plan, clips, ws)
+        torch.cuda.synchronize()
+        say("clip by clip, exchange, replay", rep)
+        check(items, refs)
+
+
 @pytest.mark.parametrize("partition", ["unfused", [3]])
 def test_batch_clip_by_clip_path(dev, partition):
     """Plans the persistent kernel does not cover run clip after clip in the graph."""
