@@ -293,3 +293,22 @@ def test_band_and_frame_run_requests_are_kept_or_refused():
     plan.set_segment_config(0, "row", (0, 120), 40)
     s = plan.segment_info()[0]
     assert (s.tile_h, s.frames_per_block) == (120, 40)
+
+
+def test_row_sizing_model_prefers_short_runs_and_full_rounds():
+    """The row kernel's band x run model (total work x (1 + 1/rounds)): with the
+    frame-boundary exchange the 800x600x1000 RGB chain gets 2-frame runs and a
+    band of 55-100 rows (the measured sweep's best region), at least four
+    rounds of wavefronts, and a workspace holding the exchange words."""
+    W, H, T = 800, 600, 1000
+    plan = fz.Plan(fz.RGB_HARRIS_CHAIN, W, H, T)
+    (s,) = plan.segment_info()
+    assert s.engine == fz.FZ_ENGINE_ROW and s.frames_per_block == 2 and 55 <= s.tile_h <= 100
+    strips = -(-(W - 128) // 116) + 1
+    items = strips * -(-H // s.tile_h) * -(-T // s.frames_per_block)
+    assert items >= 4 * 5120
+    bounds = strips * -(-H // s.tile_h) * (-(-T // s.frames_per_block) - 1)
+    assert plan.workspace_bytes >= bounds * (2 * s.tile_h * 2 * 8 + 4)
+    # one run covering the clip: no boundaries, no workspace
+    one = fz.Plan(fz.RGB_HARRIS_CHAIN, W, H, T, engine="row", band_h=75, frames_per_block=T)
+    assert one.workspace_bytes == 0
