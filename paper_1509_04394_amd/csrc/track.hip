@@ -262,6 +262,7 @@ __global__ __launch_bounds__(TRK_THREADS) void k_trk_run(const int2* bucket, con
         for (uint32_t j = lane; j < np; j += TRK_THREADS) {
             const int2 a = pin[j];
             uint32_t rank = 0;
+#pragma unroll 8
             for (uint32_t k = 0; k < np; ++k) {
                 const int2 b = pin[k];
                 rank += (b.y < a.y || (b.y == a.y && b.x < a.x)) ? 1u : 0u;
@@ -301,24 +302,36 @@ __global__ __launch_bounds__(TRK_THREADS) void k_trk_run(const int2* bucket, con
             double hs[2];
             mm<2, 4, 1>(M.H, s1, hs);
             const int32_t id = tr.id;
-            for (uint32_t j = 0; j < np; ++j) {
-                double nu[2];
-                nu[0] = (double)pts[j].x - hs[0];
-                nu[1] = (double)pts[j].y - hs[1];
-                double d2 = 0.0;
-                for (int a = 0; a < 2; ++a)
-                    for (int b = 0; b < 2; ++b) d2 = d2 + nu[a] * Si[2 * a + b] * nu[b];
-                if (d2 <= o.gate) {
-                    const uint32_t k = atomicAdd(&s_nc, 1u);
-                    if (k < (uint32_t)TRK_MAX_CANDS) {
-                        Cand c;
-                        c.d2 = d2;
-                        c.id = id;
-                        c.ti = (int16_t)i;
-                        c.pj = (int16_t)j;
-                        cand[k] = c;
-                    } else {
-                        atomicOr(&s_flags, (uint32_t)FZ_TRACK_TOO_MANY_CANDIDATES);
+            // four points at a time: their d2 are independent chains of double
+            // operations, in flight together (one at a time, each waited on the last)
+            for (uint32_t j0 = 0; j0 < np; j0 += 4) {
+                double d2v[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int2 pq = pts[min(j0 + (uint32_t)q, np - 1u)];  // the tail repeats the last point
+                    double nu[2];
+                    nu[0] = (double)pq.x - hs[0];
+                    nu[1] = (double)pq.y - hs[1];
+                    double d2 = 0.0;
+                    for (int a = 0; a < 2; ++a)
+                        for (int b = 0; b < 2; ++b) d2 = d2 + nu[a] * Si[2 * a + b] * nu[b];
+                    d2v[q] = d2;
+                }
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const uint32_t j = j0 + (uint32_t)q;
+                    if (j < np && d2v[q] <= o.gate) {
+                        const uint32_t k = atomicAdd(&s_nc, 1u);
+                        if (k < (uint32_t)TRK_MAX_CANDS) {
+                            Cand c;
+                            c.d2 = d2v[q];
+                            c.id = id;
+                            c.ti = (int16_t)i;
+                            c.pj = (int16_t)j;
+                            cand[k] = c;
+                        } else {
+                            atomicOr(&s_flags, (uint32_t)FZ_TRACK_TOO_MANY_CANDIDATES);
+                        }
                     }
                 }
             }
