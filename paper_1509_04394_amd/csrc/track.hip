@@ -16,7 +16,9 @@
 // every point left over (ids in (y, x) order).  All arithmetic is double
 // precision, every matrix product the plain sum over k = 0, 1, ... from 0.0,
 // evaluated without contraction: the association is a discrete decision, and
-// this makes it (and every state) reproducible to the bit.
+// this makes it (and every state) reproducible to the bit.  Products with F
+// and H (entries 0 and 1) are written out term by term; they give the same
+// bits as those sums (see f_row).
 //
 // Launches: the points are bucketed by frame (a histogram, one scan, a
 // scatter into the workspace), then one wavefront marches the frames in
@@ -69,24 +71,29 @@ __device__ __forceinline__ void mm(const double* A, const double* B, double* C)
         }
 }
 
-struct KModel {
-    double F[16], Ft[16], Q[16], H[8], Ht[8];
+// Products with F, H and their transposes, written out.  Their entries are
+// 0 and 1, so every term of the plain sum (from 0.0, in k order) is exact: a
+// copy of an operand, or a zero.  A partial sum there is never -0 (it starts
+// as 0.0 plus the first term, and two summands give -0 only when both are
+// -0), so adding a zero term leaves it unchanged; what remains is the sum of
+// the copied operands in k order, which these helpers form: the same value,
+// bit for bit, as the plain sum, for finite operands.
+// Row r of F (the constant-velocity transition) applied to the 4-vector v
+// with element stride st.
+__device__ __forceinline__ double f_row(const double* v, int st, int r)
+{
+    if (r < 2) return (0.0 + v[r * st]) + v[(r + 2) * st];
+    return 0.0 + v[r * st];
+}
+
+struct KModel {  // Q and R of the model (F and H enter through f_row and the written-out products)
+    double Q[16];
     double r;
     __device__ KModel(double q, double rr) : r(rr)
     {
-        const double f[16] = {1, 0, 1, 0, 0, 1, 0, 1, 0, 0, 1, 0, 0, 0, 0, 1};
         const double qq[16] = {0.25 * q, 0, 0.5 * q, 0, 0, 0.25 * q, 0, 0.5 * q,
                                0.5 * q,  0, q,       0, 0, 0.5 * q,  0, q};
-        const double h[8] = {1, 0, 0, 0, 0, 1, 0, 0};
-        for (int i = 0; i < 16; ++i) {
-            F[i] = f[i];
-            Q[i] = qq[i];
-        }
-        for (int i = 0; i < 4; ++i)
-            for (int j = 0; j < 4; ++j) Ft[j * 4 + i] = f[i * 4 + j];
-        for (int i = 0; i < 8; ++i) H[i] = h[i];
-        for (int i = 0; i < 2; ++i)
-            for (int j = 0; j < 4; ++j) Ht[j * 2 + i] = h[i * 4 + j];
+        for (int i = 0; i < 16; ++i) Q[i] = qq[i];
     }
 };
 
@@ -200,17 +207,21 @@ __device__ __forceinline__ void put_record(fz_track* out, uint32_t k, uint32_t c
 // makes, in a few rounds instead of one step per candidate.  The next frame's
 // points are loaded while the current frame is processed; the record count
 // is kept in a register (one wavefront writes every record).
-__global__ __launch_bounds__(TRK_THREADS) void k_trk_run(const int2* bucket, const uint32_t* offs, int T,
+__global__ __launch_bounds__(TRK_THREADS) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_trk_run(const int2* bucket, const uint32_t* offs, int T,
                                                           fz_track_opts o, DevTrack* buf0, DevTrack* buf1,
                                                           uint32_t max_tracks, fz_track* out, uint32_t* count,
                                                           uint32_t cap)
 {
-    __shared__ int2 pin[TRK_MAX_POINTS];   // the frame's points as loaded
-    __shared__ int2 pts[TRK_MAX_POINTS];   // sorted by (y, x)
-    // the gated candidates of the frame; after the association, the same
-    // memory holds the next list's first 64 tracks
+    // the frame's points sorted by (y, x), as doubles; the candidate search reads
+    // them eight at a time, so up to seven past the frame's are read and not used
+    __shared__ double2 pts[TRK_MAX_POINTS + 8];
+    __shared__ long long skey[TRK_THREADS];  // sort keys of a frame of at most 64 points
+    // the gated candidates of the frame; the same memory holds a frame's
+    // points as loaded before they are sorted, and after the association the
+    // next list's first 64 tracks
     __shared__ union {
-        Cand cand[TRK_MAX_CANDS];
+        Cand cand[TRK_MAX_CANDS + TRK_THREADS];  // the last 64: one discard slot per lane
+        int2 pin[TRK_MAX_POINTS];                // a frame of more than 64 points as loaded
         DevTrack stage[TRK_THREADS];
     } cu;
     __shared__ uint8_t ptaken[TRK_MAX_POINTS];
@@ -221,7 +232,8 @@ __global__ __launch_bounds__(TRK_THREADS) void k_trk_run(const int2* bucket, con
     __shared__ unsigned long long pb_d[TRK_MAX_POINTS], pb_k[TRK_MAX_POINTS];
     Cand* const cand = cu.cand;
     DevTrack* const stage = cu.stage;
-    __shared__ uint32_t s_nc, s_flags;
+    int2* const pin = cu.pin;
+    __shared__ uint32_t s_flags;
     const int lane = threadIdx.x;
     const KModel M(o.q, o.r);
     DevTrack* cur = buf0;
@@ -238,156 +250,297 @@ __global__ __launch_bounds__(TRK_THREADS) void k_trk_run(const int2* bucket, con
         pre_x = q.x;
         pre_y = q.y;
     }
+    // offs[t + 2] for the 64 frames t of the current window (lane t % 64),
+    // loaded when the window starts: a frame reads its successor's bounds
+    // from a register.  (Loading the next window ahead kept a load in flight
+    // across frames, and moving its register from frame to frame made every
+    // frame wait for all its outstanding memory operations, the record
+    // stores included; now that wait comes once in 64 frames.)
+    uint32_t ow_cur = 0;
 
     for (int t = 0; t < T; ++t) {
-        uint32_t np = f_hi - f_lo;
-        if (np > (uint32_t)TRK_MAX_POINTS) {
-            if (lane == 0) s_flags |= FZ_TRACK_TOO_MANY_POINTS;
-            np = TRK_MAX_POINTS;
-        }
+        // the frame's point count, in a scalar register (the compiler cannot
+        // tell it is the same in every lane; loops over it then run as scalar loops)
+        const uint32_t np_all = (uint32_t)__builtin_amdgcn_readfirstlane((int)(f_hi - f_lo));
+        if (np_all > (uint32_t)TRK_MAX_POINTS && lane == 0) s_flags |= FZ_TRACK_TOO_MANY_POINTS;
+        const uint32_t np = min(np_all, (uint32_t)TRK_MAX_POINTS);
         // 1. the frame's points, sorted by (y, x) (keys are distinct)
+        const int ax = pre_x, ay = pre_y;  // point f_lo + lane
         for (uint32_t j = lane; j < np; j += TRK_THREADS) {
-            pin[j] = j < (uint32_t)TRK_THREADS ? make_int2(pre_x, pre_y) : bucket[f_lo + j];
+            if (np > (uint32_t)TRK_THREADS) pin[j] = j < (uint32_t)TRK_THREADS ? make_int2(ax, ay) : bucket[f_lo + j];
             ptaken[j] = 0;
         }
         // the next frame's bounds and first points, in flight during this frame
-        const uint32_t n_lo = f_hi, n_hi = t + 2 <= T ? offs[t + 2] : f_hi;
+        const uint32_t tw = (uint32_t)t & 63u;
+        if (tw == 0u) {
+            ow_cur = offs[min(t + 2 + lane, T)];
+            asm volatile("; window bounds in %0" ::"v"(ow_cur));  // the wait for the load stays in this branch
+        }
+        const uint32_t n_lo = f_hi, n_hi = t + 2 <= T ? (uint32_t)__builtin_amdgcn_readlane((int)ow_cur, (int)tw) : f_hi;
         if (n_lo + lane < total) {
             const int2 q = bucket[n_lo + lane];
             pre_x = q.x;
             pre_y = q.y;
         }
-        if (lane == 0) s_nc = 0u;
-        __syncthreads();
-        for (uint32_t j = lane; j < np; j += TRK_THREADS) {
-            const int2 a = pin[j];
+        if (np <= (uint32_t)TRK_THREADS) {
+            // lane j holds point j: its rank counts the smaller (y, x) keys (y in
+            // the high word, x offset by 2^31 in the low word, compared as signed
+            // 64-bit integers), read back from LDS eight at a time
+            const uint32_t klo = (uint32_t)ax ^ 0x80000000u, khi = (uint32_t)ay;
+            const long long ka = (long long)(((unsigned long long)khi << 32) | klo);
+            skey[lane] = (uint32_t)lane < np ? ka : 0x7fffffffffffffffll;  // past np: never smaller
+            __syncthreads();
             uint32_t rank = 0;
+            for (uint32_t k0 = 0; k0 < np; k0 += 8) {
+                long long kb[8];
+#pragma unroll
+                for (uint32_t q = 0; q < 8; ++q) kb[q] = skey[k0 + q];
+#pragma unroll
+                for (uint32_t q = 0; q < 8; ++q) rank += kb[q] < ka ? 1u : 0u;
+            }
+            if ((uint32_t)lane < np) pts[rank] = make_double2((double)ax, (double)ay);
+        } else {
+            __syncthreads();
+            for (uint32_t j = lane; j < np; j += TRK_THREADS) {
+                const int2 a = pin[j];
+                uint32_t rank = 0;
 #pragma unroll 8
-            for (uint32_t k = 0; k < np; ++k) {
-                const int2 b = pin[k];
-                rank += (b.y < a.y || (b.y == a.y && b.x < a.x)) ? 1u : 0u;
-            }
-            pts[rank] = a;
-        }
-        __syncthreads();
-        // 2. predict every live track and list its gated candidate pairs
-        for (uint32_t i = lane; i < ntr; i += TRK_THREADS) {
-            DevTrack tr;
-            if (i < (uint32_t)TRK_THREADS)
-                tr = rt;
-            else
-                tr = cur[i];
-            double s1[4], FP[16], Pp[16], HP[8], S[4], Si[4];
-            mm<4, 4, 1>(M.F, tr.s, s1);
-            mm<4, 4, 4>(M.F, tr.P, FP);
-            mm<4, 4, 4>(FP, M.Ft, Pp);
-            for (int e = 0; e < 16; ++e) Pp[e] = Pp[e] + M.Q[e];
-            mm<2, 4, 4>(M.H, Pp, HP);
-            mm<2, 4, 2>(HP, M.Ht, S);
-            S[0] = S[0] + M.r;
-            S[3] = S[3] + M.r;
-            const double det = S[0] * S[3] - S[1] * S[2];
-            Si[0] = S[3] / det;
-            Si[1] = -S[1] / det;
-            Si[2] = -S[2] / det;
-            Si[3] = S[0] / det;
-            for (int e = 0; e < 4; ++e) tr.s[e] = s1[e];
-            for (int e = 0; e < 16; ++e) tr.P[e] = Pp[e];
-            for (int e = 0; e < 4; ++e) tr.Si[e] = Si[e];
-            if (i < (uint32_t)TRK_THREADS)
-                rt = tr;
-            else
-                cur[i] = tr;
-            tmatch[i] = -1;
-            double hs[2];
-            mm<2, 4, 1>(M.H, s1, hs);
-            const int32_t id = tr.id;
-            // four points at a time: their d2 are independent chains of double
-            // operations, in flight together (one at a time, each waited on the last)
-            for (uint32_t j0 = 0; j0 < np; j0 += 4) {
-                double d2v[4];
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int2 pq = pts[min(j0 + (uint32_t)q, np - 1u)];  // the tail repeats the last point
-                    double nu[2];
-                    nu[0] = (double)pq.x - hs[0];
-                    nu[1] = (double)pq.y - hs[1];
-                    double d2 = 0.0;
-                    for (int a = 0; a < 2; ++a)
-                        for (int b = 0; b < 2; ++b) d2 = d2 + nu[a] * Si[2 * a + b] * nu[b];
-                    d2v[q] = d2;
+                for (uint32_t k = 0; k < np; ++k) {
+                    const int2 b = pin[k];
+                    rank += (b.y < a.y || (b.y == a.y && b.x < a.x)) ? 1u : 0u;
                 }
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const uint32_t j = j0 + (uint32_t)q;
-                    if (j < np && d2v[q] <= o.gate) {
-                        const uint32_t k = atomicAdd(&s_nc, 1u);
-                        if (k < (uint32_t)TRK_MAX_CANDS) {
-                            Cand c;
-                            c.d2 = d2v[q];
-                            c.id = id;
-                            c.ti = (int16_t)i;
-                            c.pj = (int16_t)j;
-                            cand[k] = c;
-                        } else {
-                            atomicOr(&s_flags, (uint32_t)FZ_TRACK_TOO_MANY_CANDIDATES);
-                        }
-                    }
-                }
+                pts[rank] = make_double2((double)a.x, (double)a.y);
             }
         }
         __syncthreads();
-        const uint32_t nc = min(s_nc, (uint32_t)TRK_MAX_CANDS);
+        // 2. predict every live track and list its gated candidate pairs; a
+        // candidate's slot is its rank among the wavefront's candidates of the
+        // same point (a ballot) after all earlier ones, so the count stays in a
+        // wavefront-uniform register
+        uint32_t ncand = 0;
+        for (uint32_t c0 = 0; c0 < ntr; c0 += TRK_THREADS) {
+            const uint32_t i = c0 + lane;
+            const bool act = i < ntr;
+            double hs[2] = {0.0, 0.0}, Si[4] = {0.0, 0.0, 0.0, 0.0};
+            int32_t id = 0;
+            if (act) {
+                DevTrack tr;
+                if (c0 == 0)
+                    tr = rt;
+                else
+                    tr = cur[i];
+                double s1[4], FP[16], Pp[16], HP[8], S[4];
+                // s1 = F s, FP = F P, Pp = FP F^T + Q, HP = H Pp, S = HP H^T (+ R below)
+                for (int r = 0; r < 4; ++r) s1[r] = f_row(tr.s, 1, r);
+                for (int i = 0; i < 4; ++i)
+                    for (int j = 0; j < 4; ++j) FP[4 * i + j] = f_row(tr.P + j, 4, i);
+                for (int i = 0; i < 4; ++i)
+                    for (int j = 0; j < 4; ++j) Pp[4 * i + j] = f_row(FP + 4 * i, 1, j);
+                for (int e = 0; e < 16; ++e) Pp[e] = Pp[e] + M.Q[e];
+                for (int e = 0; e < 8; ++e) HP[e] = 0.0 + Pp[e];
+                for (int i = 0; i < 2; ++i)
+                    for (int j = 0; j < 2; ++j) S[2 * i + j] = 0.0 + HP[4 * i + j];
+                S[0] = S[0] + M.r;
+                S[3] = S[3] + M.r;
+                const double det = S[0] * S[3] - S[1] * S[2];
+                Si[0] = S[3] / det;
+                Si[1] = -S[1] / det;
+                Si[2] = -S[2] / det;
+                Si[3] = S[0] / det;
+                for (int e = 0; e < 4; ++e) tr.s[e] = s1[e];
+                for (int e = 0; e < 16; ++e) tr.P[e] = Pp[e];
+                for (int e = 0; e < 4; ++e) tr.Si[e] = Si[e];
+                if (c0 == 0)
+                    rt = tr;
+                else
+                    cur[i] = tr;
+                tmatch[i] = -1;
+                for (int e = 0; e < 2; ++e) hs[e] = 0.0 + s1[e];  // H s1
+                id = tr.id;
+            }
+            // eight points at a time: their d2 are independent chains of double
+            // operations, written out step by step across the eight so that each
+            // step's operations are in flight together; every lane then stores its
+            // pair, those that are not candidates into a slot of their own past the
+            // list (as does an overflow), so the group is one straight block
+            for (uint32_t j0 = 0; j0 < np; j0 += 8) {
+                double2 pv[8];
+                double nu0[8], nu1[8], tm[4][8], d2v[8];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) pv[q] = pts[j0 + (uint32_t)q];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    nu0[q] = pv[q].x - hs[0];
+                    nu1[q] = pv[q].y - hs[1];
+                }
+                // d2 = nu^T S^-1 nu: the terms (nu_a Si_ab) nu_b summed from 0.0 in
+                // (a, b) order
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    tm[0][q] = nu0[q] * Si[0];
+                    tm[1][q] = nu0[q] * Si[1];
+                    tm[2][q] = nu1[q] * Si[2];
+                    tm[3][q] = nu1[q] * Si[3];
+                }
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    tm[0][q] = tm[0][q] * nu0[q];
+                    tm[1][q] = tm[1][q] * nu1[q];
+                    tm[2][q] = tm[2][q] * nu0[q];
+                    tm[3][q] = tm[3][q] * nu1[q];
+                }
+#pragma unroll
+                for (int q = 0; q < 8; ++q) d2v[q] = 0.0 + tm[0][q];
+#pragma unroll
+                for (int e = 1; e < 4; ++e)
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) d2v[q] = d2v[q] + tm[e][q];
+                // the gate of all eight first (one mask each), then the slots:
+                // the masks' counts in order give each point's base, a lane's rank
+                // in its mask its place
+                uint64_t m[8];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    const bool in = act && j0 + (uint32_t)q < np;
+                    const double dq = in ? d2v[q] : __builtin_huge_val();  // outside: never gated in
+                    m[q] = __ballot(dq <= o.gate);
+                }
+                uint32_t base[8];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    base[q] = ncand;
+                    ncand += (uint32_t)__popcll(m[q]);
+                }
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    const bool pass = (m[q] >> lane) & 1ull;
+                    const uint32_t k = base[q] + __builtin_amdgcn_mbcnt_hi((uint32_t)(m[q] >> 32),
+                                                                           __builtin_amdgcn_mbcnt_lo((uint32_t)m[q], 0u));
+                    Cand c;
+                    c.d2 = d2v[q];
+                    c.id = id;
+                    c.ti = (int16_t)i;
+                    c.pj = (int16_t)(j0 + (uint32_t)q);
+                    cand[min(pass ? k : ~0u, (uint32_t)TRK_MAX_CANDS + (uint32_t)lane)] = c;
+                }
+            }
+        }
+        if (ncand > (uint32_t)TRK_MAX_CANDS && lane == 0) s_flags |= FZ_TRACK_TOO_MANY_CANDIDATES;
+        __syncthreads();
+        const uint32_t nc = min(ncand, (uint32_t)TRK_MAX_CANDS);
         // 3. greedy association in rounds: an open candidate that comes first
         // (in the (d2, id, point) order) among the open candidates of both its
         // track and its point is taken; then every candidate of a taken track
-        // or point closes
-        for (uint32_t c = lane; c < nc; c += TRK_THREADS) calive[c] = 1;
-        for (;;) {
-            __syncthreads();
-            for (uint32_t c = lane; c < nc; c += TRK_THREADS)
-                if (calive[c]) {
+        // or point closes.  Up to 128 candidates, each lane keeps its two
+        // (lane, lane + 64) in registers, and the first-of slots of a track or
+        // point are cleared when its candidates stay open for another round;
+        // beyond that the candidates are read from LDS in every pass.
+        if (nc <= 2u * TRK_THREADS) {
+            unsigned long long rd[2], rk[2];
+            int rti[2], rpj[2];
+            bool al[2];
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                const uint32_t c = (uint32_t)lane + (uint32_t)q * TRK_THREADS;
+                al[q] = c < nc;
+                rd[q] = rk[q] = 0ull;
+                rti[q] = rpj[q] = 0;
+                if (al[q]) {
                     const Cand a = cand[c];
+                    rd[q] = d2_key(a.d2);
+                    rk[q] = idpj_key(a);
+                    rti[q] = a.ti;
+                    rpj[q] = a.pj;
                     tb_d[a.ti] = tb_k[a.ti] = ~0ull;
                     pb_d[a.pj] = pb_k[a.pj] = ~0ull;
                 }
-            __syncthreads();
-            for (uint32_t c = lane; c < nc; c += TRK_THREADS)
-                if (calive[c]) {
-                    const Cand a = cand[c];
-                    const unsigned long long d = d2_key(a.d2);
-                    atomicMin(&tb_d[a.ti], d);
-                    atomicMin(&pb_d[a.pj], d);
-                }
-            __syncthreads();
-            for (uint32_t c = lane; c < nc; c += TRK_THREADS)
-                if (calive[c]) {
-                    const Cand a = cand[c];
-                    const unsigned long long d = d2_key(a.d2), k = idpj_key(a);
-                    if (d == tb_d[a.ti]) atomicMin(&tb_k[a.ti], k);
-                    if (d == pb_d[a.pj]) atomicMin(&pb_k[a.pj], k);
-                }
-            __syncthreads();
-            for (uint32_t c = lane; c < nc; c += TRK_THREADS)
-                if (calive[c]) {
-                    const Cand a = cand[c];
-                    const unsigned long long d = d2_key(a.d2), k = idpj_key(a);
-                    if (d == tb_d[a.ti] && k == tb_k[a.ti] && d == pb_d[a.pj] && k == pb_k[a.pj]) {
-                        tmatch[a.ti] = a.pj;
-                        ptaken[a.pj] = 1;
+            }
+            for (;;) {
+                __syncthreads();
+#pragma unroll
+                for (int q = 0; q < 2; ++q)
+                    if (al[q]) {
+                        atomicMin(&tb_d[rti[q]], rd[q]);
+                        atomicMin(&pb_d[rpj[q]], rd[q]);
                     }
-                }
-            __syncthreads();
-            bool open = false;
-            for (uint32_t c = lane; c < nc; c += TRK_THREADS)
-                if (calive[c]) {
-                    const Cand a = cand[c];
-                    if (tmatch[a.ti] >= 0 || ptaken[a.pj])
-                        calive[c] = 0;
-                    else
-                        open = true;
-                }
-            if (!__any(open)) break;
+                __syncthreads();
+#pragma unroll
+                for (int q = 0; q < 2; ++q)
+                    if (al[q]) {
+                        if (rd[q] == tb_d[rti[q]]) atomicMin(&tb_k[rti[q]], rk[q]);
+                        if (rd[q] == pb_d[rpj[q]]) atomicMin(&pb_k[rpj[q]], rk[q]);
+                    }
+                __syncthreads();
+#pragma unroll
+                for (int q = 0; q < 2; ++q)
+                    if (al[q] && rd[q] == tb_d[rti[q]] && rk[q] == tb_k[rti[q]] && rd[q] == pb_d[rpj[q]] &&
+                        rk[q] == pb_k[rpj[q]]) {
+                        tmatch[rti[q]] = (int16_t)rpj[q];
+                        ptaken[rpj[q]] = 1;
+                    }
+                __syncthreads();
+                bool open = false;
+#pragma unroll
+                for (int q = 0; q < 2; ++q)
+                    if (al[q]) {
+                        if (tmatch[rti[q]] >= 0 || ptaken[rpj[q]]) {
+                            al[q] = false;
+                        } else {
+                            open = true;
+                            tb_d[rti[q]] = tb_k[rti[q]] = ~0ull;
+                            pb_d[rpj[q]] = pb_k[rpj[q]] = ~0ull;
+                        }
+                    }
+                if (!__any(open)) break;
+            }
+        } else {
+            for (uint32_t c = lane; c < nc; c += TRK_THREADS) calive[c] = 1;
+            for (;;) {
+                __syncthreads();
+                for (uint32_t c = lane; c < nc; c += TRK_THREADS)
+                    if (calive[c]) {
+                        const Cand a = cand[c];
+                        tb_d[a.ti] = tb_k[a.ti] = ~0ull;
+                        pb_d[a.pj] = pb_k[a.pj] = ~0ull;
+                    }
+                __syncthreads();
+                for (uint32_t c = lane; c < nc; c += TRK_THREADS)
+                    if (calive[c]) {
+                        const Cand a = cand[c];
+                        const unsigned long long d = d2_key(a.d2);
+                        atomicMin(&tb_d[a.ti], d);
+                        atomicMin(&pb_d[a.pj], d);
+                    }
+                __syncthreads();
+                for (uint32_t c = lane; c < nc; c += TRK_THREADS)
+                    if (calive[c]) {
+                        const Cand a = cand[c];
+                        const unsigned long long d = d2_key(a.d2), k = idpj_key(a);
+                        if (d == tb_d[a.ti]) atomicMin(&tb_k[a.ti], k);
+                        if (d == pb_d[a.pj]) atomicMin(&pb_k[a.pj], k);
+                    }
+                __syncthreads();
+                for (uint32_t c = lane; c < nc; c += TRK_THREADS)
+                    if (calive[c]) {
+                        const Cand a = cand[c];
+                        const unsigned long long d = d2_key(a.d2), k = idpj_key(a);
+                        if (d == tb_d[a.ti] && k == tb_k[a.ti] && d == pb_d[a.pj] && k == pb_k[a.pj]) {
+                            tmatch[a.ti] = a.pj;
+                            ptaken[a.pj] = 1;
+                        }
+                    }
+                __syncthreads();
+                bool open = false;
+                for (uint32_t c = lane; c < nc; c += TRK_THREADS)
+                    if (calive[c]) {
+                        const Cand a = cand[c];
+                        if (tmatch[a.ti] >= 0 || ptaken[a.pj])
+                            calive[c] = 0;
+                        else
+                            open = true;
+                    }
+                if (!__any(open)) break;
+            }
         }
         __syncthreads();
         // 5. update or count a miss; survivors to the next list in id order, with their records
@@ -404,17 +557,25 @@ __global__ __launch_bounds__(TRK_THREADS) void k_trk_run(const int2* bucket, con
                 const int j = tmatch[i];
                 if (j >= 0) {
                     double hs[2], nu[2], PHt[8], K[8], Knu[4], KH[16], IKH[16], Pn[16];
-                    mm<2, 4, 1>(M.H, tr.s, hs);
-                    nu[0] = (double)pts[j].x - hs[0];
-                    nu[1] = (double)pts[j].y - hs[1];
-                    mm<4, 4, 2>(tr.P, M.Ht, PHt);
+                    for (int e = 0; e < 2; ++e) hs[e] = 0.0 + tr.s[e];  // H s
+                    nu[0] = pts[j].x - hs[0];
+                    nu[1] = pts[j].y - hs[1];
+                    for (int a = 0; a < 4; ++a)
+                        for (int b = 0; b < 2; ++b) PHt[2 * a + b] = 0.0 + tr.P[4 * a + b];  // P H^T
                     mm<4, 2, 2>(PHt, tr.Si, K);
                     mm<4, 2, 1>(K, nu, Knu);
                     for (int e = 0; e < 4; ++e) tr.s[e] = tr.s[e] + Knu[e];
-                    mm<4, 2, 4>(K, M.H, KH);
+                    for (int a = 0; a < 4; ++a)  // K H: columns 0, 1 of K, then zeros
+                        for (int b = 0; b < 4; ++b) KH[4 * a + b] = b < 2 ? 0.0 + K[2 * a + b] : 0.0;
                     for (int a = 0; a < 4; ++a)
                         for (int b = 0; b < 4; ++b) IKH[4 * a + b] = (a == b ? 1.0 : 0.0) - KH[4 * a + b];
-                    mm<4, 4, 4>(IKH, tr.P, Pn);
+                    // (I - KH) P: columns 2 and 3 of I - KH are those of the identity
+                    // (1 - 0 and 0 - 0 exactly), so rows 2 and 3 add P's own row
+                    for (int a = 0; a < 4; ++a)
+                        for (int b = 0; b < 4; ++b) {
+                            const double acc = (0.0 + IKH[4 * a] * tr.P[b]) + IKH[4 * a + 1] * tr.P[4 + b];
+                            Pn[4 * a + b] = a < 2 ? acc : acc + tr.P[4 * a + b];
+                        }
                     for (int e = 0; e < 16; ++e) tr.P[e] = Pn[e];
                     tr.miss = 0;
                     tr.status = 1;
@@ -453,8 +614,8 @@ __global__ __launch_bounds__(TRK_THREADS) void k_trk_run(const int2* bucket, con
                 tr.miss = 0;
                 tr.status = 2;
                 tr.pad = 0;
-                tr.s[0] = (double)pts[j].x;
-                tr.s[1] = (double)pts[j].y;
+                tr.s[0] = pts[j].x;
+                tr.s[1] = pts[j].y;
                 tr.s[2] = 0.0;
                 tr.s[3] = 0.0;
                 for (int e = 0; e < 16; ++e) tr.P[e] = 0.0;

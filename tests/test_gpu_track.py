@@ -91,6 +91,32 @@ def test_chain_points_tracked(dev):
         say(f"{W}x{H}x{T}: {n_pts} points, {n} track records, {len(set(rec['id'].tolist()))} tracks")
 
 
+def test_dense_frames_and_wide_coordinates(dev):
+    """Frames past one wavefront's registers: 144 points a frame (the sort
+    through LDS), 144 live tracks (tracks past the first 64 in the
+    workspace) and over a thousand gated candidates (association rounds
+    reading candidates from LDS), on a jittered grid drifting right and
+    down; then points with negative and 17-bit coordinates (the (y, x) order
+    of the sort as signed integers)."""
+    rng = np.random.default_rng(11)
+    rows = []
+    for t in range(10):
+        for gy in range(12):
+            for gx in range(12):
+                rows.append((t, 20 + 4 * gy + t // 2 + int(rng.integers(-1, 2)), 30 + 4 * gx + t + int(rng.integers(-1, 2))))
+    rows = list({r: None for r in rows})  # (t, y, x) keys distinct within a frame
+    pts, cnt = gpu_points(rows, dev)
+    rec, flags = fz.track_points(pts, cnt, 10)
+    n = compare(rec, flags, np.array(rows), 10)
+    say("dense grid", len(rows), "points", n, "records")
+    rows = [(0, -5, 3), (0, -5, -2), (0, 70000, 1), (0, 2, 70000), (0, -70000, 9),
+            (1, -4, 3), (1, 70001, 2), (1, 3, 69999), (1, -69999, 8), (2, -3, 4)]
+    pts, cnt = gpu_points(rows, dev)
+    rec, flags = fz.track_points(pts, cnt, 3)
+    n = compare(rec, flags, np.array(rows), 3)
+    say("wide coordinates", n, "records")
+
+
 def test_limits_are_flagged(dev):
     # a frame with more points than one wavefront's frame buffer holds (1024)
     rows = [(0, y, x) for y in range(0, 66, 2) for x in range(0, 66, 2)]  # 1089 points
