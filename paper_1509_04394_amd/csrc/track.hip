@@ -39,7 +39,8 @@
 
 namespace fz {
 
-constexpr int TRK_THREADS = 64;       // one wavefront marches the frames
+constexpr int TRK_THREADS = 64;       // lanes of a wavefront: the tracks of the list it keeps in registers
+constexpr int TRK_WAVES = 4;          // wavefronts that march the frames together
 constexpr int TRK_MAX_POINTS = 1024;  // points of one frame
 constexpr int TRK_MAX_CANDS = 2048;   // gated (track, point) pairs of one frame
 
@@ -84,6 +85,14 @@ __device__ __forceinline__ double f_row(const double* v, int st, int r)
 {
     if (r < 2) return (0.0 + v[r * st]) + v[(r + 2) * st];
     return 0.0 + v[r * st];
+}
+
+// Orders one wavefront's LDS operations before and after it (a wait for
+// its own outstanding ones); no barrier with the workgroup's other wavefronts.
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+    __builtin_amdgcn_wave_barrier();
 }
 
 struct KModel {  // Q and R of the model (F and H enter through f_row and the written-out products)
@@ -207,7 +216,7 @@ __device__ __forceinline__ void put_record(fz_track* out, uint32_t k, uint32_t c
 // makes, in a few rounds instead of one step per candidate.  The next frame's
 // points are loaded while the current frame is processed; the record count
 // is kept in a register (one wavefront writes every record).
-__global__ __launch_bounds__(TRK_THREADS) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_trk_run(const int2* bucket, const uint32_t* offs, int T,
+__global__ __launch_bounds__(TRK_THREADS * TRK_WAVES) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_trk_run(const int2* bucket, const uint32_t* offs, int T,
                                                           fz_track_opts o, DevTrack* buf0, DevTrack* buf1,
                                                           uint32_t max_tracks, fz_track* out, uint32_t* count,
                                                           uint32_t cap)
@@ -233,14 +242,16 @@ __global__ __launch_bounds__(TRK_THREADS) __attribute__((amdgpu_waves_per_eu(1, 
     Cand* const cand = cu.cand;
     DevTrack* const stage = cu.stage;
     int2* const pin = cu.pin;
-    __shared__ uint32_t s_flags;
-    const int lane = threadIdx.x;
+    __shared__ uint32_t s_flags, s_nc;
+    const int lane = threadIdx.x & (TRK_THREADS - 1);
+    const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x / TRK_THREADS);
+    const bool w0 = wave == 0;  // the wavefront that sorts, associates and writes
     const KModel M(o.q, o.r);
     DevTrack* cur = buf0;
     DevTrack* nxt = buf1;
     uint32_t ntr = 0, next_id = 0, nrec = 0;
     DevTrack rt;  // track `lane` of the current list (lane < ntr)
-    if (lane == 0) s_flags = 0u;
+    if (threadIdx.x == 0) s_flags = 0u;
     if (max_tracks > (uint32_t)FZ_TRACK_MAX_TRACKS) max_tracks = FZ_TRACK_MAX_TRACKS;
     const uint32_t total = offs[T];
     uint32_t f_lo = offs[0], f_hi = T > 0 ? offs[1] : f_lo;
@@ -262,14 +273,15 @@ __global__ __launch_bounds__(TRK_THREADS) __attribute__((amdgpu_waves_per_eu(1, 
         // the frame's point count, in a scalar register (the compiler cannot
         // tell it is the same in every lane; loops over it then run as scalar loops)
         const uint32_t np_all = (uint32_t)__builtin_amdgcn_readfirstlane((int)(f_hi - f_lo));
-        if (np_all > (uint32_t)TRK_MAX_POINTS && lane == 0) s_flags |= FZ_TRACK_TOO_MANY_POINTS;
+        if (np_all > (uint32_t)TRK_MAX_POINTS && threadIdx.x == 0) s_flags |= FZ_TRACK_TOO_MANY_POINTS;
         const uint32_t np = min(np_all, (uint32_t)TRK_MAX_POINTS);
         // 1. the frame's points, sorted by (y, x) (keys are distinct)
         const int ax = pre_x, ay = pre_y;  // point f_lo + lane
-        for (uint32_t j = lane; j < np; j += TRK_THREADS) {
-            if (np > (uint32_t)TRK_THREADS) pin[j] = j < (uint32_t)TRK_THREADS ? make_int2(ax, ay) : bucket[f_lo + j];
-            ptaken[j] = 0;
-        }
+        if (w0)
+            for (uint32_t j = lane; j < np; j += TRK_THREADS) {
+                if (np > (uint32_t)TRK_THREADS) pin[j] = j < (uint32_t)TRK_THREADS ? make_int2(ax, ay) : bucket[f_lo + j];
+                ptaken[j] = 0;
+            }
         // the next frame's bounds and first points, in flight during this frame
         const uint32_t tw = (uint32_t)t & 63u;
         if (tw == 0u) {
@@ -288,20 +300,22 @@ __global__ __launch_bounds__(TRK_THREADS) __attribute__((amdgpu_waves_per_eu(1, 
             // 64-bit integers), read back from LDS eight at a time
             const uint32_t klo = (uint32_t)ax ^ 0x80000000u, khi = (uint32_t)ay;
             const long long ka = (long long)(((unsigned long long)khi << 32) | klo);
-            skey[lane] = (uint32_t)lane < np ? ka : 0x7fffffffffffffffll;  // past np: never smaller
+            if (w0) skey[lane] = (uint32_t)lane < np ? ka : 0x7fffffffffffffffll;  // past np: never smaller
             __syncthreads();
-            uint32_t rank = 0;
-            for (uint32_t k0 = 0; k0 < np; k0 += 8) {
-                long long kb[8];
+            if (w0) {
+                uint32_t rank = 0;
+                for (uint32_t k0 = 0; k0 < np; k0 += 8) {
+                    long long kb[8];
 #pragma unroll
-                for (uint32_t q = 0; q < 8; ++q) kb[q] = skey[k0 + q];
+                    for (uint32_t q = 0; q < 8; ++q) kb[q] = skey[k0 + q];
 #pragma unroll
-                for (uint32_t q = 0; q < 8; ++q) rank += kb[q] < ka ? 1u : 0u;
+                    for (uint32_t q = 0; q < 8; ++q) rank += kb[q] < ka ? 1u : 0u;
+                }
+                if ((uint32_t)lane < np) pts[rank] = make_double2((double)ax, (double)ay);
             }
-            if ((uint32_t)lane < np) pts[rank] = make_double2((double)ax, (double)ay);
         } else {
             __syncthreads();
-            for (uint32_t j = lane; j < np; j += TRK_THREADS) {
+            for (uint32_t j = threadIdx.x; j < np; j += TRK_THREADS * TRK_WAVES) {
                 const int2 a = pin[j];
                 uint32_t rank = 0;
 #pragma unroll 8
@@ -312,19 +326,20 @@ __global__ __launch_bounds__(TRK_THREADS) __attribute__((amdgpu_waves_per_eu(1, 
                 pts[rank] = make_double2((double)a.x, (double)a.y);
             }
         }
+        if (threadIdx.x == 0) s_nc = 0u;
         __syncthreads();
-        // 2. predict every live track and list its gated candidate pairs; a
-        // candidate's slot is its rank among the wavefront's candidates of the
-        // same point (a ballot) after all earlier ones, so the count stays in a
-        // wavefront-uniform register
-        uint32_t ncand = 0;
+        // 2. predict every live track and list its gated candidate pairs.  Every
+        // wavefront predicts every track (each keeps the list's first 64 in its
+        // registers, and all make the same updates), and takes every fourth group
+        // of eight points; a group's pairs get consecutive slots from one LDS
+        // count, a pair its rank in the group's ballots
         for (uint32_t c0 = 0; c0 < ntr; c0 += TRK_THREADS) {
             const uint32_t i = c0 + lane;
             const bool act = i < ntr;
             double hs[2] = {0.0, 0.0}, Si[4] = {0.0, 0.0, 0.0, 0.0};
             int32_t id = 0;
+            DevTrack tr;
             if (act) {
-                DevTrack tr;
                 if (c0 == 0)
                     tr = rt;
                 else
@@ -350,20 +365,23 @@ __global__ __launch_bounds__(TRK_THREADS) __attribute__((amdgpu_waves_per_eu(1, 
                 for (int e = 0; e < 4; ++e) tr.s[e] = s1[e];
                 for (int e = 0; e < 16; ++e) tr.P[e] = Pp[e];
                 for (int e = 0; e < 4; ++e) tr.Si[e] = Si[e];
-                if (c0 == 0)
-                    rt = tr;
-                else
-                    cur[i] = tr;
+                if (c0 == 0) rt = tr;
                 tmatch[i] = -1;
                 for (int e = 0; e < 2; ++e) hs[e] = 0.0 + s1[e];  // H s1
                 id = tr.id;
+            }
+            // a track past the first 64 is read from the workspace by every
+            // wavefront, and its prediction written back by one, once all have read it
+            if (c0 > 0) {
+                __syncthreads();
+                if (act && w0) cur[i] = tr;
             }
             // eight points at a time: their d2 are independent chains of double
             // operations, written out step by step across the eight so that each
             // step's operations are in flight together; every lane then stores its
             // pair, those that are not candidates into a slot of their own past the
             // list (as does an overflow), so the group is one straight block
-            for (uint32_t j0 = 0; j0 < np; j0 += 8) {
+            for (uint32_t j0 = 8u * (uint32_t)wave; j0 < np; j0 += 8u * TRK_WAVES) {
                 double2 pv[8];
                 double nu0[8], nu1[8], tm[4][8], d2v[8];
 #pragma unroll
@@ -405,16 +423,24 @@ __global__ __launch_bounds__(TRK_THREADS) __attribute__((amdgpu_waves_per_eu(1, 
                     const double dq = in ? d2v[q] : __builtin_huge_val();  // outside: never gated in
                     m[q] = __ballot(dq <= o.gate);
                 }
-                uint32_t base[8];
+                uint32_t base[8], ncand = 0;
 #pragma unroll
                 for (int q = 0; q < 8; ++q) {
                     base[q] = ncand;
                     ncand += (uint32_t)__popcll(m[q]);
                 }
+                uint32_t gbase = 0;
+                if (ncand) {
+                    if (lane == 0) {
+                        gbase = atomicAdd(&s_nc, ncand);
+                        if (gbase + ncand > (uint32_t)TRK_MAX_CANDS) atomicOr(&s_flags, (uint32_t)FZ_TRACK_TOO_MANY_CANDIDATES);
+                    }
+                    gbase = (uint32_t)__builtin_amdgcn_readfirstlane((int)gbase);
+                }
 #pragma unroll
                 for (int q = 0; q < 8; ++q) {
                     const bool pass = (m[q] >> lane) & 1ull;
-                    const uint32_t k = base[q] + __builtin_amdgcn_mbcnt_hi((uint32_t)(m[q] >> 32),
+                    const uint32_t k = gbase + base[q] + __builtin_amdgcn_mbcnt_hi((uint32_t)(m[q] >> 32),
                                                                            __builtin_amdgcn_mbcnt_lo((uint32_t)m[q], 0u));
                     Cand c;
                     c.d2 = d2v[q];
@@ -425,9 +451,8 @@ __global__ __launch_bounds__(TRK_THREADS) __attribute__((amdgpu_waves_per_eu(1, 
                 }
             }
         }
-        if (ncand > (uint32_t)TRK_MAX_CANDS && lane == 0) s_flags |= FZ_TRACK_TOO_MANY_CANDIDATES;
         __syncthreads();
-        const uint32_t nc = min(ncand, (uint32_t)TRK_MAX_CANDS);
+        const uint32_t nc = min(s_nc, (uint32_t)TRK_MAX_CANDS);
         // 3. greedy association in rounds: an open candidate that comes first
         // (in the (d2, id, point) order) among the open candidates of both its
         // track and its point is taken; then every candidate of a taken track
@@ -435,111 +460,115 @@ __global__ __launch_bounds__(TRK_THREADS) __attribute__((amdgpu_waves_per_eu(1, 
         // (lane, lane + 64) in registers, and the first-of slots of a track or
         // point are cleared when its candidates stay open for another round;
         // beyond that the candidates are read from LDS in every pass.
-        if (nc <= 2u * TRK_THREADS) {
-            unsigned long long rd[2], rk[2];
-            int rti[2], rpj[2];
-            bool al[2];
+        // One wavefront forms the association (its passes are ordered by waits on
+        // its own LDS operations, no barrier); the others wait at the next barrier.
+        if (w0) {
+            if (nc <= 2u * TRK_THREADS) {
+                unsigned long long rd[2], rk[2];
+                int rti[2], rpj[2];
+                bool al[2];
 #pragma unroll
-            for (int q = 0; q < 2; ++q) {
-                const uint32_t c = (uint32_t)lane + (uint32_t)q * TRK_THREADS;
-                al[q] = c < nc;
-                rd[q] = rk[q] = 0ull;
-                rti[q] = rpj[q] = 0;
-                if (al[q]) {
-                    const Cand a = cand[c];
-                    rd[q] = d2_key(a.d2);
-                    rk[q] = idpj_key(a);
-                    rti[q] = a.ti;
-                    rpj[q] = a.pj;
-                    tb_d[a.ti] = tb_k[a.ti] = ~0ull;
-                    pb_d[a.pj] = pb_k[a.pj] = ~0ull;
-                }
-            }
-            for (;;) {
-                __syncthreads();
-#pragma unroll
-                for (int q = 0; q < 2; ++q)
+                for (int q = 0; q < 2; ++q) {
+                    const uint32_t c = (uint32_t)lane + (uint32_t)q * TRK_THREADS;
+                    al[q] = c < nc;
+                    rd[q] = rk[q] = 0ull;
+                    rti[q] = rpj[q] = 0;
                     if (al[q]) {
-                        atomicMin(&tb_d[rti[q]], rd[q]);
-                        atomicMin(&pb_d[rpj[q]], rd[q]);
-                    }
-                __syncthreads();
-#pragma unroll
-                for (int q = 0; q < 2; ++q)
-                    if (al[q]) {
-                        if (rd[q] == tb_d[rti[q]]) atomicMin(&tb_k[rti[q]], rk[q]);
-                        if (rd[q] == pb_d[rpj[q]]) atomicMin(&pb_k[rpj[q]], rk[q]);
-                    }
-                __syncthreads();
-#pragma unroll
-                for (int q = 0; q < 2; ++q)
-                    if (al[q] && rd[q] == tb_d[rti[q]] && rk[q] == tb_k[rti[q]] && rd[q] == pb_d[rpj[q]] &&
-                        rk[q] == pb_k[rpj[q]]) {
-                        tmatch[rti[q]] = (int16_t)rpj[q];
-                        ptaken[rpj[q]] = 1;
-                    }
-                __syncthreads();
-                bool open = false;
-#pragma unroll
-                for (int q = 0; q < 2; ++q)
-                    if (al[q]) {
-                        if (tmatch[rti[q]] >= 0 || ptaken[rpj[q]]) {
-                            al[q] = false;
-                        } else {
-                            open = true;
-                            tb_d[rti[q]] = tb_k[rti[q]] = ~0ull;
-                            pb_d[rpj[q]] = pb_k[rpj[q]] = ~0ull;
-                        }
-                    }
-                if (!__any(open)) break;
-            }
-        } else {
-            for (uint32_t c = lane; c < nc; c += TRK_THREADS) calive[c] = 1;
-            for (;;) {
-                __syncthreads();
-                for (uint32_t c = lane; c < nc; c += TRK_THREADS)
-                    if (calive[c]) {
                         const Cand a = cand[c];
+                        rd[q] = d2_key(a.d2);
+                        rk[q] = idpj_key(a);
+                        rti[q] = a.ti;
+                        rpj[q] = a.pj;
                         tb_d[a.ti] = tb_k[a.ti] = ~0ull;
                         pb_d[a.pj] = pb_k[a.pj] = ~0ull;
                     }
-                __syncthreads();
-                for (uint32_t c = lane; c < nc; c += TRK_THREADS)
-                    if (calive[c]) {
-                        const Cand a = cand[c];
-                        const unsigned long long d = d2_key(a.d2);
-                        atomicMin(&tb_d[a.ti], d);
-                        atomicMin(&pb_d[a.pj], d);
-                    }
-                __syncthreads();
-                for (uint32_t c = lane; c < nc; c += TRK_THREADS)
-                    if (calive[c]) {
-                        const Cand a = cand[c];
-                        const unsigned long long d = d2_key(a.d2), k = idpj_key(a);
-                        if (d == tb_d[a.ti]) atomicMin(&tb_k[a.ti], k);
-                        if (d == pb_d[a.pj]) atomicMin(&pb_k[a.pj], k);
-                    }
-                __syncthreads();
-                for (uint32_t c = lane; c < nc; c += TRK_THREADS)
-                    if (calive[c]) {
-                        const Cand a = cand[c];
-                        const unsigned long long d = d2_key(a.d2), k = idpj_key(a);
-                        if (d == tb_d[a.ti] && k == tb_k[a.ti] && d == pb_d[a.pj] && k == pb_k[a.pj]) {
-                            tmatch[a.ti] = a.pj;
-                            ptaken[a.pj] = 1;
+                }
+                for (;;) {
+                    wave_sync();
+#pragma unroll
+                    for (int q = 0; q < 2; ++q)
+                        if (al[q]) {
+                            atomicMin(&tb_d[rti[q]], rd[q]);
+                            atomicMin(&pb_d[rpj[q]], rd[q]);
                         }
-                    }
-                __syncthreads();
-                bool open = false;
-                for (uint32_t c = lane; c < nc; c += TRK_THREADS)
-                    if (calive[c]) {
-                        const Cand a = cand[c];
-                        if (tmatch[a.ti] >= 0 || ptaken[a.pj])
-                            calive[c] = 0;
-                        else
-                            open = true;
-                    }
-                if (!__any(open)) break;
+                    wave_sync();
+#pragma unroll
+                    for (int q = 0; q < 2; ++q)
+                        if (al[q]) {
+                            if (rd[q] == tb_d[rti[q]]) atomicMin(&tb_k[rti[q]], rk[q]);
+                            if (rd[q] == pb_d[rpj[q]]) atomicMin(&pb_k[rpj[q]], rk[q]);
+                        }
+                    wave_sync();
+#pragma unroll
+                    for (int q = 0; q < 2; ++q)
+                        if (al[q] && rd[q] == tb_d[rti[q]] && rk[q] == tb_k[rti[q]] && rd[q] == pb_d[rpj[q]] &&
+                            rk[q] == pb_k[rpj[q]]) {
+                            tmatch[rti[q]] = (int16_t)rpj[q];
+                            ptaken[rpj[q]] = 1;
+                        }
+                    wave_sync();
+                    bool open = false;
+#pragma unroll
+                    for (int q = 0; q < 2; ++q)
+                        if (al[q]) {
+                            if (tmatch[rti[q]] >= 0 || ptaken[rpj[q]]) {
+                                al[q] = false;
+                            } else {
+                                open = true;
+                                tb_d[rti[q]] = tb_k[rti[q]] = ~0ull;
+                                pb_d[rpj[q]] = pb_k[rpj[q]] = ~0ull;
+                            }
+                        }
+                    if (!__any(open)) break;
+                }
+            } else {
+                for (uint32_t c = lane; c < nc; c += TRK_THREADS) calive[c] = 1;
+                for (;;) {
+                    wave_sync();
+                    for (uint32_t c = lane; c < nc; c += TRK_THREADS)
+                        if (calive[c]) {
+                            const Cand a = cand[c];
+                            tb_d[a.ti] = tb_k[a.ti] = ~0ull;
+                            pb_d[a.pj] = pb_k[a.pj] = ~0ull;
+                        }
+                    wave_sync();
+                    for (uint32_t c = lane; c < nc; c += TRK_THREADS)
+                        if (calive[c]) {
+                            const Cand a = cand[c];
+                            const unsigned long long d = d2_key(a.d2);
+                            atomicMin(&tb_d[a.ti], d);
+                            atomicMin(&pb_d[a.pj], d);
+                        }
+                    wave_sync();
+                    for (uint32_t c = lane; c < nc; c += TRK_THREADS)
+                        if (calive[c]) {
+                            const Cand a = cand[c];
+                            const unsigned long long d = d2_key(a.d2), k = idpj_key(a);
+                            if (d == tb_d[a.ti]) atomicMin(&tb_k[a.ti], k);
+                            if (d == pb_d[a.pj]) atomicMin(&pb_k[a.pj], k);
+                        }
+                    wave_sync();
+                    for (uint32_t c = lane; c < nc; c += TRK_THREADS)
+                        if (calive[c]) {
+                            const Cand a = cand[c];
+                            const unsigned long long d = d2_key(a.d2), k = idpj_key(a);
+                            if (d == tb_d[a.ti] && k == tb_k[a.ti] && d == pb_d[a.pj] && k == pb_k[a.pj]) {
+                                tmatch[a.ti] = a.pj;
+                                ptaken[a.pj] = 1;
+                            }
+                        }
+                    wave_sync();
+                    bool open = false;
+                    for (uint32_t c = lane; c < nc; c += TRK_THREADS)
+                        if (calive[c]) {
+                            const Cand a = cand[c];
+                            if (tmatch[a.ti] >= 0 || ptaken[a.pj])
+                                calive[c] = 0;
+                            else
+                                open = true;
+                        }
+                    if (!__any(open)) break;
+                }
             }
         }
         __syncthreads();
@@ -587,7 +616,7 @@ __global__ __launch_bounds__(TRK_THREADS) __attribute__((amdgpu_waves_per_eu(1, 
             }
             const uint64_t m = __ballot(alive);
             const uint32_t before = (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
-            if (alive) {
+            if (alive && w0) {
                 const uint32_t pos = n_alive + before;
                 if (pos < (uint32_t)TRK_THREADS)
                     stage[pos] = tr;
@@ -606,9 +635,9 @@ __global__ __launch_bounds__(TRK_THREADS) __attribute__((amdgpu_waves_per_eu(1, 
             const uint32_t before = (uint32_t)__popcll(__ballot(fresh) & ((1ull << lane) - 1ull));
             const uint32_t pos = n_alive + n_new + before;
             const bool keep = fresh && pos < max_tracks;
-            if (fresh && !keep) atomicOr(&s_flags, (uint32_t)FZ_TRACK_TOO_MANY_TRACKS);
+            if (fresh && !keep && w0) atomicOr(&s_flags, (uint32_t)FZ_TRACK_TOO_MANY_TRACKS);
             const uint64_t m = __ballot(keep);
-            if (keep) {
+            if (keep && w0) {
                 DevTrack tr;
                 tr.id = (int32_t)(next_id + n_new + before);
                 tr.miss = 0;
@@ -644,7 +673,7 @@ __global__ __launch_bounds__(TRK_THREADS) __attribute__((amdgpu_waves_per_eu(1, 
         f_hi = n_hi;
         __syncthreads();
     }
-    if (lane == 0) {
+    if (threadIdx.x == 0) {
         count[0] = nrec;
         atomicOr(&count[1], s_flags);
     }
@@ -684,7 +713,7 @@ fz_status track_points(const fz_point* d_points, const uint32_t* d_count, uint32
     hipLaunchKernelGGL(k_trk_scan, dim3(1), dim3(256), 0, s, counts, T, offs, cursor);
     if (cap > 0)
         hipLaunchKernelGGL(k_trk_scatter, dim3(gp), dim3(256), 0, s, d_points, d_count, cap, T, cursor, bucket);
-    hipLaunchKernelGGL(k_trk_run, dim3(1), dim3(TRK_THREADS), 0, s, bucket, offs, T, o, b0, b1,
+    hipLaunchKernelGGL(k_trk_run, dim3(1), dim3(TRK_THREADS * TRK_WAVES), 0, s, bucket, offs, T, o, b0, b1,
                        (uint32_t)o.max_tracks, d_tracks, d_track_count, track_cap);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(FZ_E_HIP, std::string("fz_track_points: launch: ") + hipGetErrorString(e));
