@@ -21,7 +21,7 @@
 // bits as those sums (see f_row).
 //
 // Launches: the points are bucketed by frame (a histogram, one scan, a
-// scatter into the workspace), then one wavefront marches the frames in
+// scatter into the workspace), then one workgroup marches the frames in
 // order: it sorts the frame's points by (y, x) (rank by counting), predicts
 // every live track, lists the gated candidate pairs and takes them greedily
 // in rounds of candidates that come first for both their track and their
@@ -204,18 +204,21 @@ __device__ __forceinline__ void put_record(fz_track* out, uint32_t k, uint32_t c
     }
 }
 
-// One wavefront marches the frames.  Every lane owns the tracks lane,
-// lane + 64, ... of the current list: it predicts them and lists their gated
-// candidates in one pass, and later updates them.  The first 64 tracks of the
-// list stay in the lanes' registers from frame to frame (passed through LDS
-// when the list is compacted); tracks past them live in the workspace.  The
+// One workgroup of TRK_WAVES wavefronts marches the frames.  In every
+// wavefront each lane owns the tracks lane, lane + 64, ... of the current
+// list: it predicts them, tests them against the wavefront's share of the
+// frame's points, and later updates them; the wavefronts make the same
+// predictions and updates, so each can keep the list's first 64 tracks in its
+// registers from frame to frame (passed through LDS when the list is
+// compacted); tracks past them live in the workspace.  The first wavefront
+// sorts the points, forms the association and writes the list and records.  The
 // greedy association is formed in rounds: every candidate that is the first
 // (in the (d2, id, point) order) of the remaining candidates of both its track
 // and its point is taken, and candidates of taken tracks and points leave;
 // for a strict total order this is the matching the one-by-one greedy pass
 // makes, in a few rounds instead of one step per candidate.  The next frame's
 // points are loaded while the current frame is processed; the record count
-// is kept in a register (one wavefront writes every record).
+// is kept in a register (the first wavefront writes every record).
 __global__ __launch_bounds__(TRK_THREADS * TRK_WAVES) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_trk_run(const int2* bucket, const uint32_t* offs, int T,
                                                           fz_track_opts o, DevTrack* buf0, DevTrack* buf1,
                                                           uint32_t max_tracks, fz_track* out, uint32_t* count,
