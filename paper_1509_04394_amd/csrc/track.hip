@@ -486,6 +486,9 @@ __global__ __launch_bounds__(TRK_THREADS * TRK_WAVES) __attribute__((amdgpu_wave
                         pb_d[a.pj] = pb_k[a.pj] = ~0ull;
                     }
                 }
+                // every pass loads what it compares before comparing (loads of a
+                // closed pair read its stale slots and are not used), so a pass
+                // waits on LDS once
                 for (;;) {
                     wave_sync();
 #pragma unroll
@@ -495,26 +498,44 @@ __global__ __launch_bounds__(TRK_THREADS * TRK_WAVES) __attribute__((amdgpu_wave
                             atomicMin(&pb_d[rpj[q]], rd[q]);
                         }
                     wave_sync();
+                    unsigned long long td[2], pd[2], tk[2], pk[2];
+#pragma unroll
+                    for (int q = 0; q < 2; ++q) {
+                        td[q] = tb_d[rti[q]];
+                        pd[q] = pb_d[rpj[q]];
+                    }
 #pragma unroll
                     for (int q = 0; q < 2; ++q)
                         if (al[q]) {
-                            if (rd[q] == tb_d[rti[q]]) atomicMin(&tb_k[rti[q]], rk[q]);
-                            if (rd[q] == pb_d[rpj[q]]) atomicMin(&pb_k[rpj[q]], rk[q]);
+                            if (rd[q] == td[q]) atomicMin(&tb_k[rti[q]], rk[q]);
+                            if (rd[q] == pd[q]) atomicMin(&pb_k[rpj[q]], rk[q]);
                         }
                     wave_sync();
 #pragma unroll
-                    for (int q = 0; q < 2; ++q)
-                        if (al[q] && rd[q] == tb_d[rti[q]] && rk[q] == tb_k[rti[q]] && rd[q] == pb_d[rpj[q]] &&
-                            rk[q] == pb_k[rpj[q]]) {
+                    for (int q = 0; q < 2; ++q) {
+                        tk[q] = tb_k[rti[q]];
+                        pk[q] = pb_k[rpj[q]];
+                    }
+#pragma unroll
+                    for (int q = 0; q < 2; ++q) {
+                        const bool take = al[q] & (rd[q] == td[q]) & (rk[q] == tk[q]) & (rd[q] == pd[q]) & (rk[q] == pk[q]);
+                        if (take) {
                             tmatch[rti[q]] = (int16_t)rpj[q];
                             ptaken[rpj[q]] = 1;
                         }
+                    }
                     wave_sync();
+                    int tmq[2], ptq[2];
+#pragma unroll
+                    for (int q = 0; q < 2; ++q) {
+                        tmq[q] = tmatch[rti[q]];
+                        ptq[q] = ptaken[rpj[q]];
+                    }
                     bool open = false;
 #pragma unroll
                     for (int q = 0; q < 2; ++q)
                         if (al[q]) {
-                            if (tmatch[rti[q]] >= 0 || ptaken[rpj[q]]) {
+                            if (tmq[q] >= 0 || ptq[q]) {
                                 al[q] = false;
                             } else {
                                 open = true;
