@@ -41,6 +41,7 @@ namespace fz {
 
 constexpr int TRK_THREADS = 64;       // lanes of a wavefront: the tracks of the list it keeps in registers
 constexpr int TRK_WAVES = 4;          // wavefronts that march the frames together
+constexpr int TRK_GROUP = 4;          // points a wavefront tests at a time in the candidate search
 constexpr int TRK_MAX_POINTS = 1024;  // points of one frame
 constexpr int TRK_MAX_CANDS = 2048;   // gated (track, point) pairs of one frame
 
@@ -225,8 +226,8 @@ __global__ __launch_bounds__(TRK_THREADS * TRK_WAVES) __attribute__((amdgpu_wave
                                                           uint32_t cap)
 {
     // the frame's points sorted by (y, x), as doubles; the candidate search reads
-    // them eight at a time, so up to seven past the frame's are read and not used
-    __shared__ double2 pts[TRK_MAX_POINTS + 8];
+    // them TRK_GROUP at a time, so up to TRK_GROUP - 1 past the frame's are read and not used
+    __shared__ double2 pts[TRK_MAX_POINTS + TRK_GROUP];
     __shared__ long long skey[TRK_THREADS];  // sort keys of a frame of at most 64 points
     // the gated candidates of the frame; the same memory holds a frame's
     // points as loaded before they are sorted, and after the association the
@@ -300,19 +301,19 @@ __global__ __launch_bounds__(TRK_THREADS * TRK_WAVES) __attribute__((amdgpu_wave
         if (np <= (uint32_t)TRK_THREADS) {
             // lane j holds point j: its rank counts the smaller (y, x) keys (y in
             // the high word, x offset by 2^31 in the low word, compared as signed
-            // 64-bit integers), read back from LDS eight at a time
+            // 64-bit integers), read back from LDS sixteen at a time
             const uint32_t klo = (uint32_t)ax ^ 0x80000000u, khi = (uint32_t)ay;
             const long long ka = (long long)(((unsigned long long)khi << 32) | klo);
             if (w0) skey[lane] = (uint32_t)lane < np ? ka : 0x7fffffffffffffffll;  // past np: never smaller
             __syncthreads();
             if (w0) {
                 uint32_t rank = 0;
-                for (uint32_t k0 = 0; k0 < np; k0 += 8) {
-                    long long kb[8];
+                for (uint32_t k0 = 0; k0 < np; k0 += 16) {
+                    long long kb[16];
 #pragma unroll
-                    for (uint32_t q = 0; q < 8; ++q) kb[q] = skey[k0 + q];
+                    for (uint32_t q = 0; q < 16; ++q) kb[q] = skey[k0 + q];
 #pragma unroll
-                    for (uint32_t q = 0; q < 8; ++q) rank += kb[q] < ka ? 1u : 0u;
+                    for (uint32_t q = 0; q < 16; ++q) rank += kb[q] < ka ? 1u : 0u;
                 }
                 if ((uint32_t)lane < np) pts[rank] = make_double2((double)ax, (double)ay);
             }
@@ -334,7 +335,7 @@ __global__ __launch_bounds__(TRK_THREADS * TRK_WAVES) __attribute__((amdgpu_wave
         // 2. predict every live track and list its gated candidate pairs.  Every
         // wavefront predicts every track (each keeps the list's first 64 in its
         // registers, and all make the same updates), and takes every fourth group
-        // of eight points; a group's pairs get consecutive slots from one LDS
+        // of TRK_GROUP points; a group's pairs get consecutive slots from one LDS
         // count, a pair its rank in the group's ballots
         for (uint32_t c0 = 0; c0 < ntr; c0 += TRK_THREADS) {
             const uint32_t i = c0 + lane;
@@ -379,56 +380,56 @@ __global__ __launch_bounds__(TRK_THREADS * TRK_WAVES) __attribute__((amdgpu_wave
                 __syncthreads();
                 if (act && w0) cur[i] = tr;
             }
-            // eight points at a time: their d2 are independent chains of double
-            // operations, written out step by step across the eight so that each
+            // TRK_GROUP points at a time: their d2 are independent chains of double
+            // operations, written out step by step across the group so that each
             // step's operations are in flight together; every lane then stores its
             // pair, those that are not candidates into a slot of their own past the
             // list (as does an overflow), so the group is one straight block
-            for (uint32_t j0 = 8u * (uint32_t)wave; j0 < np; j0 += 8u * TRK_WAVES) {
-                double2 pv[8];
-                double nu0[8], nu1[8], tm[4][8], d2v[8];
+            for (uint32_t j0 = (uint32_t)TRK_GROUP * (uint32_t)wave; j0 < np; j0 += (uint32_t)TRK_GROUP * TRK_WAVES) {
+                double2 pv[TRK_GROUP];
+                double nu0[TRK_GROUP], nu1[TRK_GROUP], tm[4][TRK_GROUP], d2v[TRK_GROUP];
 #pragma unroll
-                for (int q = 0; q < 8; ++q) pv[q] = pts[j0 + (uint32_t)q];
+                for (int q = 0; q < TRK_GROUP; ++q) pv[q] = pts[j0 + (uint32_t)q];
 #pragma unroll
-                for (int q = 0; q < 8; ++q) {
+                for (int q = 0; q < TRK_GROUP; ++q) {
                     nu0[q] = pv[q].x - hs[0];
                     nu1[q] = pv[q].y - hs[1];
                 }
                 // d2 = nu^T S^-1 nu: the terms (nu_a Si_ab) nu_b summed from 0.0 in
                 // (a, b) order
 #pragma unroll
-                for (int q = 0; q < 8; ++q) {
+                for (int q = 0; q < TRK_GROUP; ++q) {
                     tm[0][q] = nu0[q] * Si[0];
                     tm[1][q] = nu0[q] * Si[1];
                     tm[2][q] = nu1[q] * Si[2];
                     tm[3][q] = nu1[q] * Si[3];
                 }
 #pragma unroll
-                for (int q = 0; q < 8; ++q) {
+                for (int q = 0; q < TRK_GROUP; ++q) {
                     tm[0][q] = tm[0][q] * nu0[q];
                     tm[1][q] = tm[1][q] * nu1[q];
                     tm[2][q] = tm[2][q] * nu0[q];
                     tm[3][q] = tm[3][q] * nu1[q];
                 }
 #pragma unroll
-                for (int q = 0; q < 8; ++q) d2v[q] = 0.0 + tm[0][q];
+                for (int q = 0; q < TRK_GROUP; ++q) d2v[q] = 0.0 + tm[0][q];
 #pragma unroll
                 for (int e = 1; e < 4; ++e)
 #pragma unroll
-                    for (int q = 0; q < 8; ++q) d2v[q] = d2v[q] + tm[e][q];
-                // the gate of all eight first (one mask each), then the slots:
+                    for (int q = 0; q < TRK_GROUP; ++q) d2v[q] = d2v[q] + tm[e][q];
+                // the gate of the whole group first (one mask each), then the slots:
                 // the masks' counts in order give each point's base, a lane's rank
                 // in its mask its place
-                uint64_t m[8];
+                uint64_t m[TRK_GROUP];
 #pragma unroll
-                for (int q = 0; q < 8; ++q) {
+                for (int q = 0; q < TRK_GROUP; ++q) {
                     const bool in = act && j0 + (uint32_t)q < np;
                     const double dq = in ? d2v[q] : __builtin_huge_val();  // outside: never gated in
                     m[q] = __ballot(dq <= o.gate);
                 }
-                uint32_t base[8], ncand = 0;
+                uint32_t base[TRK_GROUP], ncand = 0;
 #pragma unroll
-                for (int q = 0; q < 8; ++q) {
+                for (int q = 0; q < TRK_GROUP; ++q) {
                     base[q] = ncand;
                     ncand += (uint32_t)__popcll(m[q]);
                 }
@@ -441,7 +442,7 @@ __global__ __launch_bounds__(TRK_THREADS * TRK_WAVES) __attribute__((amdgpu_wave
                     gbase = (uint32_t)__builtin_amdgcn_readfirstlane((int)gbase);
                 }
 #pragma unroll
-                for (int q = 0; q < 8; ++q) {
+                for (int q = 0; q < TRK_GROUP; ++q) {
                     const bool pass = (m[q] >> lane) & 1ull;
                     const uint32_t k = gbase + base[q] + __builtin_amdgcn_mbcnt_hi((uint32_t)(m[q] >> 32),
                                                                            __builtin_amdgcn_mbcnt_lo((uint32_t)m[q], 0u));
