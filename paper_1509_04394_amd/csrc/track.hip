@@ -225,9 +225,11 @@ __global__ __launch_bounds__(TRK_THREADS * TRK_WAVES) __attribute__((amdgpu_wave
                                                           uint32_t max_tracks, fz_track* out, uint32_t* count,
                                                           uint32_t cap)
 {
-    // the frame's points sorted by (y, x), as doubles; the candidate search reads
-    // them TRK_GROUP at a time, so up to TRK_GROUP - 1 past the frame's are read and not used
-    __shared__ double2 pts[TRK_MAX_POINTS + TRK_GROUP];
+    // the frame's points sorted by (y, x), as doubles, for frames of even and
+    // odd t (the next frame's are sorted while this one is associated); the
+    // candidate search reads them TRK_GROUP at a time, so up to TRK_GROUP - 1
+    // past the frame's are read and not used
+    __shared__ double2 pts2[2][TRK_MAX_POINTS + TRK_GROUP];
     __shared__ long long skey[TRK_THREADS];  // sort keys of a frame of at most 64 points
     // the gated candidates of the frame; the same memory holds a frame's
     // points as loaded before they are sorted, and after the association the
@@ -279,7 +281,10 @@ __global__ __launch_bounds__(TRK_THREADS * TRK_WAVES) __attribute__((amdgpu_wave
         const uint32_t np_all = (uint32_t)__builtin_amdgcn_readfirstlane((int)(f_hi - f_lo));
         if (np_all > (uint32_t)TRK_MAX_POINTS && threadIdx.x == 0) s_flags |= FZ_TRACK_TOO_MANY_POINTS;
         const uint32_t np = min(np_all, (uint32_t)TRK_MAX_POINTS);
-        // 1. the frame's points, sorted by (y, x) (keys are distinct)
+        // 1. the frame's points, sorted by (y, x) (keys are distinct); a frame of
+        // at most 64 points after the first was sorted during the previous one
+        double2* const pts = pts2[t & 1];
+        const bool pre_sorted = t > 0 && np <= (uint32_t)TRK_THREADS;
         const int ax = pre_x, ay = pre_y;  // point f_lo + lane
         if (w0)
             for (uint32_t j = lane; j < np; j += TRK_THREADS) {
@@ -298,36 +303,38 @@ __global__ __launch_bounds__(TRK_THREADS * TRK_WAVES) __attribute__((amdgpu_wave
             pre_x = q.x;
             pre_y = q.y;
         }
-        if (np <= (uint32_t)TRK_THREADS) {
-            // lane j holds point j: its rank counts the smaller (y, x) keys (y in
-            // the high word, x offset by 2^31 in the low word, compared as signed
-            // 64-bit integers), read back from LDS sixteen at a time
-            const uint32_t klo = (uint32_t)ax ^ 0x80000000u, khi = (uint32_t)ay;
-            const long long ka = (long long)(((unsigned long long)khi << 32) | klo);
-            if (w0) skey[lane] = (uint32_t)lane < np ? ka : 0x7fffffffffffffffll;  // past np: never smaller
-            __syncthreads();
-            if (w0) {
-                uint32_t rank = 0;
-                for (uint32_t k0 = 0; k0 < np; k0 += 16) {
-                    long long kb[16];
+        if (!pre_sorted) {
+            if (np <= (uint32_t)TRK_THREADS) {
+                // lane j holds point j: its rank counts the smaller (y, x) keys (y in
+                // the high word, x offset by 2^31 in the low word, compared as signed
+                // 64-bit integers), read back from LDS sixteen at a time
+                const uint32_t klo = (uint32_t)ax ^ 0x80000000u, khi = (uint32_t)ay;
+                const long long ka = (long long)(((unsigned long long)khi << 32) | klo);
+                if (w0) skey[lane] = (uint32_t)lane < np ? ka : 0x7fffffffffffffffll;  // past np: never smaller
+                __syncthreads();
+                if (w0) {
+                    uint32_t rank = 0;
+                    for (uint32_t k0 = 0; k0 < np; k0 += 16) {
+                        long long kb[16];
 #pragma unroll
-                    for (uint32_t q = 0; q < 16; ++q) kb[q] = skey[k0 + q];
+                        for (uint32_t q = 0; q < 16; ++q) kb[q] = skey[k0 + q];
 #pragma unroll
-                    for (uint32_t q = 0; q < 16; ++q) rank += kb[q] < ka ? 1u : 0u;
+                        for (uint32_t q = 0; q < 16; ++q) rank += kb[q] < ka ? 1u : 0u;
+                    }
+                    if ((uint32_t)lane < np) pts[rank] = make_double2((double)ax, (double)ay);
                 }
-                if ((uint32_t)lane < np) pts[rank] = make_double2((double)ax, (double)ay);
-            }
-        } else {
-            __syncthreads();
-            for (uint32_t j = threadIdx.x; j < np; j += TRK_THREADS * TRK_WAVES) {
-                const int2 a = pin[j];
-                uint32_t rank = 0;
+            } else {
+                __syncthreads();
+                for (uint32_t j = threadIdx.x; j < np; j += TRK_THREADS * TRK_WAVES) {
+                    const int2 a = pin[j];
+                    uint32_t rank = 0;
 #pragma unroll 8
-                for (uint32_t k = 0; k < np; ++k) {
-                    const int2 b = pin[k];
-                    rank += (b.y < a.y || (b.y == a.y && b.x < a.x)) ? 1u : 0u;
+                    for (uint32_t k = 0; k < np; ++k) {
+                        const int2 b = pin[k];
+                        rank += (b.y < a.y || (b.y == a.y && b.x < a.x)) ? 1u : 0u;
+                    }
+                    pts[rank] = make_double2((double)a.x, (double)a.y);
                 }
-                pts[rank] = make_double2((double)a.x, (double)a.y);
             }
         }
         if (threadIdx.x == 0) s_nc = 0u;
@@ -466,6 +473,25 @@ __global__ __launch_bounds__(TRK_THREADS * TRK_WAVES) __attribute__((amdgpu_wave
         // beyond that the candidates are read from LDS in every pass.
         // One wavefront forms the association (its passes are ordered by waits on
         // its own LDS operations, no barrier); the others wait at the next barrier.
+        const uint32_t np_next = min(n_hi - n_lo, (uint32_t)TRK_MAX_POINTS);  // the next frame's, as it will count them
+        if (wave == 1 && t + 1 < T && np_next <= (uint32_t)TRK_THREADS) {
+            // the second wavefront sorts the next frame's points (its lanes hold
+            // them, loaded at this frame's start) into the other buffer, as the
+            // first one does for a frame it sorts itself
+            const uint32_t klo = (uint32_t)pre_x ^ 0x80000000u, khi = (uint32_t)pre_y;
+            const long long ka = (long long)(((unsigned long long)khi << 32) | klo);
+            skey[lane] = (uint32_t)lane < np_next ? ka : 0x7fffffffffffffffll;
+            wave_sync();
+            uint32_t rank = 0;
+            for (uint32_t k0 = 0; k0 < np_next; k0 += 16) {
+                long long kb[16];
+#pragma unroll
+                for (uint32_t q = 0; q < 16; ++q) kb[q] = skey[k0 + q];
+#pragma unroll
+                for (uint32_t q = 0; q < 16; ++q) rank += kb[q] < ka ? 1u : 0u;
+            }
+            if ((uint32_t)lane < np_next) pts2[(t + 1) & 1][rank] = make_double2((double)pre_x, (double)pre_y);
+        }
         if (w0) {
             if (nc <= 2u * TRK_THREADS) {
                 unsigned long long rd[2], rk[2];
