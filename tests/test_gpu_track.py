@@ -96,8 +96,9 @@ def test_dense_frames_and_wide_coordinates(dev):
     through LDS), 144 live tracks (tracks past the first 64 in the
     workspace) and over a thousand gated candidates (association rounds
     reading candidates from LDS), on a jittered grid drifting right and
-    down; then points with negative and 17-bit coordinates (the (y, x) order
-    of the sort as signed integers)."""
+    down; frames above and below 64 points in turn; then points with
+    negative and 17-bit coordinates (the (y, x) order of the sort as signed
+    integers)."""
     rng = np.random.default_rng(11)
     rows = []
     for t in range(10):
@@ -109,6 +110,16 @@ def test_dense_frames_and_wide_coordinates(dev):
     rec, flags = fz.track_points(pts, cnt, 10)
     n = compare(rec, flags, np.array(rows), 10)
     say("dense grid", len(rows), "points", n, "records")
+    # frames above and below 64 points in turn (a frame of at most 64 is sorted
+    # while the one before it is associated, a larger one at its own start)
+    rows = []
+    for t, n in enumerate([30, 100, 20, 70, 64, 65, 10, 90, 64, 1]):
+        cells = rng.choice(16 * 16, size=n, replace=False)
+        rows += [(t, 30 + 5 * int(c // 16) + t, 40 + 5 * int(c % 16) + t // 2) for c in cells]
+    pts, cnt = gpu_points(rows, dev)
+    rec, flags = fz.track_points(pts, cnt, 10)
+    n = compare(rec, flags, np.array(rows), 10)
+    say("mixed frame sizes", len(rows), "points", n, "records")
     rows = [(0, -5, 3), (0, -5, -2), (0, 70000, 1), (0, 2, 70000), (0, -70000, 9),
             (1, -4, 3), (1, 70001, 2), (1, 3, 69999), (1, -69999, 8), (2, -3, 4)]
     pts, cnt = gpu_points(rows, dev)
