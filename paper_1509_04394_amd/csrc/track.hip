@@ -212,7 +212,9 @@ __device__ __forceinline__ void put_record(fz_track* out, uint32_t k, uint32_t c
 // predictions and updates, so each can keep the list's first 64 tracks in its
 // registers from frame to frame (passed through LDS when the list is
 // compacted); tracks past them live in the workspace.  The first wavefront
-// sorts the points, forms the association and writes the list and records.  The
+// forms the association and writes the list and records; the second sorts the
+// next frame's points meanwhile (a frame of up to 64; larger ones are sorted
+// by all four at the frame's start).  The
 // greedy association is formed in rounds: every candidate that is the first
 // (in the (d2, id, point) order) of the remaining candidates of both its track
 // and its point is taken, and candidates of taken tracks and points leave;
