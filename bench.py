@@ -313,7 +313,7 @@ def tracking_leg(points, count, T, stream, reps=3, cpu=True):
     res = {"ms_per_pass": round(ms, 3), "points": n, "records": int(len(rec)), "tracks": int(len(set(rec["id"].tolist()))),
            "flags": flags, "points_per_s": round(n / (ms * 1e-3), 1),
            "note": "Table II's Kalman filter on the chain's feature points, kernel-to-kernel after the chain "
-                   "(bucketing by frame, then one wavefront marching the frames); latency-bound, sequential in t"}
+                   "(bucketing by frame, then one workgroup of four wavefronts marching the frames); latency-bound, sequential in t"}
     if cpu:
         import oracle
         host = points[:n, :3].cpu().numpy()
