@@ -42,6 +42,7 @@ namespace fz {
 constexpr int TRK_THREADS = 64;       // lanes of a wavefront: the tracks of the list it keeps in registers
 constexpr int TRK_WAVES = 4;          // wavefronts that march the frames together
 constexpr int TRK_GROUP = 4;          // points a wavefront tests at a time in the candidate search
+constexpr int TRK_ASSOC_REG = 2;      // candidates per lane the association keeps in registers
 constexpr int TRK_MAX_POINTS = 1024;  // points of one frame
 constexpr int TRK_MAX_CANDS = 2048;   // gated (track, point) pairs of one frame
 
@@ -469,10 +470,10 @@ __global__ __launch_bounds__(TRK_THREADS * TRK_WAVES) __attribute__((amdgpu_wave
         // 3. greedy association in rounds: an open candidate that comes first
         // (in the (d2, id, point) order) among the open candidates of both its
         // track and its point is taken; then every candidate of a taken track
-        // or point closes.  Up to 128 candidates, each lane keeps its two
-        // (lane, lane + 64) in registers, and the first-of slots of a track or
-        // point are cleared when its candidates stay open for another round;
-        // beyond that the candidates are read from LDS in every pass.
+        // or point closes.  Up to 64 * TRK_ASSOC_REG candidates, each lane keeps
+        // its own (lane, lane + 64, ...) in registers, and the first-of slots of
+        // a track or point are cleared when its candidates stay open for another
+        // round; beyond that the candidates are read from LDS in every pass.
         // One wavefront forms the association (its passes are ordered by waits on
         // its own LDS operations, no barrier); the others wait at the next barrier.
         const uint32_t np_next = min(n_hi - n_lo, (uint32_t)TRK_MAX_POINTS);  // the next frame's, as it will count them
@@ -495,12 +496,12 @@ __global__ __launch_bounds__(TRK_THREADS * TRK_WAVES) __attribute__((amdgpu_wave
             if ((uint32_t)lane < np_next) pts2[(t + 1) & 1][rank] = make_double2((double)pre_x, (double)pre_y);
         }
         if (w0) {
-            if (nc <= 2u * TRK_THREADS) {
-                unsigned long long rd[2], rk[2];
-                int rti[2], rpj[2];
-                bool al[2];
+            if (nc <= (uint32_t)(TRK_ASSOC_REG * TRK_THREADS)) {
+                unsigned long long rd[TRK_ASSOC_REG], rk[TRK_ASSOC_REG];
+                int rti[TRK_ASSOC_REG], rpj[TRK_ASSOC_REG];
+                bool al[TRK_ASSOC_REG];
 #pragma unroll
-                for (int q = 0; q < 2; ++q) {
+                for (int q = 0; q < TRK_ASSOC_REG; ++q) {
                     const uint32_t c = (uint32_t)lane + (uint32_t)q * TRK_THREADS;
                     al[q] = c < nc;
                     rd[q] = rk[q] = 0ull;
@@ -521,32 +522,32 @@ __global__ __launch_bounds__(TRK_THREADS * TRK_WAVES) __attribute__((amdgpu_wave
                 for (;;) {
                     wave_sync();
 #pragma unroll
-                    for (int q = 0; q < 2; ++q)
+                    for (int q = 0; q < TRK_ASSOC_REG; ++q)
                         if (al[q]) {
                             atomicMin(&tb_d[rti[q]], rd[q]);
                             atomicMin(&pb_d[rpj[q]], rd[q]);
                         }
                     wave_sync();
-                    unsigned long long td[2], pd[2], tk[2], pk[2];
+                    unsigned long long td[TRK_ASSOC_REG], pd[TRK_ASSOC_REG], tk[TRK_ASSOC_REG], pk[TRK_ASSOC_REG];
 #pragma unroll
-                    for (int q = 0; q < 2; ++q) {
+                    for (int q = 0; q < TRK_ASSOC_REG; ++q) {
                         td[q] = tb_d[rti[q]];
                         pd[q] = pb_d[rpj[q]];
                     }
 #pragma unroll
-                    for (int q = 0; q < 2; ++q)
+                    for (int q = 0; q < TRK_ASSOC_REG; ++q)
                         if (al[q]) {
                             if (rd[q] == td[q]) atomicMin(&tb_k[rti[q]], rk[q]);
                             if (rd[q] == pd[q]) atomicMin(&pb_k[rpj[q]], rk[q]);
                         }
                     wave_sync();
 #pragma unroll
-                    for (int q = 0; q < 2; ++q) {
+                    for (int q = 0; q < TRK_ASSOC_REG; ++q) {
                         tk[q] = tb_k[rti[q]];
                         pk[q] = pb_k[rpj[q]];
                     }
 #pragma unroll
-                    for (int q = 0; q < 2; ++q) {
+                    for (int q = 0; q < TRK_ASSOC_REG; ++q) {
                         const bool take = al[q] & (rd[q] == td[q]) & (rk[q] == tk[q]) & (rd[q] == pd[q]) & (rk[q] == pk[q]);
                         if (take) {
                             tmatch[rti[q]] = (int16_t)rpj[q];
@@ -554,15 +555,15 @@ __global__ __launch_bounds__(TRK_THREADS * TRK_WAVES) __attribute__((amdgpu_wave
                         }
                     }
                     wave_sync();
-                    int tmq[2], ptq[2];
+                    int tmq[TRK_ASSOC_REG], ptq[TRK_ASSOC_REG];
 #pragma unroll
-                    for (int q = 0; q < 2; ++q) {
+                    for (int q = 0; q < TRK_ASSOC_REG; ++q) {
                         tmq[q] = tmatch[rti[q]];
                         ptq[q] = ptaken[rpj[q]];
                     }
                     bool open = false;
 #pragma unroll
-                    for (int q = 0; q < 2; ++q)
+                    for (int q = 0; q < TRK_ASSOC_REG; ++q)
                         if (al[q]) {
                             if (tmq[q] >= 0 || ptq[q]) {
                                 al[q] = false;
@@ -575,15 +576,15 @@ __global__ __launch_bounds__(TRK_THREADS * TRK_WAVES) __attribute__((amdgpu_wave
                     if (!__any(open)) break;
                 }
             } else {
-                for (uint32_t c = lane; c < nc; c += TRK_THREADS) calive[c] = 1;
+                // the same passes over the LDS list (slots cleared before the first
+                // round and, for candidates still open, in the pass that closes the others)
+                for (uint32_t c = lane; c < nc; c += TRK_THREADS) {
+                    calive[c] = 1;
+                    const Cand a = cand[c];
+                    tb_d[a.ti] = tb_k[a.ti] = ~0ull;
+                    pb_d[a.pj] = pb_k[a.pj] = ~0ull;
+                }
                 for (;;) {
-                    wave_sync();
-                    for (uint32_t c = lane; c < nc; c += TRK_THREADS)
-                        if (calive[c]) {
-                            const Cand a = cand[c];
-                            tb_d[a.ti] = tb_k[a.ti] = ~0ull;
-                            pb_d[a.pj] = pb_k[a.pj] = ~0ull;
-                        }
                     wave_sync();
                     for (uint32_t c = lane; c < nc; c += TRK_THREADS)
                         if (calive[c]) {
@@ -597,15 +598,17 @@ __global__ __launch_bounds__(TRK_THREADS * TRK_WAVES) __attribute__((amdgpu_wave
                         if (calive[c]) {
                             const Cand a = cand[c];
                             const unsigned long long d = d2_key(a.d2), k = idpj_key(a);
-                            if (d == tb_d[a.ti]) atomicMin(&tb_k[a.ti], k);
-                            if (d == pb_d[a.pj]) atomicMin(&pb_k[a.pj], k);
+                            const unsigned long long td = tb_d[a.ti], pd = pb_d[a.pj];
+                            if (d == td) atomicMin(&tb_k[a.ti], k);
+                            if (d == pd) atomicMin(&pb_k[a.pj], k);
                         }
                     wave_sync();
                     for (uint32_t c = lane; c < nc; c += TRK_THREADS)
                         if (calive[c]) {
                             const Cand a = cand[c];
                             const unsigned long long d = d2_key(a.d2), k = idpj_key(a);
-                            if (d == tb_d[a.ti] && k == tb_k[a.ti] && d == pb_d[a.pj] && k == pb_k[a.pj]) {
+                            const unsigned long long td = tb_d[a.ti], tk = tb_k[a.ti], pd = pb_d[a.pj], pk = pb_k[a.pj];
+                            if ((d == td) & (k == tk) & (d == pd) & (k == pk)) {
                                 tmatch[a.ti] = a.pj;
                                 ptaken[a.pj] = 1;
                             }
@@ -615,10 +618,14 @@ __global__ __launch_bounds__(TRK_THREADS * TRK_WAVES) __attribute__((amdgpu_wave
                     for (uint32_t c = lane; c < nc; c += TRK_THREADS)
                         if (calive[c]) {
                             const Cand a = cand[c];
-                            if (tmatch[a.ti] >= 0 || ptaken[a.pj])
+                            const int tm = tmatch[a.ti], pt = ptaken[a.pj];
+                            if (tm >= 0 || pt) {
                                 calive[c] = 0;
-                            else
+                            } else {
                                 open = true;
+                                tb_d[a.ti] = tb_k[a.ti] = ~0ull;
+                                pb_d[a.pj] = pb_k[a.pj] = ~0ull;
+                            }
                         }
                     if (!__any(open)) break;
                 }
