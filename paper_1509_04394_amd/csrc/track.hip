@@ -254,7 +254,7 @@ __global__ __launch_bounds__(TRK_THREADS * TRK_WAVES) __attribute__((amdgpu_wave
     __shared__ uint32_t s_flags, s_nc;
     const int lane = threadIdx.x & (TRK_THREADS - 1);
     const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x / TRK_THREADS);
-    const bool w0 = wave == 0;  // the wavefront that sorts, associates and writes
+    const bool w0 = wave == 0;  // the wavefront that associates and writes (and sorts a frame not sorted ahead)
     const KModel M(o.q, o.r);
     DevTrack* cur = buf0;
     DevTrack* nxt = buf1;
