@@ -134,6 +134,12 @@ def test_limits_are_flagged(dev):
     pts, cnt = gpu_points(rows, dev)
     _, flags = fz.track_points(pts, cnt, 1)
     assert flags & fz.FZ_TRACK_TOO_MANY_POINTS
+    # more gated pairs in a frame than the list holds (2048): 60 tracks, each
+    # gating all 60 points of the next frame
+    rows = [(t, 10 + 3 * (k // 8), 10 + 3 * (k % 8)) for t in range(2) for k in range(60)]
+    pts, cnt = gpu_points(rows, dev)
+    _, flags = fz.track_points(pts, cnt, 2, fz.track_opts(gate=1e9))
+    assert flags & fz.FZ_TRACK_TOO_MANY_CANDIDATES
     # more live tracks than allowed
     rows = [(0, 10 * k, 10 * k) for k in range(8)]
     pts, cnt = gpu_points(rows, dev)
