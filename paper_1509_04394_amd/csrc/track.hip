@@ -41,7 +41,7 @@ namespace fz {
 
 constexpr int TRK_THREADS = 64;       // lanes of a wavefront: the tracks of the list it keeps in registers
 constexpr int TRK_WAVES = 4;          // wavefronts that march the frames together
-constexpr int TRK_GROUP = 4;          // points a wavefront tests at a time in the candidate search
+constexpr int TRK_GROUP = 5;          // points a wavefront tests at a time in the candidate search
 constexpr int TRK_ASSOC_REG = 2;      // candidates per lane the association keeps in registers
 constexpr int TRK_MAX_POINTS = 1024;  // points of one frame
 constexpr int TRK_MAX_CANDS = 2048;   // gated (track, point) pairs of one frame
